@@ -1,0 +1,235 @@
+/*
+ * vkmg.h -- Vanka-multigrid preconditioned FGMRES for the structured-grid
+ * Q2-Q1 (Taylor-Hood) Stokes discretisation, on one AMD Instinct MI355X.
+ *
+ * C ABI.  Every vector argument is caller-owned HIP device memory on the
+ * device that was current when the context was created, unless stated
+ * otherwise; the library owns only its workspace (allocated in
+ * vkmg_setup, freed in vkmg_destroy).  No C++ exception and no process
+ * exit crosses this interface: every entry point returns a status code and
+ * leaves a thread-local message behind (vkmg_last_error).  Arguments are
+ * validated before any GPU work is enqueued; on error the outputs are
+ * unspecified and the context stays usable.  A context is not thread-safe.
+ *
+ * Problem (paper, section "Problem setup" and "Discretization"):
+ *   -nu lap u + grad p = f, div u = 0 on the unit square, uniform N x N
+ *   quadrilateral mesh, biquadratic continuous velocity, bilinear continuous
+ *   pressure, Dirichlet velocity data on every edge, pressure defined up to
+ *   a constant.  The linear system is the saddle-point matrix
+ *   A = [[L, B^T], [B, 0]] (equation "stokesmatrix"), with
+ *   b(v, q) = -int q div v, after symmetric elimination of the Dirichlet
+ *   DoFs (identity rows and columns on them).
+ *
+ * Vector layout (every vector, every level): [u_x | u_y | p], where u_x and
+ * u_y hold the (2N+1)^2 Q2 nodal values and p the (N+1)^2 Q1 nodal values,
+ * each block row-major with flat index j*side + i (i along x).  Q2 node
+ * (i,j) sits at (i/(2N), j/(2N)); Q1 node (i,j) at (i/N, j/N).  Dirichlet
+ * DoFs (both velocity components at every boundary Q2 node) are present in
+ * the vector; their rows are identity rows.
+ *
+ * Streams: every entry point that takes `stream` (a hipStream_t, NULL =
+ * the legacy default stream) enqueues all its GPU work on it.
+ * vkmg_residual, vkmg_apply, vkmg_vanka_sweep, vkmg_restrict,
+ * vkmg_prolong_add, vkmg_coarse_solve, vkmg_vcycle and vkmg_assemble_rhs are
+ * asynchronous; vkmg_fgmres_solve synchronises (one small device-to-host
+ * copy per Arnoldi step) and its vkmg_info is valid on return.
+ */
+#ifndef VKMG_H
+#define VKMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vkmg_ctx vkmg_ctx; /* opaque, library-owned */
+
+typedef enum {
+    VKMG_OK = 0,
+    VKMG_ERR_INVALID_ARG = 1,    /* NULL pointer, bad size, level out of range */
+    VKMG_ERR_UNSUPPORTED = 2,    /* valid request this build does not handle */
+    VKMG_ERR_OUT_OF_MEMORY = 3,  /* device or host allocation failed */
+    VKMG_ERR_HIP = 4,            /* a HIP runtime call failed (message says which) */
+    VKMG_ERR_SINGULAR_PATCH = 5, /* a Vanka patch or the coarse matrix is singular */
+    VKMG_ERR_NOT_CONVERGED = 6,  /* FGMRES hit max_iters above the tolerance */
+    VKMG_ERR_NONFINITE = 7       /* NaN/Inf met in the right-hand side or a residual */
+} vkmg_status;
+
+typedef enum { VKMG_FP64 = 0, VKMG_FP32 = 1 } vkmg_precision;
+
+typedef struct {
+    int32_t nx, ny; /* elements per side on [0,1]^2; nx == ny required */
+} vkmg_grid;
+
+typedef struct {
+    int32_t nu_pre;              /* Vanka sweeps before the coarse correction (default 2) */
+    int32_t nu_post;             /* Vanka sweeps after it (default 2) */
+    double omega;                /* Vanka damping (default 0.5) */
+    vkmg_precision mg_precision; /* arithmetic of the whole V-cycle (default FP64) */
+} vkmg_options;
+
+typedef struct {
+    int64_t n, n_vel, n_pres;    /* total, velocity (both components), pressure DoFs */
+    int64_t off_ux, off_uy, off_p;
+    int32_t q2_side, q1_side;    /* 2N+1 and N+1 */
+    int32_t n_elem;              /* N */
+} vkmg_layout;
+
+typedef struct {
+    int32_t iterations;          /* Arnoldi steps taken (= preconditioner applications) */
+    int32_t restarts;            /* completed restart cycles */
+    double est_rel_res;          /* rotated residual estimate / ||b - A x0|| at exit */
+    double true_rel_res;         /* recomputed ||b - A x|| / ||b - A x0|| at exit */
+    vkmg_status status;          /* VKMG_OK or VKMG_ERR_NOT_CONVERGED / NONFINITE */
+} vkmg_info;
+
+/* Kernel classes that vkmg_kernel_timing reports. */
+typedef enum {
+    VKMG_KERNEL_VANKA = 0,       /* Vanka sweep (gather, patch-inverse apply, scatter) */
+    VKMG_KERNEL_RESIDUAL = 1,    /* stencil residual / operator apply */
+    VKMG_KERNEL_TRANSFER = 2,    /* restriction and prolongation */
+    VKMG_KERNEL_COARSE = 3,      /* coarsest-level dense solve */
+    VKMG_KERNEL_KRYLOV = 4,      /* FGMRES vector kernels */
+    VKMG_KERNEL_COUNT = 5
+} vkmg_kernel_class;
+
+/* {2, 2, 0.5, VKMG_FP64}: V(2,2) cycles of additive Vanka damped by 0.5. */
+vkmg_options vkmg_default_options(void);
+
+/*
+ * Build the multigrid hierarchy for the Stokes operator with constant
+ * viscosity nu on an nx x nx mesh with `levels` levels (paper, Algorithm 1;
+ * level 0 is the coarsest, N_l = N / 2^(levels-1-l)).  Rediscretises the
+ * operator on every level, assembles and inverts (partial-pivot LU, FP64)
+ * the 25 distinct Vanka patch matrices of every relaxed level (paper,
+ * subsection "Vanka patch matrices": 25 patch matrices on a uniform mesh,
+ * independent of N), and the bordered coarsest-level matrix.  Allocates the
+ * device workspace on the current HIP device; `hip_stream` is used for the
+ * uploads and is synchronised before return.
+ * Requirements: nx == ny; levels >= 2; nx divisible by 2^(levels-1);
+ * coarsest mesh at least 2 x 2; nu > 0 and finite; opts NULL or with
+ * nu_pre, nu_post in [0, 16], 0 < omega <= 2.  Violations give
+ * VKMG_ERR_INVALID_ARG; a singular patch gives VKMG_ERR_SINGULAR_PATCH.
+ */
+vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu,
+                       const vkmg_options* opts, void* hip_stream, vkmg_ctx** out);
+
+/* Destroy a context (NULL-safe).  Waits for the device to finish its work. */
+void vkmg_destroy(vkmg_ctx* ctx);
+
+/* Sizes and offsets of the finest level (level = levels-1) or of `level`. */
+vkmg_status vkmg_layout_of(const vkmg_ctx* ctx, vkmg_layout* out);
+vkmg_status vkmg_level_layout(const vkmg_ctx* ctx, int32_t level, vkmg_layout* out);
+vkmg_status vkmg_num_levels(const vkmg_ctx* ctx, int32_t* out);
+
+/*
+ * r = b - A x on the finest level, FP64 (the residual of Algorithm 1 and of
+ * FGMRES).  b, x, r: n doubles each; r must not alias x.  A is applied
+ * matrix-free: Dirichlet entries of x are treated as zero columns and the
+ * Dirichlet rows return b - x.
+ */
+vkmg_status vkmg_residual(vkmg_ctx* ctx, const double* b, const double* x, double* r, void* stream);
+
+/* y = A x on the finest level, FP64 (same conventions). */
+vkmg_status vkmg_apply(vkmg_ctx* ctx, const double* x, double* y, void* stream);
+
+/*
+ * Right-hand side of the constrained system on the finest level:
+ *   b_F = (M f)_F - A_FD g,  b_D = g_D,  b_p = -B_pD g
+ * where M is the Q2 mass matrix (so M f is the load of the body force whose
+ * Q2 interpolant has nodal values f) and g holds the Dirichlet data.
+ * f, g: 2*(2N+1)^2 doubles each ([f_x | f_y], only the boundary entries of
+ * g are read; g may be NULL for homogeneous data); b: n doubles, FP64.
+ */
+vkmg_status vkmg_assemble_rhs(vkmg_ctx* ctx, const double* f, const double* g, double* b,
+                              void* stream);
+
+/*
+ * One additive Vanka sweep on `level` (1 <= level <= levels-1), in the
+ * context's multigrid precision (x, b are double for VKMG_FP64 contexts and
+ * float for VKMG_FP32 contexts): r = b - A_l x, then
+ * x += sum_i V_i^T W_i A_i^{-1} V_i r over all patches i (paper, equation
+ * "vksystem" and Algorithm 3), W_i = omega diag(1/m_j) with m_j the number
+ * of patches containing DoF j and zero weight on Dirichlet DoFs.  x is
+ * updated in place; b is read-only and must not alias x.
+ */
+vkmg_status vkmg_vanka_sweep(vkmg_ctx* ctx, int32_t level, void* x, const void* b, void* stream);
+
+/*
+ * Grid transfers of Algorithm 1 in the multigrid precision:
+ *   vkmg_restrict:   b_coarse = P^T r_fine   (fine = level, coarse = level-1)
+ *   vkmg_prolong_add: x_fine += P e_coarse
+ * P is the finite-element interpolation from the level-1 Q2/Q1 spaces to
+ * the level ones, with rows of fine Dirichlet DoFs and columns of coarse
+ * Dirichlet DoFs zeroed.  1 <= level <= levels-1.
+ */
+vkmg_status vkmg_restrict(vkmg_ctx* ctx, int32_t level, const void* r_fine, void* b_coarse,
+                          void* stream);
+vkmg_status vkmg_prolong_add(vkmg_ctx* ctx, int32_t level, const void* e_coarse, void* x_fine,
+                             void* stream);
+
+/*
+ * Exact coarsest-level solve e = A_0^+ r (Algorithm 1, level 0), through the
+ * precomputed inverse of the matrix bordered by the constant-pressure
+ * vector, computed in FP64; r and e in the multigrid precision, n_0 values.
+ */
+vkmg_status vkmg_coarse_solve(vkmg_ctx* ctx, const void* r, void* e, void* stream);
+
+/*
+ * One multigrid V(nu_pre, nu_post) cycle with zero initial guess on every
+ * level (Algorithm 1): z = M r.  r, z: n doubles on the finest level (the
+ * V-cycle itself runs in the context's multigrid precision; FP32 contexts
+ * round r to float on entry and widen z on exit).  z must not alias r.
+ */
+vkmg_status vkmg_vcycle(vkmg_ctx* ctx, const double* r, double* z, void* stream);
+
+/*
+ * Solve A x = b by restarted flexible GMRES right-preconditioned with
+ * vkmg_vcycle (paper, section "Overall solver performance"), in FP64.
+ * x holds the initial guess on entry (use the Dirichlet lifting: g on D,
+ * zero elsewhere) and the solution on exit.  Stops when the rotated
+ * residual estimate and then the recomputed residual satisfy
+ * ||b - A x|| <= rtol ||b - A x0||; restarts every `restart` steps
+ * (1..256); at most max_iters Arnoldi steps (>= 1).  Returns VKMG_OK,
+ * VKMG_ERR_NOT_CONVERGED (x is the last iterate) or VKMG_ERR_NONFINITE;
+ * `info` (may be NULL) is filled in every case.
+ */
+vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double rtol,
+                              int32_t restart, int32_t max_iters, vkmg_info* info, void* stream);
+
+/*
+ * Per-kernel device timing.  While enabled, the library brackets every
+ * launch of the classes in vkmg_kernel_class with HIP events on the launch
+ * stream; vkmg_kernel_timing returns the number of launches recorded and
+ * the summed event-measured duration in milliseconds (it synchronises the
+ * recorded events).  vkmg_set_timing(ctx, 1) clears previous records.
+ */
+vkmg_status vkmg_set_timing(vkmg_ctx* ctx, int32_t enable);
+vkmg_status vkmg_kernel_timing(vkmg_ctx* ctx, int32_t kernel_class, int64_t* launches,
+                               double* total_ms);
+
+/*
+ * Host-only (no GPU needed): the Vanka patch matrix A_i = V_i A V_i^T of
+ * patch class `cls` (0..24, cls = 5*class_y + class_x, class 0 = on the low
+ * boundary, 1 = one element in, 2 = interior, 3 = one element from the high
+ * boundary, 4 = on the high boundary) on an N x N mesh (N >= 4) with
+ * viscosity nu, in the 51-slot patch numbering: u_x at the 5x5 Q2 nodes
+ * (2I-2+a, 2J-2+b) in slot 5b+a, u_y in slot 25+5b+a, the pressure in slot
+ * 50.  Absent slots (outside the domain) get an identity row and column and
+ * present[s] = 0.  Outputs (caller-owned host memory): A (51*51, row-major),
+ * Ainv (51*51, its inverse), Wainv (51*51, the weighted inverse
+ * W A^{-1} with omega = `omega`, zero rows on Dirichlet and absent slots),
+ * present (51).  Any output may be NULL.
+ */
+vkmg_status vkmg_host_patch_matrix(int32_t N, double nu, double omega, int32_t cls, double* A,
+                                   double* Ainv, double* Wainv, uint8_t* present);
+
+const char* vkmg_status_string(vkmg_status s);
+const char* vkmg_last_error(void); /* thread-local; "" if none */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VKMG_H */

@@ -1,0 +1,308 @@
+"""Thin ctypes binding of the vkmg C ABI (include/vkmg.h).
+
+Argument marshalling only: every numerical step runs in the HIP library
+``libvkmg.so`` built in this directory.  PyTorch supplies device memory
+(``tensor.data_ptr()``) and the current HIP stream.  There is no fallback:
+if the library is missing, loading raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int32, c_int64, c_uint8, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvkmg.so")
+
+FP64, FP32 = 0, 1
+KERNEL_VANKA, KERNEL_RESIDUAL, KERNEL_TRANSFER, KERNEL_COARSE, KERNEL_KRYLOV = range(5)
+
+STATUS = {
+    0: "VKMG_OK",
+    1: "VKMG_ERR_INVALID_ARG",
+    2: "VKMG_ERR_UNSUPPORTED",
+    3: "VKMG_ERR_OUT_OF_MEMORY",
+    4: "VKMG_ERR_HIP",
+    5: "VKMG_ERR_SINGULAR_PATCH",
+    6: "VKMG_ERR_NOT_CONVERGED",
+    7: "VKMG_ERR_NONFINITE",
+}
+
+EXPORTED = [
+    "vkmg_default_options", "vkmg_setup", "vkmg_destroy", "vkmg_layout_of", "vkmg_level_layout",
+    "vkmg_num_levels", "vkmg_residual", "vkmg_apply", "vkmg_assemble_rhs", "vkmg_vanka_sweep",
+    "vkmg_restrict", "vkmg_prolong_add", "vkmg_coarse_solve", "vkmg_vcycle",
+    "vkmg_fgmres_solve", "vkmg_set_timing", "vkmg_kernel_timing", "vkmg_host_patch_matrix",
+    "vkmg_status_string", "vkmg_last_error",
+]
+
+
+class VkmgError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        self.status = status
+        self.status_name = STATUS.get(status, str(status))
+        super().__init__(f"{where}: {self.status_name}: {message}")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("nu_pre", c_int32), ("nu_post", c_int32), ("omega", c_double),
+                ("mg_precision", c_int32)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("n_vel", c_int64), ("n_pres", c_int64), ("off_ux", c_int64),
+                ("off_uy", c_int64), ("off_p", c_int64), ("q2_side", c_int32),
+                ("q1_side", c_int32), ("n_elem", c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", c_int32), ("restarts", c_int32), ("est_rel_res", c_double),
+                ("true_rel_res", c_double), ("status", c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["status_name"] = STATUS.get(self.status, str(self.status))
+        return d
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libvkmg.so and declare its signatures (raises if missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run: python -m paper_2401_06277_amd.build)")
+    lib = ctypes.CDLL(path)
+    P = c_void_p
+    sig = {
+        "vkmg_default_options": (Options, []),
+        "vkmg_setup": (c_int32, [POINTER(Grid), c_int32, c_double, POINTER(Options), P, POINTER(P)]),
+        "vkmg_destroy": (None, [P]),
+        "vkmg_layout_of": (c_int32, [P, POINTER(Layout)]),
+        "vkmg_level_layout": (c_int32, [P, c_int32, POINTER(Layout)]),
+        "vkmg_num_levels": (c_int32, [P, POINTER(c_int32)]),
+        "vkmg_residual": (c_int32, [P, P, P, P, P]),
+        "vkmg_apply": (c_int32, [P, P, P, P]),
+        "vkmg_assemble_rhs": (c_int32, [P, P, P, P, P]),
+        "vkmg_vanka_sweep": (c_int32, [P, c_int32, P, P, P]),
+        "vkmg_restrict": (c_int32, [P, c_int32, P, P, P]),
+        "vkmg_prolong_add": (c_int32, [P, c_int32, P, P, P]),
+        "vkmg_coarse_solve": (c_int32, [P, P, P, P]),
+        "vkmg_vcycle": (c_int32, [P, P, P, P]),
+        "vkmg_fgmres_solve": (c_int32, [P, P, P, c_double, c_int32, c_int32, POINTER(Info), P]),
+        "vkmg_set_timing": (c_int32, [P, c_int32]),
+        "vkmg_kernel_timing": (c_int32, [P, c_int32, POINTER(c_int64), POINTER(c_double)]),
+        "vkmg_host_patch_matrix": (c_int32, [c_int32, c_double, c_double, c_int32, P, P, P, P]),
+        "vkmg_status_string": (c_char_p, [c_int32]),
+        "vkmg_last_error": (c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        msg = _lib.vkmg_last_error().decode(errors="replace")
+        raise VkmgError(status, where, msg)
+
+
+def host_patch_matrix(N: int, nu: float, omega: float, cls: int):
+    """Patch matrix, inverse and weighted inverse of patch class ``cls`` (host
+    only, no GPU).  Returns (A, Ainv, Wainv, present) as numpy arrays."""
+    lib = load_library()
+    A = np.zeros((51, 51))
+    Ai = np.zeros((51, 51))
+    W = np.zeros((51, 51))
+    pres = np.zeros(51, dtype=np.uint8)
+    st = lib.vkmg_host_patch_matrix(N, nu, omega, cls, A.ctypes.data, Ai.ctypes.data,
+                                    W.ctypes.data, pres.ctypes.data)
+    _check(st, "vkmg_host_patch_matrix")
+    return A, Ai, W, pres.astype(bool)
+
+
+def default_options():
+    return load_library().vkmg_default_options()
+
+
+class VkmgSolver:
+    """One vkmg context: the multigrid hierarchy of an N x N Q2-Q1 Stokes
+    problem on the current HIP device."""
+
+    def __init__(self, N: int, levels: int, nu: float = 1.0, nu_pre: int = 2, nu_post: int = 2,
+                 omega: float = 0.5, precision: str = "fp64"):
+        import torch
+        lib = load_library()
+        self._torch = torch
+        self.precision = precision
+        opts = Options(nu_pre, nu_post, omega, FP32 if precision == "fp32" else FP64)
+        ctx = c_void_p()
+        st = lib.vkmg_setup(byref(Grid(N, N)), levels, nu, byref(opts), self._stream(),
+                            byref(ctx))
+        _check(st, "vkmg_setup")
+        self._ctx = ctx
+        self.N, self.levels, self.nu = N, levels, nu
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.mg_dtype = torch.float32 if precision == "fp32" else torch.float64
+
+    # ---------------------------------------------------------------- plumbing
+    def _stream(self):
+        import torch
+        return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def _ptr(self, t, dtype, n=None, name="tensor"):
+        if not t.is_cuda or t.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if n is not None and t.numel() != n:
+            raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+        return c_void_p(t.data_ptr())
+
+    def _empty(self, n, dtype):
+        return self._torch.empty(n, dtype=dtype, device=self.device)
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            _lib.vkmg_destroy(self._ctx)
+            self._ctx = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---------------------------------------------------------------- queries
+    @property
+    def layout(self):
+        lay = Layout()
+        _check(_lib.vkmg_layout_of(self._ctx, byref(lay)), "vkmg_layout_of")
+        return lay.as_dict()
+
+    def level_layout(self, level: int):
+        lay = Layout()
+        _check(_lib.vkmg_level_layout(self._ctx, level, byref(lay)), "vkmg_level_layout")
+        return lay.as_dict()
+
+    @property
+    def num_levels(self):
+        v = c_int32()
+        _check(_lib.vkmg_num_levels(self._ctx, byref(v)), "vkmg_num_levels")
+        return v.value
+
+    # ---------------------------------------------------------------- operations
+    def residual(self, b, x, r=None):
+        n = self.layout["n"]
+        r = self._empty(n, self._torch.float64) if r is None else r
+        st = _lib.vkmg_residual(self._ctx, self._ptr(b, self._torch.float64, n, "b"),
+                                self._ptr(x, self._torch.float64, n, "x"),
+                                self._ptr(r, self._torch.float64, n, "r"), self._stream())
+        _check(st, "vkmg_residual")
+        return r
+
+    def apply(self, x, y=None):
+        n = self.layout["n"]
+        y = self._empty(n, self._torch.float64) if y is None else y
+        st = _lib.vkmg_apply(self._ctx, self._ptr(x, self._torch.float64, n, "x"),
+                             self._ptr(y, self._torch.float64, n, "y"), self._stream())
+        _check(st, "vkmg_apply")
+        return y
+
+    def assemble_rhs(self, f, g=None, b=None):
+        lay = self.layout
+        b = self._empty(lay["n"], self._torch.float64) if b is None else b
+        gp = c_void_p(None) if g is None else self._ptr(g, self._torch.float64, lay["n_vel"], "g")
+        st = _lib.vkmg_assemble_rhs(self._ctx, self._ptr(f, self._torch.float64, lay["n_vel"], "f"),
+                                    gp, self._ptr(b, self._torch.float64, lay["n"], "b"),
+                                    self._stream())
+        _check(st, "vkmg_assemble_rhs")
+        return b
+
+    def vanka_sweep(self, level: int, x, b):
+        n = self.level_layout(level)["n"]
+        st = _lib.vkmg_vanka_sweep(self._ctx, level, self._ptr(x, self.mg_dtype, n, "x"),
+                                   self._ptr(b, self.mg_dtype, n, "b"), self._stream())
+        _check(st, "vkmg_vanka_sweep")
+        return x
+
+    def restrict(self, level: int, r_fine, b_coarse=None):
+        nf = self.level_layout(level)["n"]
+        nc = self.level_layout(level - 1)["n"]
+        b_coarse = self._empty(nc, self.mg_dtype) if b_coarse is None else b_coarse
+        st = _lib.vkmg_restrict(self._ctx, level, self._ptr(r_fine, self.mg_dtype, nf, "r_fine"),
+                                self._ptr(b_coarse, self.mg_dtype, nc, "b_coarse"), self._stream())
+        _check(st, "vkmg_restrict")
+        return b_coarse
+
+    def prolong_add(self, level: int, e_coarse, x_fine):
+        nf = self.level_layout(level)["n"]
+        nc = self.level_layout(level - 1)["n"]
+        st = _lib.vkmg_prolong_add(self._ctx, level, self._ptr(e_coarse, self.mg_dtype, nc, "e_coarse"),
+                                   self._ptr(x_fine, self.mg_dtype, nf, "x_fine"), self._stream())
+        _check(st, "vkmg_prolong_add")
+        return x_fine
+
+    def coarse_solve(self, r, e=None):
+        n0 = self.level_layout(0)["n"]
+        e = self._empty(n0, self.mg_dtype) if e is None else e
+        st = _lib.vkmg_coarse_solve(self._ctx, self._ptr(r, self.mg_dtype, n0, "r"),
+                                    self._ptr(e, self.mg_dtype, n0, "e"), self._stream())
+        _check(st, "vkmg_coarse_solve")
+        return e
+
+    def vcycle(self, r, z=None):
+        n = self.layout["n"]
+        z = self._empty(n, self._torch.float64) if z is None else z
+        st = _lib.vkmg_vcycle(self._ctx, self._ptr(r, self._torch.float64, n, "r"),
+                              self._ptr(z, self._torch.float64, n, "z"), self._stream())
+        _check(st, "vkmg_vcycle")
+        return z
+
+    def fgmres_solve(self, b, x, rtol: float = 1e-8, restart: int = 30, max_iters: int = 500,
+                     raise_on_error: bool = False):
+        """Solve in place (x: initial guess in, solution out).  Returns the
+        info dict; NOT_CONVERGED and NONFINITE are reported in it (and raised
+        when ``raise_on_error``)."""
+        n = self.layout["n"]
+        info = Info()
+        st = _lib.vkmg_fgmres_solve(self._ctx, self._ptr(b, self._torch.float64, n, "b"),
+                                    self._ptr(x, self._torch.float64, n, "x"), rtol, restart,
+                                    max_iters, byref(info), self._stream())
+        if st not in (0, 6, 7) or (raise_on_error and st != 0):
+            _check(st, "vkmg_fgmres_solve")
+        return info.as_dict()
+
+    def set_timing(self, class_mask: int):
+        _check(_lib.vkmg_set_timing(self._ctx, class_mask), "vkmg_set_timing")
+
+    def kernel_timing(self, kernel_class: int):
+        n = c_int64()
+        ms = c_double()
+        _check(_lib.vkmg_kernel_timing(self._ctx, kernel_class, byref(n), byref(ms)),
+               "vkmg_kernel_timing")
+        return n.value, ms.value

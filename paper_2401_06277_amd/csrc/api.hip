@@ -1,0 +1,706 @@
+// C-ABI layer of the vkmg library: context, multigrid V-cycle orchestration
+// (paper, Algorithm 1) and restarted flexible GMRES (paper, section "Overall
+// solver performance"; Saad's flexible variant with right preconditioning).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/vkmg.h"
+#include "kernels.h"
+#include "vkmg_internal.h"
+
+using namespace vkmg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+vkmg_status fail(vkmg_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define VKMG_HIP(call)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(e_ == hipErrorOutOfMemory ? VKMG_ERR_OUT_OF_MEMORY : VKMG_ERR_HIP, \
+                        std::string(#call) + ": " + hipGetErrorString(e_));             \
+    } while (0)
+
+struct LevelBuf {
+    Geom g;
+    void* x = nullptr;  // MG precision
+    void* b = nullptr;
+    void* r = nullptr;
+    void* W = nullptr;  // 25 weighted patch inverses, MG precision (relaxed levels)
+};
+
+}  // namespace
+
+struct vkmg_ctx {
+    int device = 0;
+    int L = 0;
+    vkmg_options opt{};
+    std::vector<LevelBuf> lev;
+    double* C = nullptr;  // coarse bordered inverse (n0 x n0), FP64
+    // FP64 work vectors of the finest level
+    double* r64 = nullptr;
+    double* w64 = nullptr;
+    double* part = nullptr;   // dot partials
+    double* hdev = nullptr;   // coefficients (device)
+    double* hhost = nullptr;  // pinned host mirror
+    // FGMRES basis
+    double* V = nullptr;
+    double* Z = nullptr;
+    int basis_cap = 0;
+    // timing
+    int32_t timing_mask = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events[VKMG_KERNEL_COUNT];
+    int64_t launches[VKMG_KERNEL_COUNT] = {0};
+    double total_ms[VKMG_KERNEL_COUNT] = {0};
+    std::vector<void*> allocations;
+
+    size_t esize() const { return opt.mg_precision == VKMG_FP32 ? 4 : 8; }
+    const Geom& top() const { return lev.back().g; }
+};
+
+namespace {
+
+constexpr int kHostScratch = 1024;  // doubles in the pinned host buffer
+
+// Brackets one kernel launch with events when the class is being timed.
+struct Timed {
+    vkmg_ctx* c;
+    int cls;
+    hipStream_t s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    Timed(vkmg_ctx* ctx, int k, hipStream_t st) : c(ctx), cls(k), s(st) {
+        if (c->timing_mask & (1 << cls)) {
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+            (void)hipEventRecord(e0, s);
+        }
+    }
+    ~Timed() {
+        if (e0) {
+            (void)hipEventRecord(e1, s);
+            c->events[cls].emplace_back(e0, e1);
+        }
+    }
+};
+
+vkmg_status alloc(vkmg_ctx* c, void** p, size_t bytes) {
+    VKMG_HIP(hipMalloc(p, bytes < 256 ? 256 : bytes));
+    c->allocations.push_back(*p);
+    return VKMG_OK;
+}
+
+void free_all(vkmg_ctx* c) {
+    for (void* p : c->allocations) (void)hipFree(p);
+    c->allocations.clear();
+    if (c->hhost) (void)hipHostFree(c->hhost);
+    c->hhost = nullptr;
+    for (auto& v : c->events)
+        for (auto& e : v) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+vkmg_layout layout_of_geom(const Geom& g) {
+    vkmg_layout l;
+    l.n = g.n;
+    l.n_vel = 2 * g.nq2;
+    l.n_pres = g.nq1;
+    l.off_ux = 0;
+    l.off_uy = g.nq2;
+    l.off_p = 2 * g.nq2;
+    l.q2_side = g.s2;
+    l.q1_side = g.s1;
+    l.n_elem = g.N;
+    return l;
+}
+
+// ------------------------------------------------------------------ MG steps
+
+template <typename T>
+void sweep_t(vkmg_ctx* c, int l, T* x, const T* b, hipStream_t s) {
+    LevelBuf& L = c->lev[l];
+    T* r = static_cast<T*>(L.r);
+    {
+        Timed t(c, VKMG_KERNEL_RESIDUAL, s);
+        launch_residual<T, T>(L.g, b, x, r, 0, s);
+    }
+    Timed t(c, VKMG_KERNEL_VANKA, s);
+    launch_vanka_update<T>(L.g, r, x, static_cast<const T*>(L.W), s);
+}
+
+// MG(l, b) of Algorithm 1 with zero initial guess, result in x.
+template <typename T>
+void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
+    LevelBuf& L = c->lev[l];
+    LevelBuf& Lc = c->lev[l - 1];
+    T* r = static_cast<T*>(L.r);
+    launch_fill_zero<T>(x, L.g.n, s);
+    for (int i = 0; i < c->opt.nu_pre; ++i) {
+        if (i == 0) {
+            // x = 0, so the residual is b itself
+            Timed t(c, VKMG_KERNEL_VANKA, s);
+            launch_vanka_update<T>(L.g, b, x, static_cast<const T*>(L.W), s);
+        } else {
+            sweep_t<T>(c, l, x, b, s);
+        }
+    }
+    const T* rr = b;
+    if (c->opt.nu_pre > 0) {
+        Timed t(c, VKMG_KERNEL_RESIDUAL, s);
+        launch_residual<T, T>(L.g, b, x, r, 0, s);
+        rr = r;
+    }
+    T* bc = static_cast<T*>(Lc.b);
+    T* xc = static_cast<T*>(Lc.x);
+    {
+        Timed t(c, VKMG_KERNEL_TRANSFER, s);
+        launch_restrict<T>(L.g, Lc.g, rr, bc, s);
+    }
+    if (l - 1 == 0) {
+        Timed t(c, VKMG_KERNEL_COARSE, s);
+        launch_coarse_gemv<T>(Lc.g.n, c->C, bc, xc, s);
+    } else {
+        mg_t<T>(c, l - 1, bc, xc, s);
+    }
+    {
+        Timed t(c, VKMG_KERNEL_TRANSFER, s);
+        launch_prolong_add<T>(L.g, Lc.g, xc, x, s);
+    }
+    for (int i = 0; i < c->opt.nu_post; ++i) sweep_t<T>(c, l, x, b, s);
+}
+
+void vcycle_impl(vkmg_ctx* c, const double* r, double* z, hipStream_t s) {
+    const int top = c->L - 1;
+    if (c->opt.mg_precision == VKMG_FP64) {
+        mg_t<double>(c, top, r, z, s);
+    } else {
+        LevelBuf& L = c->lev[top];
+        launch_cast<double, float>(r, static_cast<float*>(L.b), L.g.n, s);
+        mg_t<float>(c, top, static_cast<const float*>(L.b), static_cast<float*>(L.x), s);
+        launch_cast<float, double>(static_cast<const float*>(L.x), z, L.g.n, s);
+    }
+}
+
+// ---------------------------------------------------------------- Krylov helpers
+
+// Squared norm / dots into hdev[0..k) (device), asynchronous.
+void dots_async(vkmg_ctx* c, const double* V, int64_t ldv, int k, const double* w, double* out,
+                hipStream_t s) {
+    const int64_t n = c->top().n;
+    Timed t(c, VKMG_KERNEL_KRYLOV, s);
+    launch_mdot_partial(V, ldv, k, w, n, c->part, s);
+    launch_reduce_partials(c->part, k, out, s);
+}
+
+vkmg_status norm_sync(vkmg_ctx* c, const double* w, double* out, hipStream_t s) {
+    dots_async(c, w, 0, 1, w, c->hdev, s);
+    VKMG_HIP(hipMemcpyAsync(c->hhost, c->hdev, sizeof(double), hipMemcpyDeviceToHost, s));
+    VKMG_HIP(hipStreamSynchronize(s));
+    *out = std::sqrt(c->hhost[0]);
+    return VKMG_OK;
+}
+
+vkmg_status ensure_basis(vkmg_ctx* c, int m) {
+    if (m <= c->basis_cap) return VKMG_OK;
+    const int64_t n = c->top().n;
+    // release the old basis (kept in the allocation list until destroy otherwise)
+    for (void* p : {static_cast<void*>(c->V), static_cast<void*>(c->Z)}) {
+        if (!p) continue;
+        auto it = std::find(c->allocations.begin(), c->allocations.end(), p);
+        if (it != c->allocations.end()) c->allocations.erase(it);
+        (void)hipFree(p);
+    }
+    c->V = c->Z = nullptr;
+    c->basis_cap = 0;
+    vkmg_status st = alloc(c, reinterpret_cast<void**>(&c->V), size_t(m + 1) * n * sizeof(double));
+    if (st != VKMG_OK) return st;
+    st = alloc(c, reinterpret_cast<void**>(&c->Z), size_t(m) * n * sizeof(double));
+    if (st != VKMG_OK) return st;
+    c->basis_cap = m;
+    return VKMG_OK;
+}
+
+bool check_level(const vkmg_ctx* c, int32_t level, bool relaxed) {
+    return c && level >= (relaxed ? 1 : 0) && level < c->L;
+}
+
+}  // namespace
+
+// =====================================================================================
+// C ABI
+// =====================================================================================
+
+extern "C" {
+
+vkmg_options vkmg_default_options(void) {
+    vkmg_options o;
+    o.nu_pre = 2;
+    o.nu_post = 2;
+    o.omega = 0.5;
+    o.mg_precision = VKMG_FP64;
+    return o;
+}
+
+const char* vkmg_status_string(vkmg_status s) {
+    switch (s) {
+        case VKMG_OK: return "ok";
+        case VKMG_ERR_INVALID_ARG: return "invalid argument";
+        case VKMG_ERR_UNSUPPORTED: return "unsupported";
+        case VKMG_ERR_OUT_OF_MEMORY: return "out of memory";
+        case VKMG_ERR_HIP: return "HIP runtime error";
+        case VKMG_ERR_SINGULAR_PATCH: return "singular patch or coarse matrix";
+        case VKMG_ERR_NOT_CONVERGED: return "not converged";
+        case VKMG_ERR_NONFINITE: return "non-finite value";
+    }
+    return "unknown status";
+}
+
+const char* vkmg_last_error(void) { return g_last_error.c_str(); }
+
+vkmg_status vkmg_host_patch_matrix(int32_t N, double nu, double omega, int32_t cls, double* A,
+                                   double* Ainv, double* Wainv, uint8_t* present) {
+    if (N < 4 || cls < 0 || cls >= kClasses)
+        return fail(VKMG_ERR_INVALID_ARG, "host_patch_matrix: need N >= 4 and 0 <= cls < 25");
+    if (!(nu > 0.0) || !std::isfinite(nu))
+        return fail(VKMG_ERR_INVALID_ARG, "host_patch_matrix: nu must be positive and finite");
+    std::vector<double> Ak(kSlots * kSlots), inv;
+    uint8_t pres[kSlots];
+    patch_matrix(N, nu, cls, Ak.data(), pres);
+    if (A) std::memcpy(A, Ak.data(), sizeof(double) * kSlots * kSlots);
+    if (present) std::memcpy(present, pres, kSlots);
+    std::vector<double> work = Ak;
+    if (!invert_dense(kSlots, work, inv))
+        return fail(VKMG_ERR_SINGULAR_PATCH, "host_patch_matrix: singular patch matrix");
+    if (Ainv) std::memcpy(Ainv, inv.data(), sizeof(double) * kSlots * kSlots);
+    if (Wainv) weighted_inverse(N, cls, omega, inv.data(), pres, Wainv);
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const vkmg_options* opts,
+                       void* hip_stream, vkmg_ctx** out) {
+    if (!grid || !out) return fail(VKMG_ERR_INVALID_ARG, "setup: NULL grid or out");
+    *out = nullptr;
+    if (grid->nx != grid->ny) return fail(VKMG_ERR_INVALID_ARG, "setup: nx must equal ny");
+    const int N = grid->nx;
+    if (levels < 2 || levels > 20) return fail(VKMG_ERR_INVALID_ARG, "setup: levels must be in [2, 20]");
+    if (N < 1 || N > (1 << 15)) return fail(VKMG_ERR_INVALID_ARG, "setup: bad nx");
+    if (N % (1 << (levels - 1)) != 0)
+        return fail(VKMG_ERR_INVALID_ARG, "setup: nx must be divisible by 2^(levels-1)");
+    const int N0 = N >> (levels - 1);
+    if (N0 < 2) return fail(VKMG_ERR_INVALID_ARG, "setup: coarsest mesh must be at least 2x2");
+    if (N0 > 16)
+        return fail(VKMG_ERR_UNSUPPORTED,
+                    "setup: coarsest mesh above 16x16 (dense coarse solve); add levels");
+    if (!(nu > 0.0) || !std::isfinite(nu))
+        return fail(VKMG_ERR_INVALID_ARG, "setup: nu must be positive and finite");
+    vkmg_options o = opts ? *opts : vkmg_default_options();
+    if (o.nu_pre < 0 || o.nu_pre > 16 || o.nu_post < 0 || o.nu_post > 16)
+        return fail(VKMG_ERR_INVALID_ARG, "setup: nu_pre/nu_post must be in [0, 16]");
+    if (!(o.omega > 0.0 && o.omega <= 2.0))
+        return fail(VKMG_ERR_INVALID_ARG, "setup: omega must be in (0, 2]");
+    if (o.mg_precision != VKMG_FP64 && o.mg_precision != VKMG_FP32)
+        return fail(VKMG_ERR_INVALID_ARG, "setup: bad mg_precision");
+
+    // host work first (no GPU needed to detect singular patches)
+    std::vector<std::vector<double>> Wh(levels);
+    for (int l = 1; l < levels; ++l) {
+        const int Nl = N >> (levels - 1 - l);
+        Wh[l].resize(size_t(kClasses) * kSlots * kSlots);
+        for (int c = 0; c < kClasses; ++c) {
+            std::vector<double> Ak(kSlots * kSlots), inv;
+            uint8_t pres[kSlots];
+            patch_matrix(Nl, nu, c, Ak.data(), pres);
+            if (!invert_dense(kSlots, Ak, inv))
+                return fail(VKMG_ERR_SINGULAR_PATCH, "setup: singular Vanka patch matrix");
+            weighted_inverse(Nl, c, o.omega, inv.data(), pres, &Wh[l][size_t(c) * kSlots * kSlots]);
+        }
+    }
+    std::vector<double> Ch;
+    if (!coarse_bordered_inverse(N0, nu, Ch))
+        return fail(VKMG_ERR_SINGULAR_PATCH, "setup: singular coarse matrix");
+
+    std::unique_ptr<vkmg_ctx> c(new vkmg_ctx);
+    c->L = levels;
+    c->opt = o;
+    VKMG_HIP(hipGetDevice(&c->device));
+    hipStream_t s = as_stream(hip_stream);
+    c->lev.resize(levels);
+    vkmg_status st = VKMG_OK;
+    const size_t es = c->esize();
+    for (int l = 0; l < levels && st == VKMG_OK; ++l) {
+        LevelBuf& L = c->lev[l];
+        L.g = make_geom(N >> (levels - 1 - l), nu);
+        st = alloc(c.get(), &L.x, es * L.g.n);
+        if (st == VKMG_OK) st = alloc(c.get(), &L.b, es * L.g.n);
+        if (st == VKMG_OK) st = alloc(c.get(), &L.r, es * L.g.n);
+        if (st == VKMG_OK && l >= 1) {
+            const size_t nw = size_t(kClasses) * kSlots * kSlots;
+            st = alloc(c.get(), &L.W, es * nw);
+            if (st == VKMG_OK) {
+                if (o.mg_precision == VKMG_FP64) {
+                    hipError_t e = hipMemcpyAsync(L.W, Wh[l].data(), 8 * nw, hipMemcpyHostToDevice, s);
+                    if (e != hipSuccess) st = fail(VKMG_ERR_HIP, "setup: upload of patch inverses");
+                } else {
+                    std::vector<float> wf(Wh[l].begin(), Wh[l].end());
+                    hipError_t e = hipMemcpyAsync(L.W, wf.data(), 4 * nw, hipMemcpyHostToDevice, s);
+                    if (e == hipSuccess) e = hipStreamSynchronize(s);
+                    if (e != hipSuccess) st = fail(VKMG_ERR_HIP, "setup: upload of patch inverses");
+                }
+            }
+        }
+    }
+    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->C), Ch.size() * 8);
+    if (st == VKMG_OK) {
+        hipError_t e = hipMemcpyAsync(c->C, Ch.data(), Ch.size() * 8, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) st = fail(VKMG_ERR_HIP, "setup: upload of coarse inverse");
+    }
+    const int64_t n = c->top().n;
+    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->r64), 8 * n);
+    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->w64), 8 * n);
+    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->part), 8 * size_t(kDotBlocks) * 260);
+    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->hdev), 8 * kHostScratch);
+    if (st == VKMG_OK) {
+        hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->hhost), 8 * kHostScratch, hipHostMallocDefault);
+        if (e != hipSuccess) st = fail(VKMG_ERR_OUT_OF_MEMORY, "setup: pinned host buffer");
+    }
+    if (st == VKMG_OK) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(VKMG_ERR_HIP, std::string("setup: ") + hipGetErrorString(e));
+    }
+    if (st != VKMG_OK) {
+        free_all(c.get());
+        return st;
+    }
+    *out = c.release();
+    return VKMG_OK;
+}
+
+void vkmg_destroy(vkmg_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    free_all(ctx);
+    delete ctx;
+}
+
+vkmg_status vkmg_num_levels(const vkmg_ctx* ctx, int32_t* out) {
+    if (!ctx || !out) return fail(VKMG_ERR_INVALID_ARG, "num_levels: NULL argument");
+    *out = ctx->L;
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_layout_of(const vkmg_ctx* ctx, vkmg_layout* out) {
+    if (!ctx || !out) return fail(VKMG_ERR_INVALID_ARG, "layout_of: NULL argument");
+    *out = layout_of_geom(ctx->top());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_level_layout(const vkmg_ctx* ctx, int32_t level, vkmg_layout* out) {
+    if (!out || !check_level(ctx, level, false))
+        return fail(VKMG_ERR_INVALID_ARG, "level_layout: NULL argument or level out of range");
+    *out = layout_of_geom(ctx->lev[level].g);
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_residual(vkmg_ctx* ctx, const double* b, const double* x, double* r, void* stream) {
+    if (!ctx || !b || !x || !r) return fail(VKMG_ERR_INVALID_ARG, "residual: NULL argument");
+    if (r == x) return fail(VKMG_ERR_INVALID_ARG, "residual: r must not alias x");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
+    launch_residual<double, double>(ctx->top(), b, x, r, 0, s);
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_apply(vkmg_ctx* ctx, const double* x, double* y, void* stream) {
+    if (!ctx || !x || !y) return fail(VKMG_ERR_INVALID_ARG, "apply: NULL argument");
+    if (x == y) return fail(VKMG_ERR_INVALID_ARG, "apply: y must not alias x");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
+    launch_residual<double, double>(ctx->top(), nullptr, x, y, 1, s);
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_assemble_rhs(vkmg_ctx* ctx, const double* f, const double* g, double* b,
+                              void* stream) {
+    if (!ctx || !f || !b) return fail(VKMG_ERR_INVALID_ARG, "assemble_rhs: NULL f or b");
+    if (b == f || b == g) return fail(VKMG_ERR_INVALID_ARG, "assemble_rhs: b must not alias f or g");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    launch_rhs(ctx->top(), f, g, b, as_stream(stream));
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_vanka_sweep(vkmg_ctx* ctx, int32_t level, void* x, const void* b, void* stream) {
+    if (!x || !b || !check_level(ctx, level, true))
+        return fail(VKMG_ERR_INVALID_ARG, "vanka_sweep: NULL argument or level not in [1, levels)");
+    if (x == b) return fail(VKMG_ERR_INVALID_ARG, "vanka_sweep: b must not alias x");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    if (ctx->opt.mg_precision == VKMG_FP64)
+        sweep_t<double>(ctx, level, static_cast<double*>(x), static_cast<const double*>(b), s);
+    else
+        sweep_t<float>(ctx, level, static_cast<float*>(x), static_cast<const float*>(b), s);
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_restrict(vkmg_ctx* ctx, int32_t level, const void* r_fine, void* b_coarse,
+                          void* stream) {
+    if (!r_fine || !b_coarse || !check_level(ctx, level, true))
+        return fail(VKMG_ERR_INVALID_ARG, "restrict: NULL argument or level not in [1, levels)");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    const Geom& gf = ctx->lev[level].g;
+    const Geom& gc = ctx->lev[level - 1].g;
+    Timed t(ctx, VKMG_KERNEL_TRANSFER, s);
+    if (ctx->opt.mg_precision == VKMG_FP64)
+        launch_restrict<double>(gf, gc, static_cast<const double*>(r_fine), static_cast<double*>(b_coarse), s);
+    else
+        launch_restrict<float>(gf, gc, static_cast<const float*>(r_fine), static_cast<float*>(b_coarse), s);
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_prolong_add(vkmg_ctx* ctx, int32_t level, const void* e_coarse, void* x_fine,
+                             void* stream) {
+    if (!e_coarse || !x_fine || !check_level(ctx, level, true))
+        return fail(VKMG_ERR_INVALID_ARG, "prolong_add: NULL argument or level not in [1, levels)");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    const Geom& gf = ctx->lev[level].g;
+    const Geom& gc = ctx->lev[level - 1].g;
+    Timed t(ctx, VKMG_KERNEL_TRANSFER, s);
+    if (ctx->opt.mg_precision == VKMG_FP64)
+        launch_prolong_add<double>(gf, gc, static_cast<const double*>(e_coarse), static_cast<double*>(x_fine), s);
+    else
+        launch_prolong_add<float>(gf, gc, static_cast<const float*>(e_coarse), static_cast<float*>(x_fine), s);
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_coarse_solve(vkmg_ctx* ctx, const void* r, void* e, void* stream) {
+    if (!ctx || !r || !e) return fail(VKMG_ERR_INVALID_ARG, "coarse_solve: NULL argument");
+    if (r == e) return fail(VKMG_ERR_INVALID_ARG, "coarse_solve: e must not alias r");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    Timed t(ctx, VKMG_KERNEL_COARSE, s);
+    if (ctx->opt.mg_precision == VKMG_FP64)
+        launch_coarse_gemv<double>(ctx->lev[0].g.n, ctx->C, static_cast<const double*>(r), static_cast<double*>(e), s);
+    else
+        launch_coarse_gemv<float>(ctx->lev[0].g.n, ctx->C, static_cast<const float*>(r), static_cast<float*>(e), s);
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_vcycle(vkmg_ctx* ctx, const double* r, double* z, void* stream) {
+    if (!ctx || !r || !z) return fail(VKMG_ERR_INVALID_ARG, "vcycle: NULL argument");
+    if (r == z) return fail(VKMG_ERR_INVALID_ARG, "vcycle: z must not alias r");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    vcycle_impl(ctx, r, z, as_stream(stream));
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double rtol,
+                              int32_t restart, int32_t max_iters, vkmg_info* info, void* stream) {
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->status = VKMG_ERR_INVALID_ARG;
+    }
+    if (!ctx || !b || !x) return fail(VKMG_ERR_INVALID_ARG, "fgmres_solve: NULL argument");
+    if (b == x) return fail(VKMG_ERR_INVALID_ARG, "fgmres_solve: x must not alias b");
+    if (restart < 1 || restart > 256) return fail(VKMG_ERR_INVALID_ARG, "fgmres_solve: restart must be in [1, 256]");
+    if (max_iters < 1) return fail(VKMG_ERR_INVALID_ARG, "fgmres_solve: max_iters must be >= 1");
+    if (!(rtol >= 0.0) || !std::isfinite(rtol)) return fail(VKMG_ERR_INVALID_ARG, "fgmres_solve: bad rtol");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    vkmg_status st = ensure_basis(ctx, restart);
+    if (st != VKMG_OK) return st;
+    const Geom& g = ctx->top();
+    const int64_t n = g.n;
+    const int64_t ld = n;
+    const int m = restart;
+    double* r = ctx->r64;
+    double* w = ctx->w64;
+    double* V = ctx->V;
+    double* Z = ctx->Z;
+
+    auto residual = [&](void) {
+        Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
+        launch_residual<double, double>(g, b, x, r, 0, s);
+    };
+    residual();
+    double beta0 = 0.0;
+    st = norm_sync(ctx, r, &beta0, s);
+    if (st != VKMG_OK) return st;
+    auto finish = [&](vkmg_status status, int it, int rs, double est, double tru) {
+        if (info) {
+            info->iterations = it;
+            info->restarts = rs;
+            info->est_rel_res = est;
+            info->true_rel_res = tru;
+            info->status = status;
+        }
+        if (status == VKMG_ERR_NOT_CONVERGED)
+            g_last_error = "fgmres_solve: maximum iterations reached above the tolerance";
+        if (status == VKMG_ERR_NONFINITE) g_last_error = "fgmres_solve: non-finite residual";
+        return status;
+    };
+    if (!std::isfinite(beta0)) return finish(VKMG_ERR_NONFINITE, 0, 0, NAN, NAN);
+    if (beta0 == 0.0) return finish(VKMG_OK, 0, 0, 0.0, 0.0);
+    const double target = rtol * beta0;
+    int total = 0, restarts = 0;
+    double beta = beta0;
+    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+    auto Hij = [&](int i, int j) -> double& { return H[size_t(i) * m + j]; };
+    double est = 1.0;
+    double* h1 = ctx->hdev;        // first Gram-Schmidt pass, j+1 values
+    double* h2 = ctx->hdev + 300;  // second pass, j+1 values, then ||w||^2 at [j+1]
+    for (;;) {
+        {
+            Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+            launch_scale(r, 1.0 / beta, V, n, s);
+        }
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double* vj = V + int64_t(j) * ld;
+            double* zj = Z + int64_t(j) * ld;
+            vcycle_impl(ctx, vj, zj, s);
+            {
+                Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
+                launch_residual<double, double>(g, nullptr, zj, w, 1, s);
+            }
+            // classical Gram-Schmidt, twice; the second update also forms ||w||^2
+            dots_async(ctx, V, ld, j + 1, w, h1, s);
+            {
+                Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+                launch_update(V, ld, j + 1, h1, w, n, nullptr, s);
+            }
+            dots_async(ctx, V, ld, j + 1, w, h2, s);
+            {
+                Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+                launch_update(V, ld, j + 1, h2, w, n, ctx->part, s);
+                launch_reduce_partials(ctx->part, 1, h2 + (j + 1), s);
+            }
+            VKMG_HIP(hipMemcpyAsync(ctx->hhost, h1, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+            VKMG_HIP(hipMemcpyAsync(ctx->hhost + 300, h2, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s));
+            VKMG_HIP(hipStreamSynchronize(s));
+            bool finite = true;
+            for (int i = 0; i <= j; ++i) {
+                Hij(i, j) = ctx->hhost[i] + ctx->hhost[300 + i];
+                finite = finite && std::isfinite(Hij(i, j));
+            }
+            Hij(j + 1, j) = std::sqrt(ctx->hhost[300 + j + 1]);
+            if (!finite || !std::isfinite(Hij(j + 1, j)))
+                return finish(VKMG_ERR_NONFINITE, total, restarts, NAN, NAN);
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+                Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+                Hij(i, j) = t;
+            }
+            const double hnext = Hij(j + 1, j);
+            const double denom = std::hypot(Hij(j, j), hnext);
+            cs[j] = Hij(j, j) / denom;
+            sn[j] = hnext / denom;
+            const bool breakdown = hnext == 0.0;
+            if (!breakdown) {
+                Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+                launch_scale(w, 1.0 / hnext, V + int64_t(j + 1) * ld, n, s);
+            }
+            Hij(j, j) = denom;
+            Hij(j + 1, j) = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            ++total;
+            k = j + 1;
+            est = std::fabs(gv[j + 1]) / beta0;
+            if (std::fabs(gv[j + 1]) <= target) break;
+            if (breakdown || total >= max_iters) break;
+        }
+        // y = H^{-1} g (upper triangular)
+        for (int i = k - 1; i >= 0; --i) {
+            double acc = gv[i];
+            for (int l = i + 1; l < k; ++l) acc -= Hij(i, l) * y[l];
+            y[i] = acc / Hij(i, i);
+        }
+        std::memcpy(ctx->hhost + 600, y.data(), sizeof(double) * k);
+        VKMG_HIP(hipMemcpyAsync(ctx->hdev + 600, ctx->hhost + 600, sizeof(double) * k, hipMemcpyHostToDevice, s));
+        {
+            Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+            launch_axpy_multi(Z, ld, k, ctx->hdev + 600, x, n, s);
+        }
+        residual();
+        double rn = 0.0;
+        st = norm_sync(ctx, r, &rn, s);
+        if (st != VKMG_OK) return st;
+        if (!std::isfinite(rn)) return finish(VKMG_ERR_NONFINITE, total, restarts, est, NAN);
+        if (rn <= target) return finish(VKMG_OK, total, restarts, est, rn / beta0);
+        if (total >= max_iters) return finish(VKMG_ERR_NOT_CONVERGED, total, restarts, est, rn / beta0);
+        ++restarts;
+        beta = rn;
+    }
+}
+
+vkmg_status vkmg_set_timing(vkmg_ctx* ctx, int32_t class_mask) {
+    if (!ctx) return fail(VKMG_ERR_INVALID_ARG, "set_timing: NULL context");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    for (int k = 0; k < VKMG_KERNEL_COUNT; ++k) {
+        for (auto& e : ctx->events[k]) {
+            (void)hipEventSynchronize(e.second);
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        ctx->events[k].clear();
+        ctx->launches[k] = 0;
+        ctx->total_ms[k] = 0.0;
+    }
+    ctx->timing_mask = class_mask;
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_kernel_timing(vkmg_ctx* ctx, int32_t kernel_class, int64_t* launches,
+                               double* total_ms) {
+    if (!ctx || kernel_class < 0 || kernel_class >= VKMG_KERNEL_COUNT)
+        return fail(VKMG_ERR_INVALID_ARG, "kernel_timing: bad context or class");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    auto& ev = ctx->events[kernel_class];
+    for (auto& e : ev) {
+        VKMG_HIP(hipEventSynchronize(e.second));
+        float ms = 0.f;
+        VKMG_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+        ctx->total_ms[kernel_class] += ms;
+        ctx->launches[kernel_class] += 1;
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    ev.clear();
+    if (launches) *launches = ctx->launches[kernel_class];
+    if (total_ms) *total_ms = ctx->total_ms[kernel_class];
+    return VKMG_OK;
+}
+
+}  // extern "C"

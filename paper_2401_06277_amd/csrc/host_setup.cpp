@@ -1,0 +1,279 @@
+// Host-side setup of the vkmg library, FP64.
+//
+// * Element matrices of the Q2-Q1 Taylor-Hood pair on a square element of
+//   side h, from the closed-form 1D factors (paper, section "Discretization":
+//   L_ij = a(psi_j, psi_i) with a(u,v) = nu int grad u : grad v, and
+//   B_kj = b(psi_j, phi_k) with b(v,q) = -int q div v):
+//     1D quadratic stiffness  K1 = (1/3h) [[7,-8,1],[-8,16,-8],[1,-8,7]]
+//     1D quadratic mass       M1 = (h/30) [[4,2,-1],[2,16,2],[-1,2,4]]
+//     mixed  G[c][a]  = int phi_c psi_a'  = (1/6) [[-5,4,1],[-1,-4,5]]
+//     mixed  Mq[c][a] = int phi_c psi_a   = (h/6) [[1,2,0],[0,2,1]]
+//   with L_e = nu (M1 (x) K1 + K1 (x) M1), Bx_e = -(Mq (x) G),
+//   By_e = -(G (x) Mq) (Kronecker order: y factor (x) x factor).
+// * The 25 Vanka patch matrices of a level (paper, subsection "Vanka patch
+//   matrices"), assembled locally from the elements around a representative
+//   patch of each class, with the Dirichlet DoFs eliminated symmetrically,
+//   and inverted once (the paper inverts the patch matrices ahead of time).
+// * The coarsest-level operator, bordered by the constant-pressure vector
+//   and inverted (Algorithm 1's exact level-0 solve).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "vkmg_internal.h"
+
+namespace vkmg {
+
+namespace {
+
+constexpr int K1n[3][3] = {{7, -8, 1}, {-8, 16, -8}, {1, -8, 7}};   // x 1/(3h)
+constexpr int M1n[3][3] = {{4, 2, -1}, {2, 16, 2}, {-1, 2, 4}};     // x h/30
+constexpr int Gn[2][3] = {{-5, 4, 1}, {-1, -4, 5}};                 // x 1/6
+constexpr int Mqn[2][3] = {{1, 2, 0}, {0, 2, 1}};                   // x h/6
+
+// Element Laplacian entry per unit viscosity between local Q2 nodes
+// (a,b) and (c,d): (M1[b][d] K1[a][c] + K1[b][d] M1[a][c]), h-independent.
+double elem_L(int a, int b, int c, int d) {
+    return double(M1n[b][d] * K1n[a][c] + K1n[b][d] * M1n[a][c]) / 90.0;
+}
+// -int phi_(c,d) d psi_(a,b)/dx and /dy
+double elem_Bx(int c, int d, int a, int b, double h) {
+    return -h * double(Mqn[d][b] * Gn[c][a]) / 36.0;
+}
+double elem_By(int c, int d, int a, int b, double h) {
+    return -h * double(Gn[d][b] * Mqn[c][a]) / 36.0;
+}
+
+}  // namespace
+
+Geom make_geom(int32_t N, double nu) {
+    Geom g;
+    g.N = N;
+    g.s2 = 2 * N + 1;
+    g.s1 = N + 1;
+    g.nq2 = int64_t(g.s2) * g.s2;
+    g.nq1 = int64_t(g.s1) * g.s1;
+    g.n = 2 * g.nq2 + g.nq1;
+    g.h = 1.0 / double(N);
+    g.nu = nu;
+    return g;
+}
+
+int distance_class(int i, int N) {
+    if (i == 0) return 0;
+    if (i == N) return 4;
+    if (i == 1) return 1;
+    if (i == N - 1) return 3;
+    return 2;
+}
+
+int class_representative(int c, int N) {
+    switch (c) {
+        case 0: return 0;
+        case 1: return 1;
+        case 2: return 2;
+        case 3: return N - 1;
+        default: return N;
+    }
+}
+
+bool patch_matrix(int N, double nu, int cls, double* A, uint8_t* present) {
+    if (N < 4 || cls < 0 || cls >= kClasses) return false;
+    const int I = class_representative(cls % 5, N);
+    const int J = class_representative(cls / 5, N);
+    const double h = 1.0 / N;
+    const int s2 = 2 * N + 1;
+    std::fill(A, A + kSlots * kSlots, 0.0);
+    uint8_t pres[kSlots];
+    bool dir[kSlots];
+    for (int b = 0; b < 5; ++b)
+        for (int a = 0; a < 5; ++a) {
+            const int qi = 2 * I - 2 + a, qj = 2 * J - 2 + b;
+            const bool in = qi >= 0 && qi < s2 && qj >= 0 && qj < s2;
+            const bool bnd = in && (qi == 0 || qj == 0 || qi == s2 - 1 || qj == s2 - 1);
+            pres[5 * b + a] = pres[25 + 5 * b + a] = in ? 1 : 0;
+            dir[5 * b + a] = dir[25 + 5 * b + a] = bnd;
+        }
+    pres[50] = 1;
+    dir[50] = false;
+    // slot of the Q2 node (qi, qj) or -1
+    auto vslot = [&](int qi, int qj) -> int {
+        const int a = qi - (2 * I - 2), b = qj - (2 * J - 2);
+        if (a < 0 || a > 4 || b < 0 || b > 4) return -1;
+        return 5 * b + a;
+    };
+    for (int ey = std::max(0, J - 2); ey <= std::min(N - 1, J + 1); ++ey)
+        for (int ex = std::max(0, I - 2); ex <= std::min(N - 1, I + 1); ++ex) {
+            int sl[9];
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) sl[3 * b + a] = vslot(2 * ex + a, 2 * ey + b);
+            // pressure: only the patch's own Q1 node belongs to the patch
+            int pl = -1;  // local Q1 index (d*2+c) of node (I,J) in this element
+            for (int d = 0; d < 2; ++d)
+                for (int c = 0; c < 2; ++c)
+                    if (ex + c == I && ey + d == J) pl = 2 * d + c;
+            for (int k = 0; k < 9; ++k) {
+                if (sl[k] < 0) continue;
+                const int a = k % 3, b = k / 3;
+                for (int m = 0; m < 9; ++m) {
+                    if (sl[m] < 0) continue;
+                    const double v = nu * elem_L(a, b, m % 3, m / 3);
+                    A[sl[k] * kSlots + sl[m]] += v;
+                    A[(25 + sl[k]) * kSlots + 25 + sl[m]] += v;
+                }
+                if (pl >= 0) {
+                    const int c = pl % 2, d = pl / 2;
+                    const double bx = elem_Bx(c, d, a, b, h);
+                    const double by = elem_By(c, d, a, b, h);
+                    A[50 * kSlots + sl[k]] += bx;
+                    A[sl[k] * kSlots + 50] += bx;
+                    A[50 * kSlots + 25 + sl[k]] += by;
+                    A[(25 + sl[k]) * kSlots + 50] += by;
+                }
+            }
+        }
+    // symmetric elimination of Dirichlet slots; identity on absent slots
+    for (int s = 0; s < kSlots; ++s) {
+        if (pres[s] && !dir[s]) continue;
+        for (int t = 0; t < kSlots; ++t) {
+            A[s * kSlots + t] = 0.0;
+            A[t * kSlots + s] = 0.0;
+        }
+        A[s * kSlots + s] = 1.0;
+    }
+    if (present) std::memcpy(present, pres, kSlots);
+    return true;
+}
+
+bool invert_dense(int n, std::vector<double>& A, std::vector<double>& Ainv) {
+    Ainv.assign(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) Ainv[size_t(i) * n + i] = 1.0;
+    double scale = 0.0;
+    for (double v : A) scale = std::max(scale, std::fabs(v));
+    if (!(scale > 0.0) || !std::isfinite(scale)) return false;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        double best = std::fabs(A[size_t(col) * n + col]);
+        for (int r = col + 1; r < n; ++r) {
+            const double v = std::fabs(A[size_t(r) * n + col]);
+            if (v > best) {
+                best = v;
+                piv = r;
+            }
+        }
+        if (best <= 1e-13 * scale) return false;
+        if (piv != col) {
+            for (int c = 0; c < n; ++c) {
+                std::swap(A[size_t(piv) * n + c], A[size_t(col) * n + c]);
+                std::swap(Ainv[size_t(piv) * n + c], Ainv[size_t(col) * n + c]);
+            }
+        }
+        const double d = 1.0 / A[size_t(col) * n + col];
+        for (int c = 0; c < n; ++c) {
+            A[size_t(col) * n + c] *= d;
+            Ainv[size_t(col) * n + c] *= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            const double f = A[size_t(r) * n + col];
+            if (f == 0.0) continue;
+            double* ar = &A[size_t(r) * n];
+            double* ir = &Ainv[size_t(r) * n];
+            const double* ac = &A[size_t(col) * n];
+            const double* ic = &Ainv[size_t(col) * n];
+            for (int c = 0; c < n; ++c) {
+                ar[c] -= f * ac[c];
+                ir[c] -= f * ic[c];
+            }
+        }
+    }
+    return true;
+}
+
+void weighted_inverse(int N, int cls, double omega, const double* Ainv, const uint8_t* present,
+                      double* W) {
+    const int I = class_representative(cls % 5, N);
+    const int J = class_representative(cls / 5, N);
+    const int s2 = 2 * N + 1;
+    for (int s = 0; s < kSlots; ++s) {
+        double w = 0.0;
+        if (s == 50) {
+            w = omega;  // each pressure DoF lies in exactly one patch
+        } else if (present[s]) {
+            const int loc = s % 25, a = loc % 5, b = loc / 5;
+            const int qi = 2 * I - 2 + a, qj = 2 * J - 2 + b;
+            const bool bnd = qi == 0 || qj == 0 || qi == s2 - 1 || qj == s2 - 1;
+            if (!bnd) {
+                // patches containing a free Q2 node: 3 per direction through a
+                // vertex (even index), 2 through a midpoint (odd index)
+                const int m = ((a % 2) ? 2 : 3) * ((b % 2) ? 2 : 3);
+                w = omega / double(m);
+            }
+        }
+        for (int t = 0; t < kSlots; ++t)
+            W[s * kSlots + t] = (w != 0.0 && present[t]) ? w * Ainv[s * kSlots + t] : 0.0;
+    }
+}
+
+void assemble_dense_level(int N, double nu, std::vector<double>& A) {
+    const Geom g = make_geom(N, nu);
+    const int64_t n = g.n;
+    A.assign(size_t(n) * n, 0.0);
+    auto ux = [&](int qi, int qj) { return int64_t(qj) * g.s2 + qi; };
+    auto uy = [&](int qi, int qj) { return g.nq2 + int64_t(qj) * g.s2 + qi; };
+    auto pp = [&](int i, int j) { return 2 * g.nq2 + int64_t(j) * g.s1 + i; };
+    for (int ey = 0; ey < N; ++ey)
+        for (int ex = 0; ex < N; ++ex)
+            for (int k = 0; k < 9; ++k) {
+                const int a = k % 3, b = k / 3;
+                const int qi = 2 * ex + a, qj = 2 * ey + b;
+                for (int m = 0; m < 9; ++m) {
+                    const int c = m % 3, d = m / 3;
+                    const double v = nu * elem_L(a, b, c, d);
+                    A[ux(qi, qj) * n + ux(2 * ex + c, 2 * ey + d)] += v;
+                    A[uy(qi, qj) * n + uy(2 * ex + c, 2 * ey + d)] += v;
+                }
+                for (int l = 0; l < 4; ++l) {
+                    const int c = l % 2, d = l / 2;
+                    const int64_t P = pp(ex + c, ey + d);
+                    const double bx = elem_Bx(c, d, a, b, g.h), by = elem_By(c, d, a, b, g.h);
+                    A[P * n + ux(qi, qj)] += bx;
+                    A[ux(qi, qj) * n + P] += bx;
+                    A[P * n + uy(qi, qj)] += by;
+                    A[uy(qi, qj) * n + P] += by;
+                }
+            }
+    for (int qj = 0; qj < g.s2; ++qj)
+        for (int qi = 0; qi < g.s2; ++qi) {
+            if (!(qi == 0 || qj == 0 || qi == g.s2 - 1 || qj == g.s2 - 1)) continue;
+            for (int64_t s : {ux(qi, qj), uy(qi, qj)}) {
+                for (int64_t t = 0; t < n; ++t) {
+                    A[s * n + t] = 0.0;
+                    A[t * n + s] = 0.0;
+                }
+                A[s * n + s] = 1.0;
+            }
+        }
+}
+
+bool coarse_bordered_inverse(int N, double nu, std::vector<double>& C) {
+    const Geom g = make_geom(N, nu);
+    const int64_t n = g.n, nb = n + 1;
+    std::vector<double> A;
+    assemble_dense_level(N, nu, A);
+    std::vector<double> Ab(size_t(nb) * nb, 0.0);
+    for (int64_t r = 0; r < n; ++r)
+        for (int64_t c = 0; c < n; ++c) Ab[r * nb + c] = A[r * n + c];
+    for (int64_t k = 2 * g.nq2; k < n; ++k) {
+        Ab[k * nb + n] = 1.0;
+        Ab[n * nb + k] = 1.0;
+    }
+    std::vector<double> inv;
+    if (!invert_dense(int(nb), Ab, inv)) return false;
+    C.assign(size_t(n) * n, 0.0);
+    for (int64_t r = 0; r < n; ++r)
+        for (int64_t c = 0; c < n; ++c) C[r * n + c] = inv[r * nb + c];
+    return true;
+}
+
+}  // namespace vkmg

@@ -1,0 +1,55 @@
+// Launchers of the vkmg HIP kernels (kernels.hip).  All launches are
+// asynchronous on `stream`; shapes are validated by the callers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "vkmg_internal.h"
+
+namespace vkmg {
+
+// r = b - A x (mode 0) or r = A x (mode 1, b unused); Ti: type of x,
+// To: type of b and r, arithmetic in To.
+template <typename Tx, typename T>
+void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hipStream_t s);
+
+// b = M f - A_FD g on free rows, g on Dirichlet rows, -B_pD g on pressure rows.
+void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hipStream_t s);
+
+// One Vanka update given the residual r of x: x += sum_i V_i^T W_i A_i^{-1} V_i r.
+template <typename T>
+void launch_vanka_update(const Geom& g, const T* r, T* x, const T* Wall, hipStream_t s);
+
+// Transfers between the fine level gf and the coarse level gc (gf.N == 2 gc.N).
+template <typename T>
+void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, hipStream_t s);
+template <typename T>
+void launch_prolong_add(const Geom& gf, const Geom& gc, const T* ec, T* xf, hipStream_t s);
+
+// e = C r with C (n x n, FP64) the coarse bordered inverse.
+template <typename T>
+void launch_coarse_gemv(int64_t n, const double* C, const T* r, T* e, hipStream_t s);
+
+// Elementwise helpers.
+template <typename T>
+void launch_fill_zero(T* x, int64_t n, hipStream_t s);
+template <typename Ti, typename To>
+void launch_cast(const Ti* in, To* out, int64_t n, hipStream_t s);
+
+// Krylov kernels (FP64).  V: k vectors of length n with stride ldv.
+constexpr int kDotBlocks = 512;
+// part[v * kDotBlocks + blk] = partial dot of V_v and w
+void launch_mdot_partial(const double* V, int64_t ldv, int k, const double* w, int64_t n,
+                         double* part, hipStream_t s);
+// out[v] = sum of the kDotBlocks partials of vector v (k vectors)
+void launch_reduce_partials(const double* part, int k, double* out, hipStream_t s);
+// w -= sum_v h[v] V_v ; if part != nullptr also part[blk] = partial ||w_new||^2
+void launch_update(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n,
+                   double* part, hipStream_t s);
+// x += sum_v y[v] Z_v
+void launch_axpy_multi(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t n,
+                       hipStream_t s);
+// out = alpha * in
+void launch_scale(const double* in, double alpha, double* out, int64_t n, hipStream_t s);
+
+}  // namespace vkmg

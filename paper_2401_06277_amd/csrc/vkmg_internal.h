@@ -1,0 +1,56 @@
+// Internal declarations shared by the host setup code, the kernels and the
+// C-ABI layer of the vkmg library.  Not part of the public interface.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace vkmg {
+
+constexpr int kSlots = 51;    // DoFs of a full Vanka patch: 2 x 25 velocity + 1 pressure
+constexpr int kClasses = 25;  // distinct patch matrices on a uniform mesh
+constexpr int kInteriorClass = 12;  // class_x = class_y = 2
+
+// Geometry of one level (N elements per side).
+struct Geom {
+    int32_t N;       // elements per side
+    int32_t s2, s1;  // Q2 and Q1 nodes per side: 2N+1, N+1
+    int64_t nq2;     // (2N+1)^2
+    int64_t nq1;     // (N+1)^2
+    int64_t n;       // 2 nq2 + nq1
+    double h;        // 1/N
+    double nu;       // viscosity
+};
+
+Geom make_geom(int32_t N, double nu);
+
+// ---------------------------------------------------------------------------
+// Host setup (host_setup.cpp), pure C++ in FP64.
+// ---------------------------------------------------------------------------
+
+// 0: low boundary, 1: one element in, 2: interior, 3: one element from the
+// high boundary, 4: high boundary.  Requires N >= 4 for five distinct classes.
+int distance_class(int i, int N);
+int class_representative(int c, int N);
+
+// Patch matrix of class `cls` (51x51 row-major, absent slots identity).
+// Returns false if the arguments are out of range.
+bool patch_matrix(int N, double nu, int cls, double* A, uint8_t* present);
+
+// In-place Gauss-Jordan inversion with partial pivoting; false if singular.
+bool invert_dense(int n, std::vector<double>& A, std::vector<double>& Ainv);
+
+// Weighted inverse W A^{-1}: row s scaled by omega/m_s for present free
+// slots, zero for Dirichlet and absent slots.
+void weighted_inverse(int N, int cls, double omega, const double* Ainv, const uint8_t* present,
+                      double* W);
+
+// Dense constrained operator of the whole level (n x n, row-major).
+void assemble_dense_level(int N, double nu, std::vector<double>& A);
+
+// Top-left n x n block of the inverse of the matrix bordered by the
+// constant-pressure vector; false if singular.
+bool coarse_bordered_inverse(int N, double nu, std::vector<double>& C);
+
+}  // namespace vkmg

@@ -1,0 +1,237 @@
+"""Benchmark: Vanka-multigrid-preconditioned FGMRES for Q2-Q1 Stokes on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--N 1024] [--levels 8]
+
+Workload (default): 1024 x 1024 elements, 8 levels (coarsest 8 x 8), nu = 1,
+homogeneous Dirichlet velocity, body force a seeded Gaussian random field
+(length scale 0.1, unit variance, seed 5) on the Q2 nodes; V(2,2) additive
+Vanka with omega = 0.5 inside FGMRES(30), rtol 1e-8.
+
+A step is one complete FGMRES solve to rtol 1e-8 from the zero initial
+guess (right-hand side resident in HBM), i.e. one pass of every step of the
+hot path: residual, Vanka gather/apply/scatter, restriction, coarsest solve,
+prolongation, V-cycle, Arnoldi/Givens and solution update.  The timed loop
+runs K such solves with the plain FP64 path; ``value`` is the Vanka
+patch-updates per second sustained over those solves (patch solves per
+V-cycle x V-cycles / wall time).  A second timed loop of K solves with the
+V-cycle in FP32 (FGMRES, Arnoldi and the coarse solve kept in FP64) is
+reported under "fp32_mg".
+
+Prints one JSON line.  The roofline object is for the dominant kernel, the
+finest-level Vanka update, timed with HIP events on its launch stream during
+the FP64 timed loop.  The cpu_baseline object times the CPU oracle (plain
+NumPy/SciPy FP64) on a bounded sample: V-cycles of the same method at
+256 x 256 elements.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--N", type=int, default=1024)
+    ap.add_argument("--levels", type=int, default=8)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-N", type=int, default=256)
+    ap.add_argument("--cpu-levels", type=int, default=6)
+    ap.add_argument("--cpu-vcycles", type=int, default=5)
+    ap.add_argument("--skip-fp32", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(N, levels, nvc):
+    """Oracle V-cycles at N x N (setup excluded), patch-updates/s."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import fem, multigrid
+    from stokes_inputs import gaussian_random_field
+
+    t0 = time.perf_counter()
+    H = multigrid.Hierarchy(N, levels)
+    setup_s = time.perf_counter() - t0
+    f = gaussian_random_field(N, 5, length=0.1)
+    _, b, _, _ = fem.stokes_system(N, 1.0, f_nodal=f)
+    H.vcycle(b)  # warm
+    t0 = time.perf_counter()
+    for _ in range(nvc):
+        H.vcycle(b)
+    dt = time.perf_counter() - t0
+    ups = H.patch_updates_per_cycle() * nvc / dt
+    blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {
+        "value": ups,
+        "unit": "patch-updates/s",
+        "cores": int(blas_threads),
+        "kind": "oracle",
+        "sample": (f"{nvc} FP64 V(2,2) cycles of the oracle at {N}x{N} elements, {levels} levels "
+                   f"(setup {setup_s:.1f} s excluded, {dt:.1f} s timed); dense BLAS on "
+                   f"{blas_threads} threads, sparse matvecs single-threaded; host has "
+                   f"{os.cpu_count()} logical CPUs"),
+        "seconds_per_vcycle": dt / nvc,
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
+                                   "not supported (use --gpus 1)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2401_06277_amd as vk
+    from stokes_inputs import gaussian_random_field
+
+    torch.cuda.set_device(0)
+    N, L = a.N, a.levels
+    log(f"[bench] setup N={N} levels={L}")
+    f = gaussian_random_field(N, 5, length=0.1)
+    fd = torch.from_numpy(np.ascontiguousarray(f.ravel())).cuda()
+
+    def make(prec):
+        s = vk.VkmgSolver(N, L, precision=prec)
+        b = s.assemble_rhs(fd)
+        x = torch.zeros_like(b)
+        return s, b, x
+
+    s64, b, x = make("fp64")
+    n = s64.layout["n"]
+    ups_per_cycle = sum(4 * ((N >> (L - 1 - l)) + 1) ** 2 for l in range(1, L))
+
+    def run_solves(s, b, x, steps, timed):
+        iters = []
+        infos = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            x.zero_()
+            info = s.fgmres_solve(b, x, rtol=a.rtol, restart=30, max_iters=500)
+            iters.append(info["iterations"])
+            infos.append(info)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, iters, infos
+
+    log("[bench] fp64 warmup")
+    run_solves(s64, b, x, a.warmup, False)
+    s64.set_timing(1 << vk.KERNEL_VANKA)
+    log("[bench] fp64 timed")
+    dt64, it64, inf64 = run_solves(s64, b, x, a.steps, True)
+    nl, ms = s64.kernel_timing(vk.KERNEL_VANKA, L - 1)
+    s64.set_timing(0)
+    for inf in inf64:
+        if inf["status_name"] != "VKMG_OK":
+            log(f"[bench] solve did not converge: {inf}")
+            sys.exit(1)
+    x64 = x.clone()
+    value = ups_per_cycle * sum(it64) / dt64
+    avg_launch_s = ms / 1e3 / max(nl, 1)
+    # algorithmic bytes of one finest-level Vanka update: read the residual
+    # and the iterate, write the iterate, 8 bytes each, over all n DoFs
+    alg_bytes = 3 * 8 * n
+    achieved = alg_bytes / avg_launch_s / 1e9
+
+    # standalone V-cycle rate (median of 20)
+    r = torch.randn(n, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(r)
+    for _ in range(3):
+        s64.vcycle(r, z)
+    ts = []
+    for _ in range(20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s64.vcycle(r, z)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    ts.sort()
+    vcycle_s = ts[len(ts) // 2]
+
+    out = {
+        "metric": "Vanka V-cycle patch-updates/s + FGMRES time-to-1e-8, FP64 vs FP32-MG, 1024²",
+        "value": value,
+        "unit": "patch-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt64 / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"2D Stokes Q2-Q1, {N}x{N} elements, {L} levels, GRF body force "
+                         f"(l=0.1, seed 5), FGMRES(30) + V(2,2) Vanka omega=0.5, rtol {a.rtol:g}"),
+            "N": N, "levels": L, "dofs": n, "patch_updates_per_vcycle": ups_per_cycle,
+        },
+        "time_to_1e8_s": dt64 / a.steps,
+        "fgmres_iterations": it64[0],
+        "true_rel_res": inf64[-1]["true_rel_res"],
+        "vcycle_s": vcycle_s,
+        "vcycle_patch_updates_per_s": ups_per_cycle / vcycle_s,
+        "roofline": {
+            "kernel": "vanka_update_kernel (finest level; interior + boundary tile instances)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "launches": nl,
+            "avg_launch_us": avg_launch_s * 1e6,
+            "alg_bytes_per_launch": alg_bytes,
+        },
+    }
+    s64.close()
+
+    if not a.skip_fp32:
+        s32, b32, x32 = make("fp32")
+        log("[bench] fp32-mg warmup")
+        run_solves(s32, b32, x32, a.warmup, False)
+        log("[bench] fp32-mg timed")
+        dt32, it32, inf32 = run_solves(s32, b32, x32, a.steps, True)
+        off_p = 2 * (2 * N + 1) ** 2
+
+        def centred(v):  # remove the pressure constant (the null space)
+            v = v.clone()
+            v[off_p:] -= v[off_p:].mean()
+            return v
+
+        diff = float(torch.linalg.norm(centred(x32) - centred(x64)) / torch.linalg.norm(centred(x64)))
+        out["fp32_mg"] = {
+            "time_to_1e8_s": dt32 / a.steps,
+            "fgmres_iterations": it32[0],
+            "true_rel_res": inf32[-1]["true_rel_res"],
+            "patch_updates_per_s": ups_per_cycle * sum(it32) / dt32,
+            "rel_diff_vs_fp64_path": diff,
+            "speedup_vs_fp64": dt64 / dt32,
+            "converged": all(i["status_name"] == "VKMG_OK" for i in inf32),
+        }
+        s32.close()
+
+    if not a.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(a.cpu_N, a.cpu_levels, a.cpu_vcycles)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -199,15 +199,20 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
                               int32_t restart, int32_t max_iters, vkmg_info* info, void* stream);
 
 /*
- * Per-kernel device timing.  While enabled, the library brackets every
- * launch of the classes in vkmg_kernel_class with HIP events on the launch
- * stream; vkmg_kernel_timing returns the number of launches recorded and
- * the summed event-measured duration in milliseconds (it synchronises the
- * recorded events).  vkmg_set_timing(ctx, 1) clears previous records.
+ * Per-kernel device timing.  While bit k of `class_mask` is set, the
+ * library brackets every launch of kernel class k (vkmg_kernel_class) with
+ * a pair of HIP events recorded on the launch stream, tagged with the
+ * multigrid level it ran on (-1 for the FGMRES vector kernels).  A Vanka
+ * "launch" is the update of one sweep (the interior-tile and boundary-tile
+ * kernels together).  vkmg_set_timing discards all previous records;
+ * mask 0 stops recording.  vkmg_kernel_timing waits for the recorded events
+ * and returns, for class `kernel_class` and level `level` (-1 = all
+ * levels), the number of bracketed launches and their summed duration in
+ * milliseconds.  Records accumulate until the next vkmg_set_timing.
  */
-vkmg_status vkmg_set_timing(vkmg_ctx* ctx, int32_t enable);
-vkmg_status vkmg_kernel_timing(vkmg_ctx* ctx, int32_t kernel_class, int64_t* launches,
-                               double* total_ms);
+vkmg_status vkmg_set_timing(vkmg_ctx* ctx, int32_t class_mask);
+vkmg_status vkmg_kernel_timing(vkmg_ctx* ctx, int32_t kernel_class, int32_t level,
+                               int64_t* launches, double* total_ms);
 
 /*
  * Host-only (no GPU needed): the Vanka patch matrix A_i = V_i A V_i^T of

@@ -104,7 +104,7 @@ def load_library(path: str = LIB_PATH):
         "vkmg_vcycle": (c_int32, [P, P, P, P]),
         "vkmg_fgmres_solve": (c_int32, [P, P, P, c_double, c_int32, c_int32, POINTER(Info), P]),
         "vkmg_set_timing": (c_int32, [P, c_int32]),
-        "vkmg_kernel_timing": (c_int32, [P, c_int32, POINTER(c_int64), POINTER(c_double)]),
+        "vkmg_kernel_timing": (c_int32, [P, c_int32, c_int32, POINTER(c_int64), POINTER(c_double)]),
         "vkmg_host_patch_matrix": (c_int32, [c_int32, c_double, c_double, c_int32, P, P, P, P]),
         "vkmg_status_string": (c_char_p, [c_int32]),
         "vkmg_last_error": (c_char_p, []),
@@ -300,9 +300,11 @@ class VkmgSolver:
     def set_timing(self, class_mask: int):
         _check(_lib.vkmg_set_timing(self._ctx, class_mask), "vkmg_set_timing")
 
-    def kernel_timing(self, kernel_class: int):
+    def kernel_timing(self, kernel_class: int, level: int = -1):
+        """(launches, total milliseconds) recorded for a kernel class on one
+        level (-1: all levels) since the last set_timing."""
         n = c_int64()
         ms = c_double()
-        _check(_lib.vkmg_kernel_timing(self._ctx, kernel_class, byref(n), byref(ms)),
+        _check(_lib.vkmg_kernel_timing(self._ctx, kernel_class, level, byref(n), byref(ms)),
                "vkmg_kernel_timing")
         return n.value, ms.value

@@ -40,7 +40,8 @@ struct LevelBuf {
     void* x = nullptr;  // MG precision
     void* b = nullptr;
     void* r = nullptr;
-    void* W = nullptr;  // 25 weighted patch inverses, MG precision (relaxed levels)
+    void* W = nullptr;     // patch-operator table, MG precision (relaxed levels)
+    void* dbuf = nullptr;  // boundary-patch corrections (relaxed levels)
 };
 
 }  // namespace
@@ -63,9 +64,11 @@ struct vkmg_ctx {
     int basis_cap = 0;
     // timing
     int32_t timing_mask = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> events[VKMG_KERNEL_COUNT];
-    int64_t launches[VKMG_KERNEL_COUNT] = {0};
-    double total_ms[VKMG_KERNEL_COUNT] = {0};
+    struct EventPair {
+        hipEvent_t start, stop;
+        int level;  // -1 for launches not tied to a level (Krylov vectors)
+    };
+    std::vector<EventPair> events[VKMG_KERNEL_COUNT];
     std::vector<void*> allocations;
 
     size_t esize() const { return opt.mg_precision == VKMG_FP32 ? 4 : 8; }
@@ -81,8 +84,9 @@ struct Timed {
     vkmg_ctx* c;
     int cls;
     hipStream_t s;
+    int level;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    Timed(vkmg_ctx* ctx, int k, hipStream_t st) : c(ctx), cls(k), s(st) {
+    Timed(vkmg_ctx* ctx, int k, hipStream_t st, int lev = -1) : c(ctx), cls(k), s(st), level(lev) {
         if (c->timing_mask & (1 << cls)) {
             (void)hipEventCreate(&e0);
             (void)hipEventCreate(&e1);
@@ -92,7 +96,7 @@ struct Timed {
     ~Timed() {
         if (e0) {
             (void)hipEventRecord(e1, s);
-            c->events[cls].emplace_back(e0, e1);
+            c->events[cls].push_back({e0, e1, level});
         }
     }
 };
@@ -108,10 +112,11 @@ void free_all(vkmg_ctx* c) {
     c->allocations.clear();
     if (c->hhost) (void)hipHostFree(c->hhost);
     c->hhost = nullptr;
+
     for (auto& v : c->events)
         for (auto& e : v) {
-            (void)hipEventDestroy(e.first);
-            (void)hipEventDestroy(e.second);
+            (void)hipEventDestroy(e.start);
+            (void)hipEventDestroy(e.stop);
         }
 }
 
@@ -138,11 +143,11 @@ void sweep_t(vkmg_ctx* c, int l, T* x, const T* b, hipStream_t s) {
     LevelBuf& L = c->lev[l];
     T* r = static_cast<T*>(L.r);
     {
-        Timed t(c, VKMG_KERNEL_RESIDUAL, s);
+        Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
         launch_residual<T, T>(L.g, b, x, r, 0, s);
     }
-    Timed t(c, VKMG_KERNEL_VANKA, s);
-    launch_vanka_update<T>(L.g, r, x, static_cast<const T*>(L.W), s);
+    Timed t(c, VKMG_KERNEL_VANKA, s, l);
+    launch_vanka_update<T>(L.g, r, x, static_cast<const T*>(L.W), static_cast<T*>(L.dbuf), s);
 }
 
 // MG(l, b) of Algorithm 1 with zero initial guess, result in x.
@@ -155,32 +160,33 @@ void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
     for (int i = 0; i < c->opt.nu_pre; ++i) {
         if (i == 0) {
             // x = 0, so the residual is b itself
-            Timed t(c, VKMG_KERNEL_VANKA, s);
-            launch_vanka_update<T>(L.g, b, x, static_cast<const T*>(L.W), s);
+            Timed t(c, VKMG_KERNEL_VANKA, s, l);
+            launch_vanka_update<T>(L.g, b, x, static_cast<const T*>(L.W), static_cast<T*>(L.dbuf),
+                                   s);
         } else {
             sweep_t<T>(c, l, x, b, s);
         }
     }
     const T* rr = b;
     if (c->opt.nu_pre > 0) {
-        Timed t(c, VKMG_KERNEL_RESIDUAL, s);
+        Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
         launch_residual<T, T>(L.g, b, x, r, 0, s);
         rr = r;
     }
     T* bc = static_cast<T*>(Lc.b);
     T* xc = static_cast<T*>(Lc.x);
     {
-        Timed t(c, VKMG_KERNEL_TRANSFER, s);
+        Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
         launch_restrict<T>(L.g, Lc.g, rr, bc, s);
     }
     if (l - 1 == 0) {
-        Timed t(c, VKMG_KERNEL_COARSE, s);
+        Timed t(c, VKMG_KERNEL_COARSE, s, 0);
         launch_coarse_gemv<T>(Lc.g.n, c->C, bc, xc, s);
     } else {
         mg_t<T>(c, l - 1, bc, xc, s);
     }
     {
-        Timed t(c, VKMG_KERNEL_TRANSFER, s);
+        Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
         launch_prolong_add<T>(L.g, Lc.g, xc, x, s);
     }
     for (int i = 0; i < c->opt.nu_post; ++i) sweep_t<T>(c, l, x, b, s);
@@ -322,7 +328,7 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
     std::vector<std::vector<double>> Wh(levels);
     for (int l = 1; l < levels; ++l) {
         const int Nl = N >> (levels - 1 - l);
-        Wh[l].resize(size_t(kClasses) * kSlots * kSlots);
+        Wh[l].assign(size_t(kLevelTable), 0.0);
         for (int c = 0; c < kClasses; ++c) {
             std::vector<double> Ak(kSlots * kSlots), inv;
             uint8_t pres[kSlots];
@@ -330,6 +336,16 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
             if (!invert_dense(kSlots, Ak, inv))
                 return fail(VKMG_ERR_SINGULAR_PATCH, "setup: singular Vanka patch matrix");
             weighted_inverse(Nl, c, o.omega, inv.data(), pres, &Wh[l][size_t(c) * kSlots * kSlots]);
+        }
+        if (!interior_symmetry_blocks(&Wh[l][size_t(kInteriorClass) * kSlots * kSlots],
+                                      &Wh[l][kDenseTable], 1e-12))
+            return fail(VKMG_ERR_SINGULAR_PATCH,
+                        "setup: interior patch inverse is not reflection symmetric");
+        // the device reads the dense inverses column by column: store W^T
+        for (int c = 0; c < kClasses; ++c) {
+            double* Wc = &Wh[l][size_t(c) * kSlots * kSlots];
+            for (int i = 0; i < kSlots; ++i)
+                for (int j = i + 1; j < kSlots; ++j) std::swap(Wc[i * kSlots + j], Wc[j * kSlots + i]);
         }
     }
     std::vector<double> Ch;
@@ -350,8 +366,10 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         st = alloc(c.get(), &L.x, es * L.g.n);
         if (st == VKMG_OK) st = alloc(c.get(), &L.b, es * L.g.n);
         if (st == VKMG_OK) st = alloc(c.get(), &L.r, es * L.g.n);
+        if (st == VKMG_OK && l >= 1)
+            st = alloc(c.get(), &L.dbuf, es * size_t(vanka_boundary_scratch(L.g.N)));
         if (st == VKMG_OK && l >= 1) {
-            const size_t nw = size_t(kClasses) * kSlots * kSlots;
+            const size_t nw = size_t(kLevelTable);
             st = alloc(c.get(), &L.W, es * nw);
             if (st == VKMG_OK) {
                 if (o.mg_precision == VKMG_FP64) {
@@ -670,36 +688,35 @@ vkmg_status vkmg_set_timing(vkmg_ctx* ctx, int32_t class_mask) {
     VKMG_HIP(hipSetDevice(ctx->device));
     for (int k = 0; k < VKMG_KERNEL_COUNT; ++k) {
         for (auto& e : ctx->events[k]) {
-            (void)hipEventSynchronize(e.second);
-            (void)hipEventDestroy(e.first);
-            (void)hipEventDestroy(e.second);
+            (void)hipEventSynchronize(e.stop);
+            (void)hipEventDestroy(e.start);
+            (void)hipEventDestroy(e.stop);
         }
         ctx->events[k].clear();
-        ctx->launches[k] = 0;
-        ctx->total_ms[k] = 0.0;
     }
     ctx->timing_mask = class_mask;
     return VKMG_OK;
 }
 
-vkmg_status vkmg_kernel_timing(vkmg_ctx* ctx, int32_t kernel_class, int64_t* launches,
-                               double* total_ms) {
+vkmg_status vkmg_kernel_timing(vkmg_ctx* ctx, int32_t kernel_class, int32_t level,
+                               int64_t* launches, double* total_ms) {
     if (!ctx || kernel_class < 0 || kernel_class >= VKMG_KERNEL_COUNT)
         return fail(VKMG_ERR_INVALID_ARG, "kernel_timing: bad context or class");
+    if (level < -1 || level >= ctx->L)
+        return fail(VKMG_ERR_INVALID_ARG, "kernel_timing: level must be -1 or in [0, levels)");
     VKMG_HIP(hipSetDevice(ctx->device));
-    auto& ev = ctx->events[kernel_class];
-    for (auto& e : ev) {
-        VKMG_HIP(hipEventSynchronize(e.second));
+    int64_t n = 0;
+    double ms_sum = 0.0;
+    for (auto& e : ctx->events[kernel_class]) {
+        if (level != -1 && e.level != level) continue;
+        VKMG_HIP(hipEventSynchronize(e.stop));
         float ms = 0.f;
-        VKMG_HIP(hipEventElapsedTime(&ms, e.first, e.second));
-        ctx->total_ms[kernel_class] += ms;
-        ctx->launches[kernel_class] += 1;
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
+        VKMG_HIP(hipEventElapsedTime(&ms, e.start, e.stop));
+        ms_sum += ms;
+        ++n;
     }
-    ev.clear();
-    if (launches) *launches = ctx->launches[kernel_class];
-    if (total_ms) *total_ms = ctx->total_ms[kernel_class];
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms_sum;
     return VKMG_OK;
 }
 

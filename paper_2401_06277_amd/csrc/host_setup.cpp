@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "symmetry.h"
 #include "vkmg_internal.h"
 
 namespace vkmg {
@@ -273,6 +274,52 @@ bool coarse_bordered_inverse(int N, double nu, std::vector<double>& C) {
     C.assign(size_t(n) * n, 0.0);
     for (int64_t r = 0; r < n; ++r)
         for (int64_t c = 0; c < n; ++c) C[r * n + c] = inv[r * nb + c];
+    return true;
+}
+
+bool interior_symmetry_blocks(const double* W, double* B, double tol) {
+    // U = U1 (x) U1 per velocity component, identity on the pressure
+    std::vector<double> U(kSlots * kSlots, 0.0);
+    for (int f = 0; f < 2; ++f)
+        for (int qb = 0; qb < 5; ++qb)
+            for (int qa = 0; qa < 5; ++qa)
+                for (int b = 0; b < 5; ++b)
+                    for (int a = 0; a < 5; ++a)
+                        U[(25 * f + 5 * qb + qa) * kSlots + 25 * f + 5 * b + a] =
+                            double(sym_u1(qb, b) * sym_u1(qa, a));
+    U[50 * kSlots + 50] = 1.0;
+    double D[kSlots];
+    for (int t = 0; t < kSlots; ++t) {
+        double d = 0.0;
+        for (int s = 0; s < kSlots; ++s) d += U[t * kSlots + s] * U[t * kSlots + s];
+        D[t] = d;
+    }
+    // Bf = D^{-1} U W U^T D^{-1}
+    std::vector<double> T1(kSlots * kSlots, 0.0), Bf(kSlots * kSlots, 0.0);
+    for (int i = 0; i < kSlots; ++i)
+        for (int k = 0; k < kSlots; ++k) {
+            const double u = U[i * kSlots + k];
+            if (u == 0.0) continue;
+            for (int j = 0; j < kSlots; ++j) T1[i * kSlots + j] += u * W[k * kSlots + j];
+        }
+    double scale = 0.0;
+    for (int i = 0; i < kSlots; ++i)
+        for (int j = 0; j < kSlots; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < kSlots; ++k) acc += T1[i * kSlots + k] * U[j * kSlots + k];
+            Bf[i * kSlots + j] = acc / (D[i] * D[j]);
+            scale = std::max(scale, std::fabs(Bf[i * kSlots + j]));
+        }
+    for (int i = 0; i < kSlots; ++i)
+        for (int j = 0; j < kSlots; ++j)
+            if (sym_block_of(i) != sym_block_of(j) && std::fabs(Bf[i * kSlots + j]) > tol * scale)
+                return false;
+    for (int blk = 0; blk < kSymBlocks; ++blk) {
+        const int n = sym_block_size(blk), off = sym_block_offset(blk);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                B[off + i * n + j] = Bf[sym_member(blk, i) * kSlots + sym_member(blk, j)];
+    }
     return true;
 }
 

@@ -17,8 +17,14 @@ void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hip
 void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hipStream_t s);
 
 // One Vanka update given the residual r of x: x += sum_i V_i^T W_i A_i^{-1} V_i r.
+// `table` is the level's patch-operator table (kLevelTable values: the 25
+// weighted inverses stored transposed, then the interior reflection
+// blocks); `dbuf` is scratch for the boundary patches
+// (vanka_boundary_scratch(N) values).
 template <typename T>
-void launch_vanka_update(const Geom& g, const T* r, T* x, const T* Wall, hipStream_t s);
+void launch_vanka_update(const Geom& g, const T* r, T* x, const T* table, T* dbuf,
+                         hipStream_t s);
+int64_t vanka_boundary_scratch(int N);
 
 // Transfers between the fine level gf and the coarse level gc (gf.N == 2 gc.N).
 template <typename T>

@@ -6,6 +6,7 @@
 
 #include "kernels.h"
 #include "stencil.h"
+#include "symmetry.h"
 
 namespace vkmg {
 
@@ -15,93 +16,60 @@ __device__ __forceinline__ bool q2_boundary(int qi, int qj, int s2) {
     return qi == 0 || qj == 0 || qi == s2 - 1 || qj == s2 - 1;
 }
 
-// Velocity value with Dirichlet (boundary) columns read as zero.  Callers
-// guarantee 0 <= qi, qj < s2.
-template <typename Tx>
-__device__ __forceinline__ Tx ld_free(const Tx* __restrict__ u, int qi, int qj, int s2) {
-    return q2_boundary(qi, qj, s2) ? Tx(0) : u[int64_t(qj) * s2 + qi];
-}
-
-// ---------------------------------------------------------------------------
-// Operator rows
-// ---------------------------------------------------------------------------
-
-// (A x) at the free Q2 node (i,j) of parity (PX, PY), both components.
-template <int PX, int PY, typename Tx, typename T>
-__device__ __forceinline__ void velocity_rows(const Geom& g, const Tx* __restrict__ ux,
-                                              const Tx* __restrict__ uy,
-                                              const Tx* __restrict__ p, int i, int j, T& ax,
-                                              T& ay) {
-    T lx = 0, ly = 0;
-#pragma unroll
-    for (int dy = -2; dy <= 2; ++dy) {
-#pragma unroll
-        for (int dx = -2; dx <= 2; ++dx) {
-            const int c = st_L(PY, PX, dy, dx);
-            if (c != 0) {
-                lx += T(c) * T(ld_free(ux, i + dx, j + dy, g.s2));
-                ly += T(c) * T(ld_free(uy, i + dx, j + dy, g.s2));
-            }
-        }
-    }
-    T bx = 0, by = 0;
-#pragma unroll
-    for (int oy = -2; oy <= 2; ++oy) {
-        if (((oy - PY) & 1) != 0) continue;
-#pragma unroll
-        for (int ox = -2; ox <= 2; ++ox) {
-            if (((ox - PX) & 1) != 0) continue;
-            const int cx = st_Mq(oy) * st_G(ox);
-            const int cy = st_G(oy) * st_Mq(ox);
-            if (cx == 0 && cy == 0) continue;
-            const int I = (i - ox) / 2, J = (j - oy) / 2;
-            const T pv = T(p[int64_t(J) * g.s1 + I]);
-            bx += T(cx) * pv;
-            by += T(cy) * pv;
-        }
-    }
-    const T cl = T(g.nu / 90.0), cb = T(-g.h / 36.0);
-    ax = cl * lx + cb * bx;
-    ay = cl * ly + cb * by;
-}
-
-// (B u) at the Q1 node (I,J).
-template <typename Tx, typename T>
-__device__ __forceinline__ T pressure_row(const Geom& g, const Tx* __restrict__ ux,
-                                          const Tx* __restrict__ uy, int I, int J) {
-    T s = 0;
-#pragma unroll
-    for (int oy = -2; oy <= 2; ++oy) {
-#pragma unroll
-        for (int ox = -2; ox <= 2; ++ox) {
-            const int cx = st_Mq(oy) * st_G(ox);
-            const int cy = st_G(oy) * st_Mq(ox);
-            if (cx == 0 && cy == 0) continue;
-            const int qi = 2 * I + ox, qj = 2 * J + oy;
-            if (qi < 1 || qj < 1 || qi > g.s2 - 2 || qj > g.s2 - 2) continue;
-            const int64_t q = int64_t(qj) * g.s2 + qi;
-            s += T(cx) * T(ux[q]) + T(cy) * T(uy[q]);
-        }
-    }
-    return T(-g.h / 36.0) * s;
-}
-
 // ---------------------------------------------------------------------------
 // Residual r = b - A x (MODE 0) / apply r = A x (MODE 1)
-// One thread per cell (ex, ey) in [0,N]^2: Q2 nodes (2ex+a, 2ey+b), a,b in
-// {0,1}, and the Q1 node (ex, ey).
+// A workgroup computes the rows of a tile of RT x RT cells; cell (ex, ey)
+// holds the Q2 nodes (2ex+a, 2ey+b), a, b in {0,1}, and the Q1 node
+// (ex, ey), one thread per cell.  The x values the rows need (Q2 nodes
+// within two of the tile, Q1 nodes within one) are staged in LDS with the
+// Dirichlet columns already zeroed, so that every row is a fixed stencil.
 // ---------------------------------------------------------------------------
+
+constexpr int RT = 16;              // cells per tile side
+constexpr int RQ2 = 2 * RT + 4;     // staged Q2 nodes per side
+constexpr int RQ1 = RT + 2;         // staged Q1 nodes per side
 
 template <int MODE, typename Tx, typename T>
 __global__ __launch_bounds__(256) void residual_kernel(Geom g, const T* __restrict__ b,
                                                        const Tx* __restrict__ x,
                                                        T* __restrict__ r) {
-    const int ex = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int ey = blockIdx.y * 16 + (threadIdx.x >> 4);
+    __shared__ T s_u[2][RQ2 * RQ2];
+    __shared__ T s_p[RQ1 * RQ1];
+    const int tiles = (g.N + 1 + RT - 1) / RT;
+    const int ntile = tiles * tiles;
+    const int per_xcd = (ntile + 7) / 8;
+    const int tlin = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (tlin >= ntile) return;
+    const int E0x = (tlin % tiles) * RT, E0y = (tlin / tiles) * RT;
+    const int ox = 2 * E0x - 2, oy = 2 * E0y - 2;
+#pragma unroll
+    for (int it = 0; it < (RQ2 * RQ2 + 255) / 256; ++it) {
+        const int t = threadIdx.x + it * 256;
+        if (t < RQ2 * RQ2) {
+            const int qi = ox + t % RQ2, qj = oy + t / RQ2;
+            const bool free = qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
+            const int64_t q = int64_t(qj) * g.s2 + qi;
+            s_u[0][t] = free ? T(x[q]) : T(0);
+            s_u[1][t] = free ? T(x[g.nq2 + q]) : T(0);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < (RQ1 * RQ1 + 255) / 256; ++it) {
+        const int t = threadIdx.x + it * 256;
+        if (t < RQ1 * RQ1) {
+            const int I = E0x - 1 + t % RQ1, J = E0y - 1 + t / RQ1;
+            const bool in = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
+            s_p[t] = in ? T(x[2 * g.nq2 + int64_t(J) * g.s1 + I]) : T(0);
+        }
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % RT, ty = threadIdx.x / RT;
+    const int ex = E0x + tx, ey = E0y + ty;
     if (ex > g.N || ey > g.N) return;
-    const Tx* ux = x;
-    const Tx* uy = x + g.nq2;
-    const Tx* p = x + 2 * g.nq2;
+    // staged coordinates of Q2 node (2ex, 2ey) and of Q1 node (ex, ey)
+    const int c2 = (2 * ty + 2) * RQ2 + 2 * tx + 2;
+    const int c1 = (ty + 1) * RQ1 + tx + 1;
+    const T cl = T(g.nu / 90.0), cb = T(-g.h / 36.0);
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb) {
 #pragma unroll
@@ -110,17 +78,41 @@ __global__ __launch_bounds__(256) void residual_kernel(Geom g, const T* __restri
             if (i >= g.s2 || j >= g.s2) continue;
             const int64_t q = int64_t(j) * g.s2 + i;
             T ax, ay;
-            if (q2_boundary(i, j, g.s2)) {
-                ax = T(ux[q]);
-                ay = T(uy[q]);
-            } else if (aa == 0 && bb == 0) {
-                velocity_rows<0, 0>(g, ux, uy, p, i, j, ax, ay);
-            } else if (aa == 1 && bb == 0) {
-                velocity_rows<1, 0>(g, ux, uy, p, i, j, ax, ay);
-            } else if (aa == 0 && bb == 1) {
-                velocity_rows<0, 1>(g, ux, uy, p, i, j, ax, ay);
+            if (i == 0 || j == 0 || i == g.s2 - 1 || j == g.s2 - 1) {
+                ax = T(x[q]);  // Dirichlet row: identity
+                ay = T(x[g.nq2 + q]);
             } else {
-                velocity_rows<1, 1>(g, ux, uy, p, i, j, ax, ay);
+                T lx = 0, ly = 0, bx = 0, by = 0;
+                const int cn = c2 + bb * RQ2 + aa;
+#pragma unroll
+                for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+                    for (int dx = -2; dx <= 2; ++dx) {
+                        const int c = st_L(bb, aa, dy, dx);
+                        if (c != 0) {
+                            lx += T(c) * s_u[0][cn + dy * RQ2 + dx];
+                            ly += T(c) * s_u[1][cn + dy * RQ2 + dx];
+                        }
+                    }
+                // B^T p: Q1 nodes I with |i - 2I| <= 2, offsets o = i - 2I of
+                // the parity of i
+#pragma unroll
+                for (int oy = -2; oy <= 2; ++oy) {
+                    if (((oy - bb) & 1) != 0) continue;
+#pragma unroll
+                    for (int oxx = -2; oxx <= 2; ++oxx) {
+                        if (((oxx - aa) & 1) != 0) continue;
+                        const int cx = st_Mq(oy) * st_G(oxx);
+                        const int cy = st_G(oy) * st_Mq(oxx);
+                        if (cx == 0 && cy == 0) continue;
+                        // I = (i - o)/2 = ex + (aa - o)/2
+                        const T pv = s_p[c1 + ((bb - oy) / 2) * RQ1 + (aa - oxx) / 2];
+                        bx += T(cx) * pv;
+                        by += T(cy) * pv;
+                    }
+                }
+                ax = cl * lx + cb * bx;
+                ay = cl * ly + cb * by;
             }
             if (MODE == 0) {
                 r[q] = b[q] - ax;
@@ -131,9 +123,19 @@ __global__ __launch_bounds__(256) void residual_kernel(Geom g, const T* __restri
             }
         }
     }
+    T sp = 0;
+#pragma unroll
+    for (int oy = -2; oy <= 2; ++oy)
+#pragma unroll
+        for (int oxx = -2; oxx <= 2; ++oxx) {
+            const int cx = st_Mq(oy) * st_G(oxx);
+            const int cy = st_G(oy) * st_Mq(oxx);
+            if (cx == 0 && cy == 0) continue;
+            const int cc = c2 + oy * RQ2 + oxx;
+            sp += T(cx) * s_u[0][cc] + T(cy) * s_u[1][cc];
+        }
     const int64_t qp = 2 * g.nq2 + int64_t(ey) * g.s1 + ex;
-    const T ap = pressure_row<Tx, T>(g, ux, uy, ex, ey);
-    r[qp] = (MODE == 0) ? b[qp] - ap : ap;
+    r[qp] = (MODE == 0) ? b[qp] - cb * sp : cb * sp;
 }
 
 // ---------------------------------------------------------------------------
@@ -223,154 +225,289 @@ __global__ __launch_bounds__(256) void rhs_kernel(Geom g, const double* __restri
 // Vanka update (owner computes).  A workgroup owns the elements
 // [E0, E0+VT) in each direction: the Q2 nodes [2E0, 2E0+2VT) and the Q1
 // nodes [E0, E0+VT).  It solves every patch that touches an owned DoF --
-// the Q1 nodes [E0-1, E0+VT], VP = VT+2 per direction, one thread each --
-// from the residual staged in LDS, and sums the weighted corrections of
-// the owned DoFs in a fixed order, so every DoF is written by one
-// workgroup and results are bitwise reproducible.
+// the Q1 nodes [E0-1, E0+VT], VP = VT+2 = 16 per direction, one thread
+// each, lanes row-major so that a row of 16 patches is one DPP row -- and
+// sums the weighted corrections of each owned DoF in a fixed order, so
+// every DoF is written by exactly one workgroup and the result is bitwise
+// reproducible.
+//
+// Interior patches (distance >= 2 from the boundary) share one inverse,
+// applied in the reflection-adapted block form (symmetry.h: 651
+// multiply-adds instead of 2601) with coefficients read through the scalar
+// cache.  The O(N) boundary patches (24 other classes) are solved first by
+// vanka_boundary_kernel, one wavefront per patch, into a side buffer that
+// the tile kernel reads.
+//
+// Summation of the corrections: a patch with its lower-left window corner
+// at Q2 column 2tx-4 (tile coordinates) sends slot a to column 2tx-4+a, so
+// column 2m receives slot 4 of patch m, slot 2 of patch m+1 and slot 0 of
+// patch m+2, and column 2m+1 slots 3 and 1 of patches m+1 and m+2.  These
+// x-sums are formed with DPP row shifts inside each 16-lane row; the same
+// rule in y combines rows through one LDS exchange.
 // ---------------------------------------------------------------------------
 
 constexpr int VT = 14;            // owned elements per tile side
-constexpr int VP = VT + 2;        // patches per tile side
+constexpr int VP = VT + 2;        // patches per tile side (= DPP row width)
 constexpr int VNT = VP * VP;      // threads per workgroup (256)
 constexpr int VR = 2 * VT + 7;    // staged residual region (Q2 nodes per side)
-constexpr int VOWN = 2 * VT;      // owned Q2 nodes per side
-constexpr int VOWN_PER_THREAD = (VOWN * VOWN + VNT - 1) / VNT;  // 4
 
-// One row of a patch inverse applied to the gathered patch residual.
+// 1D reflection butterfly and its transpose on 5 values v[o + k*st].
 template <typename T>
-__device__ __forceinline__ T row_dot(const T* __restrict__ Mrow, const T (&rv)[kSlots]) {
-    T a0 = 0, a1 = 0;
+__device__ __forceinline__ void bfly(T (&v)[kSlots], int o, int st) {
+    const T f0 = v[o], f1 = v[o + st], f3 = v[o + 3 * st], f4 = v[o + 4 * st];
+    v[o] = f0 + f4;
+    v[o + st] = f1 + f3;
+    v[o + 3 * st] = f0 - f4;
+    v[o + 4 * st] = f1 - f3;
+}
+template <typename T>
+__device__ __forceinline__ void bfly_t(T (&v)[kSlots], int o, int st) {
+    const T e0 = v[o], e1 = v[o + st], o0 = v[o + 3 * st], o1 = v[o + 4 * st];
+    v[o] = e0 + o0;
+    v[o + st] = e1 + o1;
+    v[o + 3 * st] = e1 - o1;
+    v[o + 4 * st] = e0 - o0;
+}
+
+// v <- W v for the interior weighted inverse W = U^T B U (symmetry.h), in place.
+template <typename T>
+__device__ __forceinline__ void sym_apply(const T* __restrict__ B, T (&v)[kSlots]) {
 #pragma unroll
-    for (int t = 0; t + 1 < kSlots; t += 2) {
-        a0 += Mrow[t] * rv[t];
-        a1 += Mrow[t + 1] * rv[t + 1];
+    for (int f = 0; f < 2; ++f) {
+#pragma unroll
+        for (int b = 0; b < 5; ++b) bfly(v, 25 * f + 5 * b, 1);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) bfly(v, 25 * f + q, 5);
     }
-    a0 += Mrow[kSlots - 1] * rv[kSlots - 1];
-    return a0 + a1;
+#pragma unroll
+    for (int blk = 0; blk < kSymBlocks; ++blk) {
+        constexpr int nmax = 13;
+        const int n = sym_block_size(blk);
+        const T* __restrict__ Bb = B + sym_block_offset(blk);
+        T y[nmax];
+#pragma unroll
+        for (int i = 0; i < nmax; ++i) {
+            if (i >= n) break;
+            T a0 = 0, a1 = 0;
+#pragma unroll
+            for (int j = 0; j < nmax; ++j) {
+                if (j >= n) break;
+                if (j & 1)
+                    a1 += Bb[i * n + j] * v[kSymTable.m[blk][j]];
+                else
+                    a0 += Bb[i * n + j] * v[kSymTable.m[blk][j]];
+            }
+            y[i] = a0 + a1;
+        }
+#pragma unroll
+        for (int i = 0; i < nmax; ++i) {
+            if (i >= n) break;
+            v[kSymTable.m[blk][i]] = y[i];
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) bfly_t(v, 25 * f + q, 5);
+#pragma unroll
+        for (int b = 0; b < 5; ++b) bfly_t(v, 25 * f + 5 * b, 1);
+    }
+}
+
+// Value of lane (l + S) of the same 16-lane row, 0 past the row end
+// (DPP row_shl; the 64-bit value moves as two 32-bit halves).
+template <int S>
+__device__ __forceinline__ double row_shl(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(u & 0xffffffffLL), 0x100 + S, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(u >> 32), 0x100 + S, 0xF, 0xF, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                static_cast<unsigned int>(lo));
+}
+template <int S>
+__device__ __forceinline__ float row_shl(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + S, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ int dclass(int i, int N) {
     return i == 0 ? 0 : i == N ? 4 : i == 1 ? 1 : i == N - 1 ? 3 : 2;
 }
 
-// Tiles whose patches all lie at distance >= 2 from the boundary share the
-// interior inverse (INTERIOR = true: the matrix address is a kernel-uniform
-// value and is read through the scalar cache); the others (INTERIOR = false,
-// launched over all tiles, interior ones returning at once) read the inverse
-// of each patch's class per lane.
-struct TileRange {
-    int lo, hi;  // interior tiles per direction: lo <= t < hi
-};
+// Boundary patches (Q1 nodes within one element of the boundary, 8N - 8 of
+// them, N >= 4) in a fixed order: rows 0, 1, N-1, N in full, then for rows
+// 2..N-2 the columns 0, 1, N-1, N.
+__host__ __device__ inline int n_boundary_patches(int N) { return 8 * N - 8; }
 
-__host__ __device__ inline TileRange interior_tiles(int N) {
-    // tile t covers patches [t VT - 1, t VT + VT]; interior class needs
-    // 2 <= I <= N - 2
-    TileRange r;
-    r.lo = 1;
-    r.hi = (N - 2 - VT) / VT + 1;  // largest t with t VT + VT <= N - 2, plus one
-    if (N - 2 - VT < 0) r.hi = 1;
-    if (r.hi < r.lo) r.hi = r.lo;
-    return r;
+__device__ __forceinline__ void boundary_patch(int k, int N, int& I, int& J) {
+    const int w = N + 1;
+    if (k < 4 * w) {
+        const int rrow = k / w;
+        J = rrow < 2 ? rrow : N - 3 + rrow;
+        I = k % w;
+    } else {
+        k -= 4 * w;
+        J = 2 + k / 4;
+        const int c = k % 4;
+        I = c < 2 ? c : N - 3 + c;
+    }
 }
 
-template <typename T, bool INTERIOR>
-__global__ __launch_bounds__(VNT) void vanka_update_kernel(Geom g, const T* __restrict__ r,
-                                                           T* __restrict__ x,
-                                                           const T* __restrict__ Wall) {
-    __shared__ T s_rx[VR * VR];
-    __shared__ T s_ry[VR * VR];
-    __shared__ T s_d[VNT * 10];
-    const TileRange ir = interior_tiles(g.N);
-    int tbx = blockIdx.x, tby = blockIdx.y;
-    if (INTERIOR) {
-        tbx += ir.lo;
-        tby += ir.lo;
-    } else if (tbx >= ir.lo && tbx < ir.hi && tby >= ir.lo && tby < ir.hi) {
-        return;  // handled by the interior instance
+__device__ __forceinline__ int boundary_index(int I, int J, int N) {
+    const int w = N + 1;
+    if (J <= 1) return J * w + I;
+    if (J >= N - 1) return (J - N + 3) * w + I;
+    const int c = I <= 1 ? I : I - N + 3;
+    return 4 * w + (J - 2) * 4 + c;
+}
+
+// Global index of patch slot s of the patch at Q1 node (I, J), or -1 if the
+// slot lies outside the domain.
+__device__ __forceinline__ int64_t slot_index(const Geom& g, int I, int J, int s) {
+    if (s == 50) return 2 * g.nq2 + int64_t(J) * g.s1 + I;
+    const int f = s / 25, l = s % 25;
+    const int qi = 2 * I - 2 + l % 5, qj = 2 * J - 2 + l / 5;
+    if (qi < 0 || qj < 0 || qi >= g.s2 || qj >= g.s2) return -1;
+    return int64_t(f) * g.nq2 + int64_t(qj) * g.s2 + qi;
+}
+
+// One wavefront per boundary patch: lane s gathers r at slot s, then
+// computes row s of the class's weighted inverse (stored transposed, so the
+// lanes read consecutive addresses) against the gathered residual.
+template <typename T>
+__global__ __launch_bounds__(256) void vanka_boundary_kernel(Geom g, const T* __restrict__ r,
+                                                             const T* __restrict__ table,
+                                                             T* __restrict__ dbuf) {
+    __shared__ T s_r[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + w;
+    const bool active = k < n_boundary_patches(g.N);
+    int I = 0, J = 0;
+    if (active) boundary_patch(k, g.N, I, J);
+    const int cls = 5 * dclass(J, g.N) + dclass(I, g.N);
+    T rv = 0;
+    if (active && lane < kSlots) {
+        const int64_t q = slot_index(g, I, J, lane);
+        if (q >= 0) rv = r[q];
     }
-    const int E0x = tbx * VT, E0y = tby * VT;
-    const int ox = 2 * E0x - 4, oy = 2 * E0y - 4;
-    const int tid = threadIdx.x;
-    for (int t = tid; t < VR * VR; t += VNT) {
-        const int qi = ox + t % VR, qj = oy + t / VR;
-        const bool in = qi >= 0 && qj >= 0 && qi < g.s2 && qj < g.s2;
-        const int64_t q = int64_t(qj) * g.s2 + qi;
-        s_rx[t] = in ? r[q] : T(0);
-        s_ry[t] = in ? r[g.nq2 + q] : T(0);
+    s_r[w][lane] = rv;
+    __syncthreads();
+    if (!active || lane >= kSlots) return;
+    const T* __restrict__ Mt = table + cls * kSlots * kSlots;  // Mt[t][s] = W[s][t]
+    // issue every coefficient load before the first use (one memory round trip)
+    T m[kSlots];
+#pragma unroll
+    for (int t = 0; t < kSlots; ++t) m[t] = Mt[t * kSlots + lane];
+    T a0 = 0, a1 = 0;
+#pragma unroll
+    for (int t = 0; t + 1 < kSlots; t += 2) {
+        a0 += m[t] * s_r[w][t];
+        a1 += m[t + 1] * s_r[w][t + 1];
     }
-    const int tx = tid % VP, ty = tid / VP;
+    a0 += m[kSlots - 1] * s_r[w][kSlots - 1];
+    dbuf[int64_t(k) * 64 + lane] = a0 + a1;
+}
+
+// Tile grid and the XCD-aware tile order: consecutive workgroup ids are
+// dealt round-robin to the 8 XCDs, so id L takes tile (L mod 8) ceil(T/8) +
+// L/8 in row-major order, giving every XCD a contiguous band of tiles whose
+// shared halos stay in its L2.
+__host__ __device__ inline int vanka_tiles(int N) { return (N + 1 + VT - 1) / VT; }
+
+template <typename T>
+__global__ __launch_bounds__(VNT, 2) void vanka_tile_kernel(Geom g, const T* __restrict__ r,
+                                                            T* __restrict__ x,
+                                                            const T* __restrict__ table,
+                                                            const T* __restrict__ dbuf) {
+    // staging of the residual region (2 VR^2 values), reused for the
+    // exchange of the x-sums (20 values per thread)
+    __shared__ T s_buf[20 * VNT];
+    static_assert(2 * VR * VR <= 20 * VNT, "staging region exceeds the shared buffer");
+    T* s_rx = s_buf;
+    T* s_ry = s_buf + VR * VR;
+    const int tiles = vanka_tiles(g.N);
+    const int ntile = tiles * tiles;
+    const int per_xcd = (ntile + 7) / 8;
+    const int tlin = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (tlin >= ntile) return;
+    const int E0x = (tlin % tiles) * VT, E0y = (tlin / tiles) * VT;
+    const int tx = threadIdx.x % VP, ty = threadIdx.x / VP;
     const int I = E0x - 1 + tx, J = E0y - 1 + ty;
     const bool valid = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
+
+    // stage the residual region and gather this thread's patch
+    const int ox = 2 * E0x - 4, oy = 2 * E0y - 4;
+#pragma unroll
+    for (int it = 0; it < (VR * VR + VNT - 1) / VNT; ++it) {
+        const int t = threadIdx.x + it * VNT;
+        if (t < VR * VR) {
+            const int qi = ox + t % VR, qj = oy + t / VR;
+            const bool in = qi >= 0 && qj >= 0 && qi < g.s2 && qj < g.s2;
+            const int64_t q = int64_t(qj) * g.s2 + qi;
+            s_rx[t] = in ? r[q] : T(0);
+            s_ry[t] = in ? r[g.nq2 + q] : T(0);
+        }
+    }
     const T rp = valid ? r[2 * g.nq2 + int64_t(J) * g.s1 + I] : T(0);
     __syncthreads();
-
     T rv[kSlots];
 #pragma unroll
     for (int b = 0; b < 5; ++b)
 #pragma unroll
         for (int a = 0; a < 5; ++a) {
             const int l = (2 * ty + b) * VR + 2 * tx + a;
-            rv[5 * b + a] = valid ? s_rx[l] : T(0);
-            rv[25 + 5 * b + a] = valid ? s_ry[l] : T(0);
+            rv[5 * b + a] = s_rx[l];
+            rv[25 + 5 * b + a] = s_ry[l];
         }
     rv[50] = rp;
-    const int cls = INTERIOR ? kInteriorClass
-                             : (valid ? 5 * dclass(J, g.N) + dclass(I, g.N) : kInteriorClass);
-    const T* __restrict__ M = Wall + cls * kSlots * kSlots;
 
-    T acc_x[VOWN_PER_THREAD], acc_y[VOWN_PER_THREAD];
+    sym_apply(table + kDenseTable, rv);  // interior inverse, every lane
+    const bool interior = valid && I >= 2 && J >= 2 && I <= g.N - 2 && J <= g.N - 2;
+    if (!interior) {
+        // boundary patch: corrections precomputed; outside the domain: none
+        const int bi = valid ? boundary_index(I, J, g.N) : 0;
 #pragma unroll
-    for (int k = 0; k < VOWN_PER_THREAD; ++k) acc_x[k] = acc_y[k] = T(0);
+        for (int s = 0; s < kSlots; ++s) rv[s] = valid ? dbuf[int64_t(bi) * 64 + s] : T(0);
+    }
+    __syncthreads();  // the staging buffer is reused for the exchange below
 
-    // Corrections are produced one patch row (5 nodes, both components) at a
-    // time, staged in LDS and pulled by the owners of the DoFs.
-#pragma unroll 1
-    for (int b = 0; b < 5; ++b) {
+    // x-sums within the 16-lane rows: column 2tx (even) and 2tx+1 (odd) of
+    // patch row slot b, both components; exchanged through LDS by b
+    T* xs = s_buf;  // 20 values per thread: [(b*2 + c)*2 + parity][thread]
 #pragma unroll
-        for (int a = 0; a < 5; ++a) {
-            const int sx = 5 * b + a, sy = 25 + 5 * b + a;
-            s_d[tid * 10 + a] = row_dot(M + sx * kSlots, rv);
-            s_d[tid * 10 + 5 + a] = row_dot(M + sy * kSlots, rv);
+    for (int b = 0; b < 5; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int o = 25 * c + 5 * b;
+            const T ev = rv[o + 4] + row_shl<1>(rv[o + 2]) + row_shl<2>(rv[o + 0]);
+            const T od = row_shl<1>(rv[o + 3]) + row_shl<2>(rv[o + 1]);
+            const int base = ((b * 2 + c) * 2) * VNT;
+            xs[base + threadIdx.x] = ev;
+            xs[base + VNT + threadIdx.x] = od;
         }
-        __syncthreads();
+    __syncthreads();
+    if (tx < VT && ty < VT) {
+        const int gi0 = 2 * E0x + 2 * tx, gj0 = 2 * E0y + 2 * ty;
 #pragma unroll
-        for (int k = 0; k < VOWN_PER_THREAD; ++k) {
-            const int q = tid + k * VNT;
-            if (q >= VOWN * VOWN) continue;
-            const int qa = q % VOWN, qb = q / VOWN;
-            if (((qb - b) & 1) != 0) continue;
-            const int pty = (qb - b) / 2 + 2;
-            if (qa & 1) {
+        for (int c = 0; c < 2; ++c)
 #pragma unroll
-                for (int a = 1; a < 5; a += 2) {
-                    const int ptx = (qa - a) / 2 + 2;
-                    acc_x[k] += s_d[(pty * VP + ptx) * 10 + a];
-                    acc_y[k] += s_d[(pty * VP + ptx) * 10 + 5 + a];
-                }
-            } else {
+            for (int px = 0; px < 2; ++px) {
+                auto at = [&](int b, int dty) {
+                    return xs[((b * 2 + c) * 2 + px) * VNT + threadIdx.x + dty * VP];
+                };
+                const T even_row = at(4, 0) + at(2, 1) + at(0, 2);
+                const T odd_row = at(3, 1) + at(1, 2);
+                const int gi = gi0 + px;
 #pragma unroll
-                for (int a = 0; a < 5; a += 2) {
-                    const int ptx = (qa - a) / 2 + 2;
-                    acc_x[k] += s_d[(pty * VP + ptx) * 10 + a];
-                    acc_y[k] += s_d[(pty * VP + ptx) * 10 + 5 + a];
+                for (int py = 0; py < 2; ++py) {
+                    const int gj = gj0 + py;
+                    if (gi <= 0 || gj <= 0 || gi >= g.s2 - 1 || gj >= g.s2 - 1) continue;
+                    x[int64_t(c) * g.nq2 + int64_t(gj) * g.s2 + gi] += py ? odd_row : even_row;
                 }
             }
-        }
-        __syncthreads();
-    }
-    const T dp = row_dot(M + 50 * kSlots, rv);
-#pragma unroll
-    for (int k = 0; k < VOWN_PER_THREAD; ++k) {
-        const int q = tid + k * VNT;
-        if (q >= VOWN * VOWN) continue;
-        const int gi = 2 * E0x + q % VOWN, gj = 2 * E0y + q / VOWN;
-        if (gi >= g.s2 - 1 || gj >= g.s2 - 1 || gi == 0 || gj == 0) continue;
-        const int64_t qq = int64_t(gj) * g.s2 + gi;
-        x[qq] += acc_x[k];
-        x[g.nq2 + qq] += acc_y[k];
     }
     if (valid && tx >= 1 && tx <= VT && ty >= 1 && ty <= VT)
-        x[2 * g.nq2 + int64_t(J) * g.s1 + I] += dp;
+        x[2 * g.nq2 + int64_t(J) * g.s1 + I] += rv[50];
 }
 
 // ---------------------------------------------------------------------------
@@ -653,7 +790,8 @@ int elementwise_blocks(int64_t n) {
 
 template <typename Tx, typename T>
 void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hipStream_t s) {
-    const dim3 grid((g.N + 1 + 15) / 16, (g.N + 1 + 15) / 16);
+    const int tiles = (g.N + 1 + RT - 1) / RT;
+    const int grid = 8 * ((tiles * tiles + 7) / 8);
     if (mode == 0)
         residual_kernel<0, Tx, T><<<grid, 256, 0, s>>>(g, b, x, r);
     else
@@ -669,17 +807,19 @@ void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hip
     rhs_kernel<<<grid, 256, 0, s>>>(g, f, gd, b);
 }
 
+int64_t vanka_boundary_scratch(int N) { return int64_t(n_boundary_patches(N)) * 64; }
+
 template <typename T>
-void launch_vanka_update(const Geom& g, const T* r, T* x, const T* Wall, hipStream_t s) {
-    const int tiles = (g.N + 1 + VT - 1) / VT;
-    const TileRange ir = interior_tiles(g.N);
-    const int ni = ir.hi - ir.lo;
-    if (ni > 0) vanka_update_kernel<T, true><<<dim3(ni, ni), VNT, 0, s>>>(g, r, x, Wall);
-    vanka_update_kernel<T, false><<<dim3(tiles, tiles), VNT, 0, s>>>(g, r, x, Wall);
+void launch_vanka_update(const Geom& g, const T* r, T* x, const T* table, T* dbuf,
+                         hipStream_t s) {
+    const int nb = n_boundary_patches(g.N);
+    vanka_boundary_kernel<T><<<(nb + 3) / 4, 256, 0, s>>>(g, r, table, dbuf);
+    const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
+    vanka_tile_kernel<T><<<8 * ((ntile + 7) / 8), VNT, 0, s>>>(g, r, x, table, dbuf);
 }
 template void launch_vanka_update<double>(const Geom&, const double*, double*, const double*,
-                                          hipStream_t);
-template void launch_vanka_update<float>(const Geom&, const float*, float*, const float*,
+                                          double*, hipStream_t);
+template void launch_vanka_update<float>(const Geom&, const float*, float*, const float*, float*,
                                          hipStream_t);
 
 template <typename T>

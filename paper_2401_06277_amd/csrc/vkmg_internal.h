@@ -53,4 +53,16 @@ void assemble_dense_level(int N, double nu, std::vector<double>& A);
 // constant-pressure vector; false if singular.
 bool coarse_bordered_inverse(int N, double nu, std::vector<double>& C);
 
+// Block-diagonal form of the interior weighted inverse W in the reflection-
+// adapted coordinates of symmetry.h (651 values, blocks concatenated
+// row-major).  Returns false if W does not commute with the reflections to
+// within `tol` relative to its largest entry.
+bool interior_symmetry_blocks(const double* W, double* B, double tol);
+
+// Per-level device table of patch operators: the 25 dense weighted inverses
+// (51 x 51 each) followed by the 651 reflection-block values of the
+// interior one.
+constexpr int kDenseTable = kClasses * kSlots * kSlots;
+constexpr int kLevelTable = kDenseTable + 651;
+
 }  // namespace vkmg

@@ -22,13 +22,14 @@ LIB = os.path.join(PKG, "libvkmg.so")
 
 HIP_SOURCES = ["kernels.hip", "api.hip"]
 HOST_SOURCES = ["host_setup.cpp"]
+GEN_DIR = os.path.join(BUILD, "gen")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Wno-unused-function", "-Wno-unknown-pragmas",
     # no packed FP32 VALU instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
+    "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-I" + GEN_DIR,
 ]
 GXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
@@ -50,8 +51,24 @@ def _run(cmd, verbose):
         sys.stdout.write(res.stdout + res.stderr)
 
 
+def generate_headers(verbose: bool = False) -> None:
+    """Compile and run the generator of the interior-operator constants."""
+    os.makedirs(GEN_DIR, exist_ok=True)
+    exe = os.path.join(BUILD, "gen_interior_blocks")
+    _run(["g++", *GXX_FLAGS, os.path.join(CSRC, "gen_interior_blocks.cpp"),
+          os.path.join(CSRC, "host_setup.cpp"), "-o", exe], verbose)
+    res = subprocess.run([exe], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"gen_interior_blocks failed with status {res.returncode}")
+    out = os.path.join(GEN_DIR, "interior_blocks.h")
+    with open(out + ".tmp", "w") as f:
+        f.write(res.stdout)
+    os.replace(out + ".tmp", out)
+
+
 def build(verbose: bool = False, extra_flags=None) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    generate_headers(verbose)
     hipcc = _hipcc()
     objs = []
     for src in HIP_SOURCES:

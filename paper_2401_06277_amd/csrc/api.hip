@@ -147,7 +147,7 @@ void sweep_t(vkmg_ctx* c, int l, T* x, const T* b, hipStream_t s) {
         launch_residual<T, T>(L.g, b, x, r, 0, s);
     }
     Timed t(c, VKMG_KERNEL_VANKA, s, l);
-    launch_vanka_update<T>(L.g, r, x, static_cast<const T*>(L.W), static_cast<T*>(L.dbuf), s);
+    launch_vanka_update<T>(L.g, r, x, static_cast<const T*>(L.W), static_cast<T*>(L.dbuf), c->opt.omega, s);
 }
 
 // MG(l, b) of Algorithm 1 with zero initial guess, result in x.
@@ -162,7 +162,7 @@ void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
             // x = 0, so the residual is b itself
             Timed t(c, VKMG_KERNEL_VANKA, s, l);
             launch_vanka_update<T>(L.g, b, x, static_cast<const T*>(L.W), static_cast<T*>(L.dbuf),
-                                   s);
+                                   c->opt.omega, s);
         } else {
             sweep_t<T>(c, l, x, b, s);
         }
@@ -325,6 +325,9 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         return fail(VKMG_ERR_INVALID_ARG, "setup: bad mg_precision");
 
     // host work first (no GPU needed to detect singular patches)
+    double B1[651];
+    if (!universal_interior_blocks(B1))
+        return fail(VKMG_ERR_SINGULAR_PATCH, "setup: universal interior operator failed");
     std::vector<std::vector<double>> Wh(levels);
     for (int l = 1; l < levels; ++l) {
         const int Nl = N >> (levels - 1 - l);
@@ -341,6 +344,11 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
                                       &Wh[l][kDenseTable], 1e-12))
             return fail(VKMG_ERR_SINGULAR_PATCH,
                         "setup: interior patch inverse is not reflection symmetric");
+        // the kernels apply the interior operator as the scaled universal one
+        const double mis = universal_mismatch(&Wh[l][kDenseTable], B1, o.omega, nu, 1.0 / Nl);
+        if (!(mis <= 1e-10))
+            return fail(VKMG_ERR_UNSUPPORTED,
+                        "setup: interior operator differs from the scaled universal form");
         // the device reads the dense inverses column by column: store W^T
         for (int c = 0; c < kClasses; ++c) {
             double* Wc = &Wh[l][size_t(c) * kSlots * kSlots];

@@ -323,4 +323,42 @@ bool interior_symmetry_blocks(const double* W, double* B, double tol) {
     return true;
 }
 
+bool universal_interior_blocks(double* B1) {
+    const int N = 8;
+    std::vector<double> A(kSlots * kSlots), inv;
+    uint8_t pres[kSlots];
+    if (!patch_matrix(N, 1.0, kInteriorClass, A.data(), pres)) return false;
+    if (!invert_dense(kSlots, A, inv)) return false;
+    // A1^{-1} = P8 A8^{-1} P8 with P8 = diag(I, 1/N): exact scalings by 2^-3
+    for (int i = 0; i < kSlots; ++i)
+        for (int j = 0; j < kSlots; ++j) {
+            double f = 1.0;
+            if (i == 50) f /= N;
+            if (j == 50) f /= N;
+            inv[i * kSlots + j] *= f;
+        }
+    std::vector<double> W(kSlots * kSlots);
+    weighted_inverse(N, kInteriorClass, 1.0, inv.data(), pres, W.data());
+    return interior_symmetry_blocks(W.data(), B1, 1e-12);
+}
+
+double universal_mismatch(const double* Blevel, const double* B1, double omega, double nu,
+                          double h) {
+    const double scale = omega / nu, t = nu / h;
+    double err = 0.0, ref = 0.0;
+    for (int blk = 0; blk < kSymBlocks; ++blk) {
+        const int n = sym_block_size(blk), off = sym_block_offset(blk);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double f = scale;
+                if (sym_member(blk, i) == 50) f *= t;
+                if (sym_member(blk, j) == 50) f *= t;
+                const double want = f * B1[off + i * n + j];
+                err = std::max(err, std::fabs(Blevel[off + i * n + j] - want));
+                ref = std::max(ref, std::fabs(Blevel[off + i * n + j]));
+            }
+    }
+    return err / ref;
+}
+
 }  // namespace vkmg

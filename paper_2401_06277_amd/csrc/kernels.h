@@ -19,10 +19,11 @@ void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hip
 // One Vanka update given the residual r of x: x += sum_i V_i^T W_i A_i^{-1} V_i r.
 // `table` is the level's patch-operator table (kLevelTable values: the 25
 // weighted inverses stored transposed, then the interior reflection
-// blocks); `dbuf` is scratch for the boundary patches
+// blocks, which the kernels take from compile-time constants instead);
+// `dbuf` is scratch for the boundary patches
 // (vanka_boundary_scratch(N) values).
 template <typename T>
-void launch_vanka_update(const Geom& g, const T* r, T* x, const T* table, T* dbuf,
+void launch_vanka_update(const Geom& g, const T* r, T* x, const T* table, T* dbuf, double omega,
                          hipStream_t s);
 int64_t vanka_boundary_scratch(int N);
 

@@ -6,6 +6,7 @@
 
 #include "kernels.h"
 #include "stencil.h"
+#include "interior_blocks.h"
 #include "symmetry.h"
 
 namespace vkmg {
@@ -269,9 +270,12 @@ __device__ __forceinline__ void bfly_t(T (&v)[kSlots], int o, int st) {
     v[o + 4 * st] = e0 - o0;
 }
 
-// v <- W v for the interior weighted inverse W = U^T B U (symmetry.h), in place.
+// v <- D W1 D v in place, for the universal interior operator W1 (compile-
+// time constants, symmetry.h blocks) and D = diag(I, t) applied to the
+// pressure output here; the caller scales the input (velocity by
+// omega/nu, pressure by t omega/nu with t = nu/h).
 template <typename T>
-__device__ __forceinline__ void sym_apply(const T* __restrict__ B, T (&v)[kSlots]) {
+__device__ __forceinline__ void sym_apply(T (&v)[kSlots], T t) {
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
 #pragma unroll
@@ -283,7 +287,7 @@ __device__ __forceinline__ void sym_apply(const T* __restrict__ B, T (&v)[kSlots
     for (int blk = 0; blk < kSymBlocks; ++blk) {
         constexpr int nmax = 13;
         const int n = sym_block_size(blk);
-        const T* __restrict__ Bb = B + sym_block_offset(blk);
+        const int off = sym_block_offset(blk);
         T y[nmax];
 #pragma unroll
         for (int i = 0; i < nmax; ++i) {
@@ -292,10 +296,11 @@ __device__ __forceinline__ void sym_apply(const T* __restrict__ B, T (&v)[kSlots
 #pragma unroll
             for (int j = 0; j < nmax; ++j) {
                 if (j >= n) break;
+                const T c = T(kInteriorW1[off + i * n + j]);
                 if (j & 1)
-                    a1 += Bb[i * n + j] * v[kSymTable.m[blk][j]];
+                    a1 += c * v[kSymTable.m[blk][j]];
                 else
-                    a0 += Bb[i * n + j] * v[kSymTable.m[blk][j]];
+                    a0 += c * v[kSymTable.m[blk][j]];
             }
             y[i] = a0 + a1;
         }
@@ -305,6 +310,7 @@ __device__ __forceinline__ void sym_apply(const T* __restrict__ B, T (&v)[kSlots
             v[kSymTable.m[blk][i]] = y[i];
         }
     }
+    v[50] *= t;
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
 #pragma unroll
@@ -417,8 +423,8 @@ __host__ __device__ inline int vanka_tiles(int N) { return (N + 1 + VT - 1) / VT
 template <typename T>
 __global__ __launch_bounds__(VNT, 2) void vanka_tile_kernel(Geom g, const T* __restrict__ r,
                                                             T* __restrict__ x,
-                                                            const T* __restrict__ table,
-                                                            const T* __restrict__ dbuf) {
+                                                            const T* __restrict__ dbuf,
+                                                            T scale, T t) {
     // staging of the residual region (2 VR^2 values), reused for the
     // exchange of the x-sums (20 values per thread)
     __shared__ T s_buf[20 * VNT];
@@ -444,11 +450,11 @@ __global__ __launch_bounds__(VNT, 2) void vanka_tile_kernel(Geom g, const T* __r
             const int qi = ox + t % VR, qj = oy + t / VR;
             const bool in = qi >= 0 && qj >= 0 && qi < g.s2 && qj < g.s2;
             const int64_t q = int64_t(qj) * g.s2 + qi;
-            s_rx[t] = in ? r[q] : T(0);
-            s_ry[t] = in ? r[g.nq2 + q] : T(0);
+            s_rx[t] = in ? scale * r[q] : T(0);
+            s_ry[t] = in ? scale * r[g.nq2 + q] : T(0);
         }
     }
-    const T rp = valid ? r[2 * g.nq2 + int64_t(J) * g.s1 + I] : T(0);
+    const T rp = valid ? (scale * t) * r[2 * g.nq2 + int64_t(J) * g.s1 + I] : T(0);
     __syncthreads();
     T rv[kSlots];
 #pragma unroll
@@ -461,7 +467,7 @@ __global__ __launch_bounds__(VNT, 2) void vanka_tile_kernel(Geom g, const T* __r
         }
     rv[50] = rp;
 
-    sym_apply(table + kDenseTable, rv);  // interior inverse, every lane
+    sym_apply(rv, t);  // interior operator, every lane
     const bool interior = valid && I >= 2 && J >= 2 && I <= g.N - 2 && J <= g.N - 2;
     if (!interior) {
         // boundary patch: corrections precomputed; outside the domain: none
@@ -810,17 +816,18 @@ void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hip
 int64_t vanka_boundary_scratch(int N) { return int64_t(n_boundary_patches(N)) * 64; }
 
 template <typename T>
-void launch_vanka_update(const Geom& g, const T* r, T* x, const T* table, T* dbuf,
+void launch_vanka_update(const Geom& g, const T* r, T* x, const T* table, T* dbuf, double omega,
                          hipStream_t s) {
     const int nb = n_boundary_patches(g.N);
     vanka_boundary_kernel<T><<<(nb + 3) / 4, 256, 0, s>>>(g, r, table, dbuf);
     const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
-    vanka_tile_kernel<T><<<8 * ((ntile + 7) / 8), VNT, 0, s>>>(g, r, x, table, dbuf);
+    vanka_tile_kernel<T><<<8 * ((ntile + 7) / 8), VNT, 0, s>>>(g, r, x, dbuf, T(omega / g.nu),
+                                                               T(g.nu / g.h));
 }
 template void launch_vanka_update<double>(const Geom&, const double*, double*, const double*,
-                                          double*, hipStream_t);
+                                          double*, double, hipStream_t);
 template void launch_vanka_update<float>(const Geom&, const float*, float*, const float*, float*,
-                                         hipStream_t);
+                                         double, hipStream_t);
 
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, hipStream_t s) {

@@ -59,6 +59,15 @@ bool coarse_bordered_inverse(int N, double nu, std::vector<double>& C);
 // within `tol` relative to its largest entry.
 bool interior_symmetry_blocks(const double* W, double* B, double tol);
 
+// Reflection blocks of the universal interior operator W1 (mesh size 1,
+// unit viscosity, unit damping); the operator of a level with mesh size h,
+// viscosity nu and damping omega is (omega/nu) D W1 D, D = diag(I, nu/h).
+bool universal_interior_blocks(double* B1);
+// Largest deviation of a level's blocks from that scaled universal form,
+// relative to the largest block entry.
+double universal_mismatch(const double* Blevel, const double* B1, double omega, double nu,
+                          double h);
+
 // Per-level device table of patch operators: the 25 dense weighted inverses
 // (51 x 51 each) followed by the 651 reflection-block values of the
 // interior one.

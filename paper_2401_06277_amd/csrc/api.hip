@@ -223,9 +223,13 @@ vkmg_status norm_sync(vkmg_ctx* c, const double* w, double* out, hipStream_t s) 
     return VKMG_OK;
 }
 
+// Basis vectors are stored with a stride rounded up to 64 doubles (512 B),
+// so that every vector starts on a cache-line boundary.
+int64_t basis_stride(int64_t n) { return (n + 63) / 64 * 64; }
+
 vkmg_status ensure_basis(vkmg_ctx* c, int m) {
     if (m <= c->basis_cap) return VKMG_OK;
-    const int64_t n = c->top().n;
+    const int64_t n = basis_stride(c->top().n);
     // release the old basis (kept in the allocation list until destroy otherwise)
     for (void* p : {static_cast<void*>(c->V), static_cast<void*>(c->Z)}) {
         if (!p) continue;
@@ -400,7 +404,7 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
     const int64_t n = c->top().n;
     if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->r64), 8 * n);
     if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->w64), 8 * n);
-    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->part), 8 * size_t(kDotBlocks) * 260);
+    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->part), 8 * size_t(kDotBlocks) * 264);
     if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->hdev), 8 * kHostScratch);
     if (st == VKMG_OK) {
         hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->hhost), 8 * kHostScratch, hipHostMallocDefault);
@@ -565,7 +569,7 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
     if (st != VKMG_OK) return st;
     const Geom& g = ctx->top();
     const int64_t n = g.n;
-    const int64_t ld = n;
+    const int64_t ld = basis_stride(n);
     const int m = restart;
     double* r = ctx->r64;
     double* w = ctx->w64;
@@ -620,40 +624,64 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
                 Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
                 launch_residual<double, double>(g, nullptr, zj, w, 1, s);
             }
-            // classical Gram-Schmidt, twice; the second update also forms ||w||^2
-            dots_async(ctx, V, ld, j + 1, w, h1, s);
-            {
-                Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
-                launch_update(V, ld, j + 1, h1, w, n, nullptr, s);
+            // classical Gram-Schmidt, twice (Giraud et al.'s CGS2):
+            //   h1 = V^T w;  w' = w - V h1 with h2 = V^T w' and |w'|^2 in the
+            //   same pass;  v_{j+1} = (w' - V h2) / |w' - V h2| in a third,
+            //   with |w' - V h2|^2 = |w'|^2 - |h2|^2 (V orthonormal).
+            const int kb = j + 1;  // basis vectors so far
+            bool normalized = false;
+            double hnext = 0.0;
+            dots_async(ctx, V, ld, kb, w, h1, s);
+            if (kb <= 32) {
+                {
+                    Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+                    launch_update_dot(V, ld, kb, h1, w, n, ctx->part, s);
+                    launch_reduce_partials(ctx->part, kb + 1, h2, s);
+                    launch_normalize(V, ld, kb, h2, h2 + kb, w, V + int64_t(kb) * ld, n, s);
+                }
+                normalized = true;
+            } else {
+                {
+                    Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+                    launch_update(V, ld, kb, h1, w, n, s);
+                }
+                dots_async(ctx, V, ld, kb, w, h2, s);
+                {
+                    Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+                    launch_update(V, ld, kb, h2, w, n, s);
+                }
+                dots_async(ctx, w, 0, 1, w, h2 + kb, s);
             }
-            dots_async(ctx, V, ld, j + 1, w, h2, s);
-            {
-                Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
-                launch_update(V, ld, j + 1, h2, w, n, ctx->part, s);
-                launch_reduce_partials(ctx->part, 1, h2 + (j + 1), s);
-            }
-            VKMG_HIP(hipMemcpyAsync(ctx->hhost, h1, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-            VKMG_HIP(hipMemcpyAsync(ctx->hhost + 300, h2, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s));
+            VKMG_HIP(hipMemcpyAsync(ctx->hhost, h1, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
+            VKMG_HIP(hipMemcpyAsync(ctx->hhost + 300, h2, sizeof(double) * (kb + 1), hipMemcpyDeviceToHost, s));
             VKMG_HIP(hipStreamSynchronize(s));
             bool finite = true;
+            double hh = 0.0;
             for (int i = 0; i <= j; ++i) {
                 Hij(i, j) = ctx->hhost[i] + ctx->hhost[300 + i];
                 finite = finite && std::isfinite(Hij(i, j));
+                hh += ctx->hhost[300 + i] * ctx->hhost[300 + i];
             }
-            Hij(j + 1, j) = std::sqrt(ctx->hhost[300 + j + 1]);
-            if (!finite || !std::isfinite(Hij(j + 1, j)))
+            if (normalized) {
+                // the formula of the normalisation kernel
+                const double d = ctx->hhost[300 + kb] - hh;
+                hnext = d > 0.0 ? std::sqrt(d) : 0.0;
+            } else {
+                hnext = std::sqrt(ctx->hhost[300 + kb]);
+            }
+            Hij(j + 1, j) = hnext;
+            if (!finite || !std::isfinite(hnext))
                 return finish(VKMG_ERR_NONFINITE, total, restarts, NAN, NAN);
             for (int i = 0; i < j; ++i) {
                 const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
                 Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
                 Hij(i, j) = t;
             }
-            const double hnext = Hij(j + 1, j);
             const double denom = std::hypot(Hij(j, j), hnext);
             cs[j] = Hij(j, j) / denom;
             sn[j] = hnext / denom;
             const bool breakdown = hnext == 0.0;
-            if (!breakdown) {
+            if (!breakdown && !normalized) {
                 Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
                 launch_scale(w, 1.0 / hnext, V + int64_t(j + 1) * ld, n, s);
             }

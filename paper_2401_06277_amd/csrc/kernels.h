@@ -44,15 +44,22 @@ template <typename Ti, typename To>
 void launch_cast(const Ti* in, To* out, int64_t n, hipStream_t s);
 
 // Krylov kernels (FP64).  V: k vectors of length n with stride ldv.
-constexpr int kDotBlocks = 512;
+constexpr int kDotBlocks = 2048;
 // part[v * kDotBlocks + blk] = partial dot of V_v and w
 void launch_mdot_partial(const double* V, int64_t ldv, int k, const double* w, int64_t n,
                          double* part, hipStream_t s);
 // out[v] = sum of the kDotBlocks partials of vector v (k vectors)
 void launch_reduce_partials(const double* part, int k, double* out, hipStream_t s);
-// w -= sum_v h[v] V_v ; if part != nullptr also part[blk] = partial ||w_new||^2
+// w -= sum_v h[v] V_v
 void launch_update(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n,
-                   double* part, hipStream_t s);
+                   hipStream_t s);
+// w -= sum_v h[v] V_v, then partials of V^T w (k values) and ||w||^2 (one
+// more) into part; k <= 32
+void launch_update_dot(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n,
+                       double* part, hipStream_t s);
+// out = (w - V h2) / sqrt(nrm2[0] - |h2|^2); k <= 32
+void launch_normalize(const double* V, int64_t ldv, int k, const double* h2, const double* nrm2,
+                      const double* w, double* out, int64_t n, hipStream_t s);
 // x += sum_v y[v] Z_v
 void launch_axpy_multi(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t n,
                        hipStream_t s);

@@ -739,15 +739,87 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
     if (threadIdx.x == 0) out[v] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// w <- w - V h; part[v * G + blk] = partial of V_v . w_new (v < k) and
+// part[k * G + blk] = partial of ||w_new||^2, G = gridDim.x.
+template <int KMAX>
+__global__ __launch_bounds__(256) void update_dot_kernel(const double* __restrict__ V,
+                                                         int64_t ldv, int k,
+                                                         const double* __restrict__ h,
+                                                         double* __restrict__ w, int64_t n,
+                                                         double* __restrict__ part) {
+    double hv[KMAX], acc[KMAX];
+#pragma unroll
+    for (int v = 0; v < KMAX; ++v) {
+        hv[v] = v < k ? h[v] : 0.0;
+        acc[v] = 0.0;
+    }
+    double nrm = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * 256) {
+        double vv[KMAX];
+#pragma unroll
+        for (int v = 0; v < KMAX; ++v) vv[v] = v < k ? V[v * ldv + i] : 0.0;
+        double s = w[i];
+#pragma unroll
+        for (int v = 0; v < KMAX; ++v) s -= hv[v] * vv[v];
+        w[i] = s;
+        nrm += s * s;
+#pragma unroll
+        for (int v = 0; v < KMAX; ++v) acc[v] += vv[v] * s;
+    }
+    __shared__ double red[KMAX + 1][4];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < KMAX; ++v) {
+        const double t = wave_sum(acc[v]);
+        if (lane == 0) red[v][wv] = t;
+    }
+    const double tn = wave_sum(nrm);
+    if (lane == 0) red[KMAX][wv] = tn;
+    __syncthreads();
+    if (threadIdx.x <= k) {
+        const int v = threadIdx.x < k ? threadIdx.x : KMAX;
+        part[int64_t(threadIdx.x) * gridDim.x + blockIdx.x] =
+            (red[v][0] + red[v][1]) + (red[v][2] + red[v][3]);
+    }
+}
+
+// out = (w - V h2) / sqrt(nrm2 - |h2|^2): the second Gram-Schmidt
+// correction fused with the normalisation (|w - V h2|^2 = nrm2 - |h2|^2 for
+// orthonormal V and h2 = V^T w).  Writes zeros if the norm vanishes.
+template <int KMAX>
+__global__ __launch_bounds__(256) void normalize_kernel(const double* __restrict__ V, int64_t ldv,
+                                                        int k, const double* __restrict__ h2,
+                                                        const double* __restrict__ nrm2,
+                                                        const double* __restrict__ w,
+                                                        double* __restrict__ out, int64_t n) {
+    double hv[KMAX];
+    double hh = 0.0;
+#pragma unroll
+    for (int v = 0; v < KMAX; ++v) {
+        hv[v] = v < k ? h2[v] : 0.0;
+        hh += hv[v] * hv[v];
+    }
+    const double d = nrm2[0] - hh;
+    const double scale = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * 256) {
+        double s = w[i];
+#pragma unroll
+        for (int v = 0; v < KMAX; ++v)
+            if (v < k) s -= hv[v] * V[v * ldv + i];
+        out[i] = s * scale;
+    }
+}
+
+// w <- w - V h (no reduction)
 template <int KMAX>
 __global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ V, int64_t ldv,
                                                      int k, const double* __restrict__ h,
-                                                     double* __restrict__ w, int64_t n,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ w, int64_t n) {
     double hv[KMAX];
 #pragma unroll
     for (int v = 0; v < KMAX; ++v) hv[v] = v < k ? h[v] : 0.0;
-    double nrm = 0.0;
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * 256) {
         double s = w[i];
@@ -755,14 +827,6 @@ __global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ 
         for (int v = 0; v < KMAX; ++v)
             if (v < k) s -= hv[v] * V[v * ldv + i];
         w[i] = s;
-        nrm += s * s;
-    }
-    if (part != nullptr) {
-        __shared__ double red[4];
-        nrm = wave_sum(nrm);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
-        __syncthreads();
-        if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
     }
 }
 
@@ -899,12 +963,21 @@ void launch_reduce_partials(const double* part, int k, double* out, hipStream_t 
 }
 
 void launch_update(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n,
-                   double* part, hipStream_t s) {
+                   hipStream_t s) {
     for (int c0 = 0; c0 < k; c0 += kChunk) {
         const int kc = k - c0 < kChunk ? k - c0 : kChunk;
-        double* pp = (c0 + kc >= k) ? part : nullptr;  // norm after the last chunk
-        VKMG_KDISPATCH(kc, update_kernel, V + c0 * ldv, ldv, kc, h + c0, w, n, pp);
+        VKMG_KDISPATCH(kc, update_kernel, V + c0 * ldv, ldv, kc, h + c0, w, n);
     }
+}
+
+void launch_update_dot(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n,
+                       double* part, hipStream_t s) {
+    VKMG_KDISPATCH(k, update_dot_kernel, V, ldv, k, h, w, n, part);
+}
+
+void launch_normalize(const double* V, int64_t ldv, int k, const double* h2, const double* nrm2,
+                      const double* w, double* out, int64_t n, hipStream_t s) {
+    VKMG_KDISPATCH(k, normalize_kernel, V, ldv, k, h2, nrm2, w, out, n);
 }
 
 void launch_axpy_multi(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t n,

@@ -33,6 +33,25 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def measured_traffic():
+    """HBM bytes per finest-level Vanka update measured with rocprofv3 byte
+    counters (profiles/vanka_update_traffic.json), or None if the kernel
+    source has changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "vanka_update_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        with open(os.path.join(ROOT, d["source"]), "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if h != d.get("kernel_source_sha256"):
+        return None
+    return float(d["read_bytes"] + d["write_bytes"])
 
 
 def parse():
@@ -48,7 +67,22 @@ def parse():
     ap.add_argument("--cpu-levels", type=int, default=6)
     ap.add_argument("--cpu-vcycles", type=int, default=5)
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB "
+                         "(3 times) and exit: the reference kernel for scaling HBM "
+                         "byte counters")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8}))
 
 
 def log(msg):
@@ -90,6 +124,9 @@ def cpu_baseline(N, levels, nvc):
 
 def main():
     a = parse()
+    if a.copy_calibration_mib:
+        copy_calibration(a.copy_calibration_mib)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
                                    "not supported (use --gpus 1)"}))
@@ -194,7 +231,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "launches": nl,
             "avg_launch_us": avg_launch_s * 1e6,
             "alg_bytes_per_launch": alg_bytes,

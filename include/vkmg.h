@@ -192,8 +192,10 @@ vkmg_status vkmg_vcycle(vkmg_ctx* ctx, const double* r, double* z, void* stream)
  * residual estimate and then the recomputed residual satisfy
  * ||b - A x|| <= rtol ||b - A x0||; restarts every `restart` steps
  * (1..256); at most max_iters Arnoldi steps (>= 1).  Returns VKMG_OK,
- * VKMG_ERR_NOT_CONVERGED (x is the last iterate) or VKMG_ERR_NONFINITE;
- * `info` (may be NULL) is filled in every case.
+ * VKMG_ERR_NOT_CONVERGED (x is the last iterate: max_iters reached, or a
+ * restart cycle whose estimate met rtol left the recomputed residual above
+ * it and not halved, i.e. rtol is below the rounding floor of the system)
+ * or VKMG_ERR_NONFINITE; `info` (may be NULL) is filled in every case.
  */
 vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double rtol,
                               int32_t restart, int32_t max_iters, vkmg_info* info, void* stream);

@@ -311,6 +311,69 @@ def stokes_system(N: int, nu=1.0, f_nodal=None, g_nodal=None, b_load=None):
 
 
 # ----------------------------------------------------------------------------
+# Rows of the constrained operator one by one (for sampled checks on meshes
+# too large to assemble)
+# ----------------------------------------------------------------------------
+
+def residual_rows(N: int, x: np.ndarray, b: np.ndarray, rows, nu: float = 1.0) -> np.ndarray:
+    """(b - A x)[rows] for the Dirichlet-eliminated operator, each row summed
+    over the element matrices of the elements that contain its DoF (the
+    definition of assembly); Dirichlet columns are dropped and Dirichlet rows
+    are identity rows."""
+    g = grid_sizes(N)
+    h = 1.0 / N
+    E = element_matrices(h)
+    s2, s1 = g.q2_side, g.q1_side
+    out = np.empty(len(rows))
+
+    def q2_free(qi, qj):
+        return 0 < qi < s2 - 1 and 0 < qj < s2 - 1
+
+    for n_, row in enumerate(rows):
+        row = int(row)
+        acc = 0.0
+        if row < g.off_p:
+            f = row // g.n_q2
+            node = row % g.n_q2
+            qi, qj = node % s2, node // s2
+            if not q2_free(qi, qj):
+                out[n_] = b[row] - x[row]
+                continue
+            off = g.off_ux if f == 0 else g.off_uy
+            Bk = E["Bx"] if f == 0 else E["By"]
+            for ey in range((qj - 1) // 2, qj // 2 + 1):
+                for ex in range((qi - 1) // 2, qi // 2 + 1):
+                    if not (0 <= ex < N and 0 <= ey < N):
+                        continue
+                    li = (qj - 2 * ey) * 3 + (qi - 2 * ex)
+                    for bb in range(3):
+                        for aa in range(3):
+                            cj, ci = 2 * ey + bb, 2 * ex + aa
+                            if q2_free(ci, cj):
+                                acc += nu * E["L"][li, bb * 3 + aa] * x[off + cj * s2 + ci]
+                    for d in range(2):
+                        for c in range(2):
+                            acc += Bk[d * 2 + c, li] * x[g.off_p + (ey + d) * s1 + ex + c]
+        else:
+            node = row - g.off_p
+            I, J = node % s1, node // s1
+            for ey in (J - 1, J):
+                for ex in (I - 1, I):
+                    if not (0 <= ex < N and 0 <= ey < N):
+                        continue
+                    lk = (J - ey) * 2 + (I - ex)
+                    for bb in range(3):
+                        for aa in range(3):
+                            cj, ci = 2 * ey + bb, 2 * ex + aa
+                            if q2_free(ci, cj):
+                                q = cj * s2 + ci
+                                acc += E["Bx"][lk, bb * 3 + aa] * x[g.off_ux + q]
+                                acc += E["By"][lk, bb * 3 + aa] * x[g.off_uy + q]
+        out[n_] = b[row] - acc
+    return out
+
+
+# ----------------------------------------------------------------------------
 # Null space and errors
 # ----------------------------------------------------------------------------
 

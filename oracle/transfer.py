@@ -62,3 +62,51 @@ def prolongation(nc: int) -> sp.csr_matrix:
     P.eliminate_zeros()
     assert P.shape == (grid_sizes(2 * nc).n, grid_sizes(nc).n)
     return P
+
+
+def prolong_rows(nc: int, ec: np.ndarray, rows) -> np.ndarray:
+    """(P ec)[rows] computed row by row from the 1D interpolation matrices
+    (the tensor-product definition of P), for meshes too large to assemble
+    P.  Same Dirichlet reading as ``prolongation``."""
+    return _tensor_rows(nc, ec, rows, transpose=False)
+
+
+def restrict_rows(nc: int, rf: np.ndarray, rows) -> np.ndarray:
+    """(P^T rf)[rows] for coarse rows, computed one coarse DoF at a time."""
+    return _tensor_rows(nc, rf, rows, transpose=True)
+
+
+def _tensor_rows(nc, v, rows, transpose):
+    gf, gc = grid_sizes(2 * nc), grid_sizes(nc)
+    fmask = velocity_dirichlet_mask(2 * nc)
+    cmask = velocity_dirichlet_mask(nc)
+    P1d = {2: interpolation_1d(nc, 2), 1: interpolation_1d(nc, 1)}
+    out = np.empty(len(rows))
+    for n_, row in enumerate(rows):
+        row = int(row)
+        g_out, g_in = (gc, gf) if transpose else (gf, gc)
+        m_out, m_in = (cmask, fmask) if transpose else (fmask, cmask)
+        if m_out[row]:
+            out[n_] = 0.0
+            continue
+        if row < g_out.off_p:
+            deg, f = 2, row // g_out.n_q2
+            node = row % g_out.n_q2
+            side_out, side_in = g_out.q2_side, g_in.q2_side
+            off_in = g_in.off_ux if f == 0 else g_in.off_uy
+        else:
+            deg, node = 1, row - g_out.off_p
+            side_out, side_in = g_out.q1_side, g_in.q1_side
+            off_in = g_in.off_p
+        i, j = node % side_out, node // side_out
+        M = P1d[deg].T if transpose else P1d[deg]
+        ci = np.nonzero(M[i])[0]
+        cj = np.nonzero(M[j])[0]
+        acc = 0.0
+        for jj in cj:
+            for ii in ci:
+                k = off_in + jj * side_in + ii
+                if not m_in[k]:
+                    acc += M[j, jj] * M[i, ii] * v[k]
+        out[n_] = acc
+    return out

@@ -109,6 +109,106 @@ def patch_inverses(A: sp.csr_matrix, N: int, shared: bool):
     return inv, cls
 
 
+def local_patch_matrix(N: int, I: int, J: int, nu: float = 1.0):
+    """V_i A V_i^T for the patch at Q1 node (I, J) of an N x N mesh without
+    assembling the global matrix: the entries between patch DoFs summed over
+    the element matrices of every element that touches the patch, then the
+    Dirichlet DoFs eliminated (identity rows and columns).  Returns the dense
+    matrix on the present slots and the patch's global DoF indices."""
+    from .fem import element_matrices
+    g = grid_sizes(N)
+    s2, s1 = g.q2_side, g.q1_side
+    E = element_matrices(1.0 / N)
+    dofs = patch_dofs_one(N, I, J)
+    present = np.nonzero(dofs >= 0)[0]
+    S = dofs[present]
+    pos = {int(d): k for k, d in enumerate(S)}
+    A = np.zeros((len(S), len(S)))
+    for ey in range(max(0, J - 2), min(N, J + 2)):
+        for ex in range(max(0, I - 2), min(N, I + 2)):
+            q2 = [(2 * ey + bb) * s2 + 2 * ex + aa for bb in range(3) for aa in range(3)]
+            q1 = [(ey + d) * s1 + ex + c for d in range(2) for c in range(2)]
+            for f, Bk in ((0, E["Bx"]), (1, E["By"])):
+                off = g.off_ux if f == 0 else g.off_uy
+                for a_ in range(9):
+                    ia = pos.get(off + q2[a_])
+                    if ia is None:
+                        continue
+                    for b_ in range(9):
+                        ib = pos.get(off + q2[b_])
+                        if ib is not None:
+                            A[ia, ib] += nu * E["L"][a_, b_]
+                    for k in range(4):
+                        ip = pos.get(g.off_p + q1[k])
+                        if ip is not None:
+                            A[ip, ia] += Bk[k, a_]
+                            A[ia, ip] += Bk[k, a_]
+    for k, d in enumerate(S):
+        if d < g.off_p:
+            node = d % g.n_q2
+            qi, qj = node % s2, node // s2
+            if qi == 0 or qj == 0 or qi == s2 - 1 or qj == s2 - 1:
+                A[k, :] = 0.0
+                A[:, k] = 0.0
+                A[k, k] = 1.0
+    return A, S
+
+
+def patch_dofs_one(N: int, I: int, J: int) -> np.ndarray:
+    """The 51-slot DoF list of the patch at Q1 node (I, J), -1 = absent."""
+    g = grid_sizes(N)
+    s2 = g.q2_side
+    idx = -np.ones(PATCH_SLOTS, dtype=np.int64)
+    for b in range(5):
+        for a in range(5):
+            qi, qj = 2 * I - 2 + a, 2 * J - 2 + b
+            if 0 <= qi < s2 and 0 <= qj < s2:
+                idx[b * 5 + a] = g.off_ux + qj * s2 + qi
+                idx[25 + b * 5 + a] = g.off_uy + qj * s2 + qi
+    idx[50] = g.off_p + J * (N + 1) + I
+    return idx
+
+
+def sampled_sweep_update(N: int, x: np.ndarray, b: np.ndarray, dofs, omega: float = 0.5,
+                         nu: float = 1.0) -> np.ndarray:
+    """The change one additive sweep makes at the given DoFs, computed one DoF
+    at a time: sum over the patches i containing DoF j of
+    (omega/m_j) (A_i^{-1} V_i r)_j, with r from residual_rows and A_i from
+    local_patch_matrix (for meshes too large to assemble).  Dirichlet DoFs do
+    not change."""
+    from .fem import residual_rows
+    g = grid_sizes(N)
+    s2 = g.q2_side
+    inv_cache = {}
+    out = np.zeros(len(dofs))
+    for n_, d in enumerate(dofs):
+        d = int(d)
+        if d < g.off_p:
+            node = d % g.n_q2
+            qi, qj = node % s2, node // s2
+            if qi == 0 or qj == 0 or qi == s2 - 1 or qj == s2 - 1:
+                continue
+            Is = [I for I in range((qi - 1) // 2, qi // 2 + 2) if abs(2 * I - qi) <= 2 and 0 <= I <= N]
+            Js = [J for J in range((qj - 1) // 2, qj // 2 + 2) if abs(2 * J - qj) <= 2 and 0 <= J <= N]
+            patches = [(I, J) for J in Js for I in Is]
+        else:
+            node = d - g.off_p
+            patches = [(node % (N + 1), node // (N + 1))]
+        total = 0.0
+        for I, J in patches:
+            key = (int(distance_class(np.array(I), N)), int(distance_class(np.array(J), N)))
+            if key not in inv_cache:
+                Ak, _ = local_patch_matrix(N, I, J, nu)
+                inv_cache[key] = np.linalg.inv(Ak)
+            S = patch_dofs_one(N, I, J)
+            S = S[S >= 0]
+            r = residual_rows(N, x, b, S, nu)
+            pos = int(np.nonzero(S == d)[0][0])
+            total += inv_cache[key][pos] @ r
+        out[n_] = omega / len(patches) * total
+    return out
+
+
 def multiplicities(N: int) -> np.ndarray:
     """m_j = number of patches containing DoF j, counted by brute force."""
     idx = patch_dofs(N)

@@ -40,6 +40,7 @@ struct LevelBuf {
     void* x = nullptr;  // MG precision
     void* b = nullptr;
     void* r = nullptr;
+    void* xt = nullptr;    // second iterate buffer for the fused sweeps (relaxed levels)
     void* W = nullptr;     // patch-operator table, MG precision (relaxed levels)
     void* dbuf = nullptr;  // boundary-patch corrections (relaxed levels)
 };
@@ -138,39 +139,43 @@ vkmg_layout layout_of_geom(const Geom& g) {
 
 // ------------------------------------------------------------------ MG steps
 
+// One fused sweep x_out = S(x_in) on level l (x_in == nullptr: x_in = 0).
 template <typename T>
-void sweep_t(vkmg_ctx* c, int l, T* x, const T* b, hipStream_t s) {
+void fused_sweep_t(vkmg_ctx* c, int l, const T* b, const T* xin, T* xout, hipStream_t s) {
     LevelBuf& L = c->lev[l];
-    T* r = static_cast<T*>(L.r);
-    {
-        Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
-        launch_residual<T, T>(L.g, b, x, r, 0, s);
-    }
     Timed t(c, VKMG_KERNEL_VANKA, s, l);
-    launch_vanka_update<T>(L.g, r, x, static_cast<const T*>(L.W), static_cast<T*>(L.dbuf), c->opt.omega, s);
+    launch_vanka_sweep<T>(L.g, b, xin, xout, static_cast<const T*>(L.W), static_cast<T*>(L.dbuf),
+                          c->opt.omega, s);
 }
 
-// MG(l, b) of Algorithm 1 with zero initial guess, result in x.
+// MG(l, b) of Algorithm 1 with zero initial guess, result in x.  The sweeps
+// alternate between x and the level's second buffer (a fused sweep reads x
+// with a halo, so it cannot update in place); the first target is chosen so
+// that the last sweep writes x.
 template <typename T>
 void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
     LevelBuf& L = c->lev[l];
     LevelBuf& Lc = c->lev[l - 1];
     T* r = static_cast<T*>(L.r);
-    launch_fill_zero<T>(x, L.g.n, s);
+    T* xt = static_cast<T*>(L.xt);
+    const int total = c->opt.nu_pre + c->opt.nu_post;
+    const T* cur = nullptr;  // current iterate; nullptr while it is zero
+    auto next = [&](void) -> T* {
+        if (cur == nullptr) return (total % 2 == 1) ? x : xt;
+        return cur == x ? xt : x;
+    };
     for (int i = 0; i < c->opt.nu_pre; ++i) {
-        if (i == 0) {
-            // x = 0, so the residual is b itself
-            Timed t(c, VKMG_KERNEL_VANKA, s, l);
-            launch_vanka_update<T>(L.g, b, x, static_cast<const T*>(L.W), static_cast<T*>(L.dbuf),
-                                   c->opt.omega, s);
-        } else {
-            sweep_t<T>(c, l, x, b, s);
-        }
+        T* dst = next();
+        fused_sweep_t<T>(c, l, b, cur, dst, s);
+        cur = dst;
     }
     const T* rr = b;
-    if (c->opt.nu_pre > 0) {
+    if (cur == nullptr) {
+        launch_fill_zero<T>(x, L.g.n, s);
+        cur = x;
+    } else {
         Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
-        launch_residual<T, T>(L.g, b, x, r, 0, s);
+        launch_residual<T, T>(L.g, b, cur, r, 0, s);
         rr = r;
     }
     T* bc = static_cast<T*>(Lc.b);
@@ -185,11 +190,17 @@ void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
     } else {
         mg_t<T>(c, l - 1, bc, xc, s);
     }
+    T* cw = const_cast<T*>(cur);
     {
         Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
-        launch_prolong_add<T>(L.g, Lc.g, xc, x, s);
+        launch_prolong_add<T>(L.g, Lc.g, xc, cw, s);
     }
-    for (int i = 0; i < c->opt.nu_post; ++i) sweep_t<T>(c, l, x, b, s);
+    for (int i = 0; i < c->opt.nu_post; ++i) {
+        T* dst = next();
+        fused_sweep_t<T>(c, l, b, cur, dst, s);
+        cur = dst;
+    }
+    if (cur != x) (void)hipMemcpyAsync(x, cur, sizeof(T) * L.g.n, hipMemcpyDeviceToDevice, s);
 }
 
 void vcycle_impl(vkmg_ctx* c, const double* r, double* z, hipStream_t s) {
@@ -380,6 +391,7 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         if (st == VKMG_OK) st = alloc(c.get(), &L.r, es * L.g.n);
         if (st == VKMG_OK && l >= 1)
             st = alloc(c.get(), &L.dbuf, es * size_t(vanka_boundary_scratch(L.g.N)));
+        if (st == VKMG_OK && l >= 1) st = alloc(c.get(), &L.xt, es * L.g.n);
         if (st == VKMG_OK && l >= 1) {
             const size_t nw = size_t(kLevelTable);
             st = alloc(c.get(), &L.W, es * nw);
@@ -487,11 +499,18 @@ vkmg_status vkmg_vanka_sweep(vkmg_ctx* ctx, int32_t level, void* x, const void* 
     if (x == b) return fail(VKMG_ERR_INVALID_ARG, "vanka_sweep: b must not alias x");
     VKMG_HIP(hipSetDevice(ctx->device));
     hipStream_t s = as_stream(stream);
+    // the fused sweep the V-cycle runs, into the level's second buffer, then
+    // copied back (the sweep reads x with a halo, so it cannot run in place)
+    LevelBuf& L = ctx->lev[level];
+    const size_t bytes = (ctx->opt.mg_precision == VKMG_FP64 ? sizeof(double) : sizeof(float)) * L.g.n;
     if (ctx->opt.mg_precision == VKMG_FP64)
-        sweep_t<double>(ctx, level, static_cast<double*>(x), static_cast<const double*>(b), s);
+        fused_sweep_t<double>(ctx, level, static_cast<const double*>(b), static_cast<const double*>(x),
+                              static_cast<double*>(L.xt), s);
     else
-        sweep_t<float>(ctx, level, static_cast<float*>(x), static_cast<const float*>(b), s);
+        fused_sweep_t<float>(ctx, level, static_cast<const float*>(b), static_cast<const float*>(x),
+                             static_cast<float*>(L.xt), s);
     VKMG_HIP(hipGetLastError());
+    VKMG_HIP(hipMemcpyAsync(x, L.xt, bytes, hipMemcpyDeviceToDevice, s));
     return VKMG_OK;
 }
 
@@ -714,6 +733,14 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
         if (!std::isfinite(rn)) return finish(VKMG_ERR_NONFINITE, total, restarts, est, NAN);
         if (rn <= target) return finish(VKMG_OK, total, restarts, est, rn / beta0);
         if (total >= max_iters) return finish(VKMG_ERR_NOT_CONVERGED, total, restarts, est, rn / beta0);
+        // the Arnoldi estimate met the tolerance but the true residual did
+        // not, and the cycle did not halve it: the tolerance is below what
+        // FP64 residuals of this system can resolve; more cycles only repeat
+        if (std::fabs(gv[k]) <= target && rn > 0.5 * beta) {
+            finish(VKMG_ERR_NOT_CONVERGED, total, restarts, est, rn / beta0);
+            g_last_error = "fgmres_solve: true residual stagnates above the tolerance (rounding floor)";
+            return VKMG_ERR_NOT_CONVERGED;
+        }
         ++restarts;
         beta = rn;
     }

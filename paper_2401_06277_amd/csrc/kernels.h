@@ -27,6 +27,13 @@ void launch_vanka_update(const Geom& g, const T* r, T* x, const T* table, T* dbu
                          hipStream_t s);
 int64_t vanka_boundary_scratch(int N);
 
+// One fused sweep: r = b - A x formed in LDS per tile, then the update,
+// written to x_out (x_out must not alias x_in; x_in == nullptr means x = 0
+// and then r = b).  Every DoF of x_out is written.
+template <typename T>
+void launch_vanka_sweep(const Geom& g, const T* b, const T* xin, T* xout, const T* table, T* dbuf,
+                        double omega, hipStream_t s);
+
 // Transfers between the fine level gf and the coarse level gc (gf.N == 2 gc.N).
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, hipStream_t s);

@@ -18,12 +18,74 @@ __device__ __forceinline__ bool q2_boundary(int qi, int qj, int s2) {
 }
 
 // ---------------------------------------------------------------------------
+// Rows of A for one cell from LDS-staged values.  A cell (ex, ey) holds the
+// Q2 nodes (2ex+a, 2ey+b), a, b in {0,1}, and the Q1 node (ex, ey).  The
+// staged velocity arrays (row stride SQ2) hold x with Dirichlet columns and
+// outside nodes already zeroed; c2 is the staged index of node (2ex, 2ey);
+// the staged pressure array (row stride SQ1) has c1 at Q1 node (ex, ey).
+// Returns (A x) at the four Q2 nodes (both components; meaningful for free
+// nodes) and (B u) at the Q1 node.
+// ---------------------------------------------------------------------------
+
+template <int SQ2, int SQ1, typename T>
+__device__ __forceinline__ void cell_rows(const T* __restrict__ su0, const T* __restrict__ su1,
+                                          const T* __restrict__ sp, int c2, int c1, T cl, T cb,
+                                          T (&ax)[2][2], T (&ay)[2][2], T& ap) {
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) {
+            T lx = 0, ly = 0, bx = 0, by = 0;
+            const int cn = c2 + bb * SQ2 + aa;
+#pragma unroll
+            for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+                for (int dx = -2; dx <= 2; ++dx) {
+                    const int c = st_L(bb, aa, dy, dx);
+                    if (c != 0) {
+                        lx += T(c) * su0[cn + dy * SQ2 + dx];
+                        ly += T(c) * su1[cn + dy * SQ2 + dx];
+                    }
+                }
+            // B^T p: Q1 nodes I with offsets o = i - 2I of the parity of i
+#pragma unroll
+            for (int oy = -2; oy <= 2; ++oy) {
+                if (((oy - bb) & 1) != 0) continue;
+#pragma unroll
+                for (int oxx = -2; oxx <= 2; ++oxx) {
+                    if (((oxx - aa) & 1) != 0) continue;
+                    const int cx = st_Mq(oy) * st_G(oxx);
+                    const int cy = st_G(oy) * st_Mq(oxx);
+                    if (cx == 0 && cy == 0) continue;
+                    const T pv = sp[c1 + ((bb - oy) / 2) * SQ1 + (aa - oxx) / 2];
+                    bx += T(cx) * pv;
+                    by += T(cy) * pv;
+                }
+            }
+            ax[bb][aa] = cl * lx + cb * bx;
+            ay[bb][aa] = cl * ly + cb * by;
+        }
+    }
+    T sp_ = 0;
+#pragma unroll
+    for (int oy = -2; oy <= 2; ++oy)
+#pragma unroll
+        for (int oxx = -2; oxx <= 2; ++oxx) {
+            const int cx = st_Mq(oy) * st_G(oxx);
+            const int cy = st_G(oy) * st_Mq(oxx);
+            if (cx == 0 && cy == 0) continue;
+            const int cc = c2 + oy * SQ2 + oxx;
+            sp_ += T(cx) * su0[cc] + T(cy) * su1[cc];
+        }
+    ap = cb * sp_;
+}
+
+// ---------------------------------------------------------------------------
 // Residual r = b - A x (MODE 0) / apply r = A x (MODE 1)
-// A workgroup computes the rows of a tile of RT x RT cells; cell (ex, ey)
-// holds the Q2 nodes (2ex+a, 2ey+b), a, b in {0,1}, and the Q1 node
-// (ex, ey), one thread per cell.  The x values the rows need (Q2 nodes
-// within two of the tile, Q1 nodes within one) are staged in LDS with the
-// Dirichlet columns already zeroed, so that every row is a fixed stencil.
+// A workgroup computes the rows of a tile of RT x RT cells, one thread per
+// cell; x on the Q2 nodes within two of the tile and the Q1 nodes within
+// one is staged in LDS with the Dirichlet columns zeroed, so that every row
+// is a fixed stencil.
 // ---------------------------------------------------------------------------
 
 constexpr int RT = 16;              // cells per tile side
@@ -67,10 +129,9 @@ __global__ __launch_bounds__(256) void residual_kernel(Geom g, const T* __restri
     const int tx = threadIdx.x % RT, ty = threadIdx.x / RT;
     const int ex = E0x + tx, ey = E0y + ty;
     if (ex > g.N || ey > g.N) return;
-    // staged coordinates of Q2 node (2ex, 2ey) and of Q1 node (ex, ey)
-    const int c2 = (2 * ty + 2) * RQ2 + 2 * tx + 2;
-    const int c1 = (ty + 1) * RQ1 + tx + 1;
-    const T cl = T(g.nu / 90.0), cb = T(-g.h / 36.0);
+    T ax[2][2], ay[2][2], ap;
+    cell_rows<RQ2, RQ1>(s_u[0], s_u[1], s_p, (2 * ty + 2) * RQ2 + 2 * tx + 2,
+                        (ty + 1) * RQ1 + tx + 1, T(g.nu / 90.0), T(-g.h / 36.0), ax, ay, ap);
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb) {
 #pragma unroll
@@ -78,65 +139,22 @@ __global__ __launch_bounds__(256) void residual_kernel(Geom g, const T* __restri
             const int i = 2 * ex + aa, j = 2 * ey + bb;
             if (i >= g.s2 || j >= g.s2) continue;
             const int64_t q = int64_t(j) * g.s2 + i;
-            T ax, ay;
+            T vx = ax[bb][aa], vy = ay[bb][aa];
             if (i == 0 || j == 0 || i == g.s2 - 1 || j == g.s2 - 1) {
-                ax = T(x[q]);  // Dirichlet row: identity
-                ay = T(x[g.nq2 + q]);
-            } else {
-                T lx = 0, ly = 0, bx = 0, by = 0;
-                const int cn = c2 + bb * RQ2 + aa;
-#pragma unroll
-                for (int dy = -2; dy <= 2; ++dy)
-#pragma unroll
-                    for (int dx = -2; dx <= 2; ++dx) {
-                        const int c = st_L(bb, aa, dy, dx);
-                        if (c != 0) {
-                            lx += T(c) * s_u[0][cn + dy * RQ2 + dx];
-                            ly += T(c) * s_u[1][cn + dy * RQ2 + dx];
-                        }
-                    }
-                // B^T p: Q1 nodes I with |i - 2I| <= 2, offsets o = i - 2I of
-                // the parity of i
-#pragma unroll
-                for (int oy = -2; oy <= 2; ++oy) {
-                    if (((oy - bb) & 1) != 0) continue;
-#pragma unroll
-                    for (int oxx = -2; oxx <= 2; ++oxx) {
-                        if (((oxx - aa) & 1) != 0) continue;
-                        const int cx = st_Mq(oy) * st_G(oxx);
-                        const int cy = st_G(oy) * st_Mq(oxx);
-                        if (cx == 0 && cy == 0) continue;
-                        // I = (i - o)/2 = ex + (aa - o)/2
-                        const T pv = s_p[c1 + ((bb - oy) / 2) * RQ1 + (aa - oxx) / 2];
-                        bx += T(cx) * pv;
-                        by += T(cy) * pv;
-                    }
-                }
-                ax = cl * lx + cb * bx;
-                ay = cl * ly + cb * by;
+                vx = T(x[q]);  // Dirichlet row: identity
+                vy = T(x[g.nq2 + q]);
             }
             if (MODE == 0) {
-                r[q] = b[q] - ax;
-                r[g.nq2 + q] = b[g.nq2 + q] - ay;
+                r[q] = b[q] - vx;
+                r[g.nq2 + q] = b[g.nq2 + q] - vy;
             } else {
-                r[q] = ax;
-                r[g.nq2 + q] = ay;
+                r[q] = vx;
+                r[g.nq2 + q] = vy;
             }
         }
     }
-    T sp = 0;
-#pragma unroll
-    for (int oy = -2; oy <= 2; ++oy)
-#pragma unroll
-        for (int oxx = -2; oxx <= 2; ++oxx) {
-            const int cx = st_Mq(oy) * st_G(oxx);
-            const int cy = st_G(oy) * st_Mq(oxx);
-            if (cx == 0 && cy == 0) continue;
-            const int cc = c2 + oy * RQ2 + oxx;
-            sp += T(cx) * s_u[0][cc] + T(cy) * s_u[1][cc];
-        }
     const int64_t qp = 2 * g.nq2 + int64_t(ey) * g.s1 + ex;
-    r[qp] = (MODE == 0) ? b[qp] - cb * sp : cb * sp;
+    r[qp] = (MODE == 0) ? b[qp] - ap : ap;
 }
 
 // ---------------------------------------------------------------------------
@@ -377,11 +395,63 @@ __device__ __forceinline__ int64_t slot_index(const Geom& g, int I, int J, int s
     return int64_t(f) * g.nq2 + int64_t(qj) * g.s2 + qi;
 }
 
-// One wavefront per boundary patch: lane s gathers r at slot s, then
-// computes row s of the class's weighted inverse (stored transposed, so the
-// lanes read consecutive addresses) against the gathered residual.
+// Residual b - A x at patch slot s of the patch at Q1 node (I, J), read from
+// global memory (used for the O(N) boundary patches).  Dirichlet and absent
+// slots give 0: their weighted-inverse rows and columns vanish.
 template <typename T>
-__global__ __launch_bounds__(256) void vanka_boundary_kernel(Geom g, const T* __restrict__ r,
+__device__ T slot_residual(const Geom& g, const T* __restrict__ b, const T* __restrict__ x, int I,
+                           int J, int s) {
+    const T* ux = x;
+    const T* uy = x + g.nq2;
+    const T* p = x + 2 * g.nq2;
+    auto uval = [&](const T* u, int qi, int qj) -> T {
+        const bool free = qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
+        return free ? u[int64_t(qj) * g.s2 + qi] : T(0);
+    };
+    const T cl = T(g.nu / 90.0), cb = T(-g.h / 36.0);
+    if (s == 50) {
+        T acc = 0;
+        for (int oy = -2; oy <= 2; ++oy)
+            for (int ox = -2; ox <= 2; ++ox) {
+                const int cx = st_Mq(oy) * st_G(ox), cy = st_G(oy) * st_Mq(ox);
+                if (cx == 0 && cy == 0) continue;
+                const int qi = 2 * I + ox, qj = 2 * J + oy;
+                acc += T(cx) * uval(ux, qi, qj) + T(cy) * uval(uy, qi, qj);
+            }
+        const int64_t q = 2 * g.nq2 + int64_t(J) * g.s1 + I;
+        return b[q] - cb * acc;
+    }
+    const int f = s / 25, l = s % 25;
+    const int qi = 2 * I - 2 + l % 5, qj = 2 * J - 2 + l / 5;
+    if (qi <= 0 || qj <= 0 || qi >= g.s2 - 1 || qj >= g.s2 - 1) return T(0);
+    const int px = qi & 1, py = qj & 1;
+    const T* u = f ? uy : ux;
+    T lacc = 0;
+    for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+            const int c = st_L(py, px, dy, dx);
+            if (c != 0) lacc += T(c) * uval(u, qi + dx, qj + dy);
+        }
+    T bacc = 0;
+    for (int oy = -2; oy <= 2; ++oy) {
+        if (((oy - py) & 1) != 0) continue;
+        for (int ox = -2; ox <= 2; ++ox) {
+            if (((ox - px) & 1) != 0) continue;
+            const int c = f ? st_G(oy) * st_Mq(ox) : st_Mq(oy) * st_G(ox);
+            if (c == 0) continue;
+            bacc += T(c) * p[int64_t((qj - oy) / 2) * g.s1 + (qi - ox) / 2];
+        }
+    }
+    return b[int64_t(f) * g.nq2 + int64_t(qj) * g.s2 + qi] - (cl * lacc + cb * bacc);
+}
+
+// One wavefront per boundary patch: lane s forms the patch residual at slot s
+// (gathered from r, or computed from b and x when FROM_X), then computes row
+// s of the class's weighted inverse (stored transposed, so the lanes read
+// consecutive addresses) against the residual broadcast from LDS.
+template <typename T, bool FROM_X>
+__global__ __launch_bounds__(256) void vanka_boundary_kernel(Geom g, const T* __restrict__ rb,
+                                                             const T* __restrict__ x,
                                                              const T* __restrict__ table,
                                                              T* __restrict__ dbuf) {
     __shared__ T s_r[4][64];
@@ -393,8 +463,12 @@ __global__ __launch_bounds__(256) void vanka_boundary_kernel(Geom g, const T* __
     const int cls = 5 * dclass(J, g.N) + dclass(I, g.N);
     T rv = 0;
     if (active && lane < kSlots) {
-        const int64_t q = slot_index(g, I, J, lane);
-        if (q >= 0) rv = r[q];
+        if (FROM_X) {
+            rv = slot_residual(g, rb, x, I, J, lane);
+        } else {
+            const int64_t q = slot_index(g, I, J, lane);
+            if (q >= 0) rv = rb[q];
+        }
     }
     s_r[w][lane] = rv;
     __syncthreads();
@@ -420,17 +494,36 @@ __global__ __launch_bounds__(256) void vanka_boundary_kernel(Geom g, const T* __
 // shared halos stay in its L2.
 __host__ __device__ inline int vanka_tiles(int N) { return (N + 1 + VT - 1) / VT; }
 
-template <typename T>
-__global__ __launch_bounds__(VNT, 2) void vanka_tile_kernel(Geom g, const T* __restrict__ r,
-                                                            T* __restrict__ x,
-                                                            const T* __restrict__ dbuf,
-                                                            T scale, T t) {
-    // staging of the residual region (2 VR^2 values), reused for the
-    // exchange of the x-sums (20 values per thread)
-    __shared__ T s_buf[20 * VNT];
-    static_assert(2 * VR * VR <= 20 * VNT, "staging region exceeds the shared buffer");
-    T* s_rx = s_buf;
-    T* s_ry = s_buf + VR * VR;
+// Staged regions of the sweep kernel (per tile, Q2 / Q1 nodes per side):
+//   x region: Q2 [2E0-6, 2E0+2VT+4], Q1 [E0-3, E0+VT+2]   (FROM_X only)
+//   r region: Q2 [2E0-4, 2E0+2VT+2], Q1 [E0-1, E0+VT]
+constexpr int VX2 = 2 * VT + 11;  // 39
+constexpr int VX1 = VT + 6;       // 20
+constexpr int VR1 = VT + 2;       // 16
+constexpr int kXRegion = 2 * VX2 * VX2 + VX1 * VX1;
+constexpr int kRRegion = 2 * VR * VR + VR1 * VR1;
+constexpr int kExchange = 20 * VNT;
+constexpr int kSweepLdsFromX = (kXRegion + kRRegion > kExchange) ? kXRegion + kRRegion : kExchange;
+constexpr int kSweepLdsGivenR = (kRRegion > kExchange) ? kRRegion : kExchange;
+constexpr int kResidualCells = (VX2 - 3) / 2;  // 18 cells per side cover the r region
+
+// One additive Vanka sweep on a tile.
+//   FROM_X:  r = b - A x is computed in LDS from x (staged with its halo) and
+//            b; x_out = x_in + corrections (x_in and x_out distinct).
+//   !FROM_X: r is read from `rb`; x_out = x_in + corrections, with x_in ==
+//            x_out allowed (in place) and x_in == nullptr meaning x_in = 0.
+// Every DoF a tile owns is written (Dirichlet DoFs keep x_in).  The interior
+// operator is applied to the residual scaled by omega/nu (pressure also by
+// t = nu/h), see sym_apply.
+template <typename T, bool FROM_X>
+__global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __restrict__ rb,
+                                                             const T* xin, T* xout,
+                                                             const T* __restrict__ dbuf, T scale,
+                                                             T t) {
+    __shared__ T s_buf[FROM_X ? kSweepLdsFromX : kSweepLdsGivenR];
+    T* const sr0 = s_buf + (FROM_X ? kXRegion : 0);
+    T* const sr1 = sr0 + VR * VR;
+    T* const srp = sr1 + VR * VR;
     const int tiles = vanka_tiles(g.N);
     const int ntile = tiles * tiles;
     const int per_xcd = (ntile + 7) / 8;
@@ -441,31 +534,93 @@ __global__ __launch_bounds__(VNT, 2) void vanka_tile_kernel(Geom g, const T* __r
     const int I = E0x - 1 + tx, J = E0y - 1 + ty;
     const bool valid = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
 
-    // stage the residual region and gather this thread's patch
-    const int ox = 2 * E0x - 4, oy = 2 * E0y - 4;
+    if (FROM_X) {
+        // stage x (Dirichlet columns and outside nodes zeroed)
+        T* const sx0 = s_buf;
+        T* const sx1 = s_buf + VX2 * VX2;
+        T* const sxp = s_buf + 2 * VX2 * VX2;
+        const int ox = 2 * E0x - 6, oy = 2 * E0y - 6;
 #pragma unroll
-    for (int it = 0; it < (VR * VR + VNT - 1) / VNT; ++it) {
-        const int t = threadIdx.x + it * VNT;
-        if (t < VR * VR) {
-            const int qi = ox + t % VR, qj = oy + t / VR;
-            const bool in = qi >= 0 && qj >= 0 && qi < g.s2 && qj < g.s2;
-            const int64_t q = int64_t(qj) * g.s2 + qi;
-            s_rx[t] = in ? scale * r[q] : T(0);
-            s_ry[t] = in ? scale * r[g.nq2 + q] : T(0);
+        for (int it = 0; it < (VX2 * VX2 + VNT - 1) / VNT; ++it) {
+            const int k = threadIdx.x + it * VNT;
+            if (k < VX2 * VX2) {
+                const int qi = ox + k % VX2, qj = oy + k / VX2;
+                const bool free = qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
+                const int64_t q = int64_t(qj) * g.s2 + qi;
+                sx0[k] = free ? xin[q] : T(0);
+                sx1[k] = free ? xin[g.nq2 + q] : T(0);
+            }
         }
+#pragma unroll
+        for (int it = 0; it < (VX1 * VX1 + VNT - 1) / VNT; ++it) {
+            const int k = threadIdx.x + it * VNT;
+            if (k < VX1 * VX1) {
+                const int Iq = E0x - 3 + k % VX1, Jq = E0y - 3 + k / VX1;
+                const bool in = Iq >= 0 && Jq >= 0 && Iq <= g.N && Jq <= g.N;
+                sxp[k] = in ? xin[2 * g.nq2 + int64_t(Jq) * g.s1 + Iq] : T(0);
+            }
+        }
+        __syncthreads();
+        // residual on the r region, one 2x2-node cell per thread and pass;
+        // cell (cx, cy) has its vertex at r-region node (2cx, 2cy)
+        const T cl = T(g.nu / 90.0), cb = T(-g.h / 36.0);
+        for (int c = threadIdx.x; c < kResidualCells * kResidualCells; c += VNT) {
+            const int cx = c % kResidualCells, cy = c / kResidualCells;
+            T ax[2][2], ay[2][2], ap;
+            cell_rows<VX2, VX1>(sx0, sx1, sxp, (2 * cy + 2) * VX2 + 2 * cx + 2,
+                                (cy + 1) * VX1 + cx + 1, cl, cb, ax, ay, ap);
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+                for (int aa = 0; aa < 2; ++aa) {
+                    const int u = 2 * cx + aa, v = 2 * cy + bb;
+                    if (u >= VR || v >= VR) continue;
+                    const int qi = 2 * E0x - 4 + u, qj = 2 * E0y - 4 + v;
+                    const bool free = qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
+                    T r0 = 0, r1 = 0;
+                    if (free) {
+                        const int64_t q = int64_t(qj) * g.s2 + qi;
+                        r0 = scale * (rb[q] - ax[bb][aa]);
+                        r1 = scale * (rb[g.nq2 + q] - ay[bb][aa]);
+                    }
+                    sr0[v * VR + u] = r0;
+                    sr1[v * VR + u] = r1;
+                }
+            if (cx >= 1 && cx <= VR1 && cy >= 1 && cy <= VR1) {
+                const int Iq = E0x - 2 + cx, Jq = E0y - 2 + cy;
+                T rp = 0;
+                if (Iq >= 0 && Jq >= 0 && Iq <= g.N && Jq <= g.N)
+                    rp = (scale * t) * (rb[2 * g.nq2 + int64_t(Jq) * g.s1 + Iq] - ap);
+                srp[(cy - 1) * VR1 + (cx - 1)] = rp;
+            }
+        }
+    } else {
+        const int ox = 2 * E0x - 4, oy = 2 * E0y - 4;
+#pragma unroll
+        for (int it = 0; it < (VR * VR + VNT - 1) / VNT; ++it) {
+            const int k = threadIdx.x + it * VNT;
+            if (k < VR * VR) {
+                const int qi = ox + k % VR, qj = oy + k / VR;
+                const bool in = qi >= 0 && qj >= 0 && qi < g.s2 && qj < g.s2;
+                const int64_t q = int64_t(qj) * g.s2 + qi;
+                sr0[k] = in ? scale * rb[q] : T(0);
+                sr1[k] = in ? scale * rb[g.nq2 + q] : T(0);
+            }
+        }
+        srp[threadIdx.x] = valid ? (scale * t) * rb[2 * g.nq2 + int64_t(J) * g.s1 + I] : T(0);
     }
-    const T rp = valid ? (scale * t) * r[2 * g.nq2 + int64_t(J) * g.s1 + I] : T(0);
     __syncthreads();
+
     T rv[kSlots];
 #pragma unroll
     for (int b = 0; b < 5; ++b)
 #pragma unroll
         for (int a = 0; a < 5; ++a) {
             const int l = (2 * ty + b) * VR + 2 * tx + a;
-            rv[5 * b + a] = s_rx[l];
-            rv[25 + 5 * b + a] = s_ry[l];
+            rv[5 * b + a] = sr0[l];
+            rv[25 + 5 * b + a] = sr1[l];
         }
-    rv[50] = rp;
+    rv[50] = srp[ty * VR1 + tx];
 
     sym_apply(rv, t);  // interior operator, every lane
     const bool interior = valid && I >= 2 && J >= 2 && I <= g.N - 2 && J <= g.N - 2;
@@ -475,7 +630,7 @@ __global__ __launch_bounds__(VNT, 2) void vanka_tile_kernel(Geom g, const T* __r
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) rv[s] = valid ? dbuf[int64_t(bi) * 64 + s] : T(0);
     }
-    __syncthreads();  // the staging buffer is reused for the exchange below
+    __syncthreads();  // the staging buffers are reused for the exchange below
 
     // x-sums within the 16-lane rows: column 2tx (even) and 2tx+1 (odd) of
     // patch row slot b, both components; exchanged through LDS by b
@@ -507,13 +662,18 @@ __global__ __launch_bounds__(VNT, 2) void vanka_tile_kernel(Geom g, const T* __r
 #pragma unroll
                 for (int py = 0; py < 2; ++py) {
                     const int gj = gj0 + py;
-                    if (gi <= 0 || gj <= 0 || gi >= g.s2 - 1 || gj >= g.s2 - 1) continue;
-                    x[int64_t(c) * g.nq2 + int64_t(gj) * g.s2 + gi] += py ? odd_row : even_row;
+                    if (gi >= g.s2 || gj >= g.s2) continue;
+                    const int64_t q = int64_t(c) * g.nq2 + int64_t(gj) * g.s2 + gi;
+                    const bool free = gi > 0 && gj > 0 && gi < g.s2 - 1 && gj < g.s2 - 1;
+                    const T base = xin ? xin[q] : T(0);
+                    xout[q] = free ? base + (py ? odd_row : even_row) : base;
                 }
             }
     }
-    if (valid && tx >= 1 && tx <= VT && ty >= 1 && ty <= VT)
-        x[2 * g.nq2 + int64_t(J) * g.s1 + I] += rv[50];
+    if (valid && tx >= 1 && tx <= VT && ty >= 1 && ty <= VT) {
+        const int64_t q = 2 * g.nq2 + int64_t(J) * g.s1 + I;
+        xout[q] = (xin ? xin[q] : T(0)) + rv[50];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -883,11 +1043,34 @@ template <typename T>
 void launch_vanka_update(const Geom& g, const T* r, T* x, const T* table, T* dbuf, double omega,
                          hipStream_t s) {
     const int nb = n_boundary_patches(g.N);
-    vanka_boundary_kernel<T><<<(nb + 3) / 4, 256, 0, s>>>(g, r, table, dbuf);
+    vanka_boundary_kernel<T, false><<<(nb + 3) / 4, 256, 0, s>>>(g, r, nullptr, table, dbuf);
     const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
-    vanka_tile_kernel<T><<<8 * ((ntile + 7) / 8), VNT, 0, s>>>(g, r, x, dbuf, T(omega / g.nu),
-                                                               T(g.nu / g.h));
+    vanka_sweep_kernel<T, false><<<8 * ((ntile + 7) / 8), VNT, 0, s>>>(
+        g, r, x, x, dbuf, T(omega / g.nu), T(g.nu / g.h));
 }
+
+template <typename T>
+void launch_vanka_sweep(const Geom& g, const T* b, const T* xin, T* xout, const T* table, T* dbuf,
+                        double omega, hipStream_t s) {
+    const int nb = n_boundary_patches(g.N);
+    const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
+    const int grid = 8 * ((ntile + 7) / 8);
+    if (xin == nullptr) {
+        // x = 0: the residual is b
+        vanka_boundary_kernel<T, false><<<(nb + 3) / 4, 256, 0, s>>>(g, b, nullptr, table, dbuf);
+        vanka_sweep_kernel<T, false><<<grid, VNT, 0, s>>>(g, b, nullptr, xout, dbuf,
+                                                           T(omega / g.nu), T(g.nu / g.h));
+    } else {
+        vanka_boundary_kernel<T, true><<<(nb + 3) / 4, 256, 0, s>>>(g, b, xin, table, dbuf);
+        vanka_sweep_kernel<T, true><<<grid, VNT, 0, s>>>(g, b, xin, xout, dbuf, T(omega / g.nu),
+                                                          T(g.nu / g.h));
+    }
+}
+template void launch_vanka_sweep<double>(const Geom&, const double*, const double*, double*,
+                                         const double*, double*, double, hipStream_t);
+template void launch_vanka_sweep<float>(const Geom&, const float*, const float*, float*,
+                                        const float*, float*, double, hipStream_t);
+
 template void launch_vanka_update<double>(const Geom&, const double*, double*, const double*,
                                           double*, double, hipStream_t);
 template void launch_vanka_update<float>(const Geom&, const float*, float*, const float*, float*,

@@ -175,6 +175,21 @@ def test_vcycle(N, levels):
     assert rel(z, H.vcycle(r)) < 1e-11
 
 
+@pytest.mark.parametrize("nu_pre,nu_post", [(1, 1), (1, 2), (0, 2), (3, 0), (0, 0), (2, 3)])
+def test_vcycle_shapes(nu_pre, nu_post):
+    # odd sweep counts exercise the alternation of the fused sweeps' buffers
+    N, levels = 32, 3
+    note(f"vcycle V({nu_pre},{nu_post})")
+    s = vk.VkmgSolver(N, levels, nu_pre=nu_pre, nu_post=nu_post)
+    H = multigrid.Hierarchy(N, levels, nu_pre=nu_pre, nu_post=nu_post)
+    g = grid_sizes(N)
+    r = uniform_vector(g.n, 91)
+    r[velocity_dirichlet_mask(N)] = 0.0
+    z = host(s.vcycle(dev(r)))
+    assert rel(z, H.vcycle(r)) < 1e-11
+    s.close()
+
+
 def _manufactured_system(N, name="trig"):
     gd = manufactured_boundary_values(N, name)
     A, b, dm, xl = fem.stokes_system(N, 1.0, f_nodal=manufactured_nodal_force(N, name), g_nodal=gd)

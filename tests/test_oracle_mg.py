@@ -278,3 +278,54 @@ def test_fgmres_restart_and_edge_cases():
     # iteration cap
     cap = fgmres.fgmres(A, b, xl, H.vcycle, rtol=1e-14, max_iters=2)
     assert cap.iterations == 2 and not cap.converged
+
+
+# ---------------------------------------------------------------- local forms
+
+def test_residual_rows_match_assembled_operator():
+    N = 8
+    g = grid_sizes(N)
+    A, _, dm, _ = fem.stokes_system(N, 1.0)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(g.n)
+    b = rng.standard_normal(g.n)
+    rows = np.arange(g.n)
+    assert np.abs(fem.residual_rows(N, x, b, rows) - (b - A @ x)).max() < 1e-13
+
+
+def test_local_patch_matrices_equal_extracted_blocks():
+    N = 8
+    A, _, _, _ = fem.stokes_system(N, 1.0)
+    idx = vanka.patch_dofs(N)
+    for k in range(idx.shape[0]):
+        I, J = k % (N + 1), k // (N + 1)
+        Al, S = vanka.local_patch_matrix(N, I, J)
+        assert np.array_equal(S, idx[k][idx[k] >= 0])
+        assert np.array_equal(Al, vanka.extract_patch_matrix(A, idx[k]))
+
+
+def test_sampled_sweep_update_matches_full_sweep():
+    N = 12
+    A, _, dm, _ = fem.stokes_system(N, 1.0)
+    g = grid_sizes(N)
+    rng = np.random.default_rng(6)
+    x = rng.uniform(-1, 1, g.n)
+    b = rng.uniform(-1, 1, g.n)
+    x[dm] = 0.0
+    b[dm] = 0.0
+    full = vanka.VankaSmoother(A, N, dm, 0.5, shared=False).sweep(x, b) - x
+    dofs = np.concatenate([rng.choice(g.n, 60, replace=False),
+                           [g.off_uy + 1 * g.q2_side + 1, g.off_p, g.off_p + g.n_pres - 1]])
+    got = vanka.sampled_sweep_update(N, x, b, dofs)
+    assert np.abs(got - full[dofs]).max() <= 1e-12 * np.abs(full).max()
+
+
+def test_sampled_transfers_match_assembled_prolongation():
+    nc = 6
+    P = transfer.prolongation(nc)
+    gf, gc = grid_sizes(2 * nc), grid_sizes(nc)
+    rng = np.random.default_rng(8)
+    ec = rng.standard_normal(gc.n)
+    rf = rng.standard_normal(gf.n)
+    assert np.abs(transfer.prolong_rows(nc, ec, np.arange(gf.n)) - P @ ec).max() < 1e-14
+    assert np.abs(transfer.restrict_rows(nc, rf, np.arange(gc.n)) - P.T @ rf).max() < 1e-13

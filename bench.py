@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--cpu-levels", type=int, default=6)
     ap.add_argument("--cpu-vcycles", type=int, default=5)
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--interior-apply", choices=["vector", "matrix"], default="vector",
+                    help="interior Vanka apply: vector ALUs (default) or matrix cores")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB "
                          "(3 times) and exit: the reference kernel for scaling HBM "
@@ -144,7 +146,7 @@ def main():
     fd = torch.from_numpy(np.ascontiguousarray(f.ravel())).cuda()
 
     def make(prec):
-        s = vk.VkmgSolver(N, L, precision=prec)
+        s = vk.VkmgSolver(N, L, precision=prec, interior_apply=a.interior_apply)
         b = s.assemble_rhs(fd)
         x = torch.zeros_like(b)
         return s, b, x
@@ -218,6 +220,7 @@ def main():
             "workload": (f"2D Stokes Q2-Q1, {N}x{N} elements, {L} levels, GRF body force "
                          f"(l=0.1, seed 5), FGMRES(30) + V(2,2) Vanka omega=0.5, rtol {a.rtol:g}"),
             "N": N, "levels": L, "dofs": n, "patch_updates_per_vcycle": ups_per_cycle,
+            "interior_apply": a.interior_apply,
         },
         "time_to_1e8_s": dt64 / a.steps,
         "fgmres_iterations": it64[0],
@@ -225,7 +228,9 @@ def main():
         "vcycle_s": vcycle_s,
         "vcycle_patch_updates_per_s": ups_per_cycle / vcycle_s,
         "roofline": {
-            "kernel": "vanka_update_kernel (finest level; interior + boundary tile instances)",
+            "kernel": ("Vanka update at the finest level (boundary-patch kernel + "
+                       + ("vanka_mfma_kernel" if a.interior_apply == "matrix"
+                          else "vanka_sweep_kernel") + ")"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

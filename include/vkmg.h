@@ -58,6 +58,13 @@ typedef enum {
 
 typedef enum { VKMG_FP64 = 0, VKMG_FP32 = 1 } vkmg_precision;
 
+/* How the interior Vanka patches (all patches two or more elements from the
+ * boundary, which share one inverse) are applied: one patch per lane on the
+ * vector ALUs (default, the faster on MI355X), or as 16-patch dense
+ * products on the matrix cores.  Both give the same result up to rounding
+ * order. */
+typedef enum { VKMG_APPLY_VECTOR = 0, VKMG_APPLY_MATRIX = 1 } vkmg_interior_apply;
+
 typedef struct {
     int32_t nx, ny; /* elements per side on [0,1]^2; nx == ny required */
 } vkmg_grid;
@@ -67,6 +74,7 @@ typedef struct {
     int32_t nu_post;             /* Vanka sweeps after it (default 2) */
     double omega;                /* Vanka damping (default 0.5) */
     vkmg_precision mg_precision; /* arithmetic of the whole V-cycle (default FP64) */
+    vkmg_interior_apply interior_apply; /* default VKMG_APPLY_VECTOR */
 } vkmg_options;
 
 typedef struct {

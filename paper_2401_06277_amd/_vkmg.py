@@ -17,6 +17,7 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvkmg.so")
 
 FP64, FP32 = 0, 1
+APPLY = {"vector": 0, "matrix": 1}
 KERNEL_VANKA, KERNEL_RESIDUAL, KERNEL_TRANSFER, KERNEL_COARSE, KERNEL_KRYLOV = range(5)
 
 STATUS = {
@@ -52,7 +53,7 @@ class Grid(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("nu_pre", c_int32), ("nu_post", c_int32), ("omega", c_double),
-                ("mg_precision", c_int32)]
+                ("mg_precision", c_int32), ("interior_apply", c_int32)]
 
 
 class Layout(ctypes.Structure):
@@ -146,12 +147,16 @@ class VkmgSolver:
     problem on the current HIP device."""
 
     def __init__(self, N: int, levels: int, nu: float = 1.0, nu_pre: int = 2, nu_post: int = 2,
-                 omega: float = 0.5, precision: str = "fp64"):
+                 omega: float = 0.5, precision: str = "fp64", interior_apply: str = "vector"):
         import torch
         lib = load_library()
         self._torch = torch
         self.precision = precision
-        opts = Options(nu_pre, nu_post, omega, FP32 if precision == "fp32" else FP64)
+        self.interior_apply = interior_apply
+        if interior_apply not in APPLY:
+            raise ValueError(f"interior_apply must be one of {sorted(APPLY)}")
+        opts = Options(nu_pre, nu_post, omega, FP32 if precision == "fp32" else FP64,
+                       APPLY[interior_apply])
         ctx = c_void_p()
         st = lib.vkmg_setup(byref(Grid(N, N)), levels, nu, byref(opts), self._stream(),
                             byref(ctx))

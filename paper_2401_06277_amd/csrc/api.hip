@@ -40,7 +40,6 @@ struct LevelBuf {
     void* x = nullptr;  // MG precision
     void* b = nullptr;
     void* r = nullptr;
-    void* xt = nullptr;    // second iterate buffer for the fused sweeps (relaxed levels)
     void* W = nullptr;     // patch-operator table, MG precision (relaxed levels)
     void* dbuf = nullptr;  // boundary-patch corrections (relaxed levels)
 };
@@ -53,6 +52,7 @@ struct vkmg_ctx {
     vkmg_options opt{};
     std::vector<LevelBuf> lev;
     double* C = nullptr;  // coarse bordered inverse (n0 x n0), FP64
+    void* mtab = nullptr; // matrix-instruction operands of the interior operator (MG precision)
     // FP64 work vectors of the finest level
     double* r64 = nullptr;
     double* w64 = nullptr;
@@ -139,43 +139,41 @@ vkmg_layout layout_of_geom(const Geom& g) {
 
 // ------------------------------------------------------------------ MG steps
 
-// One fused sweep x_out = S(x_in) on level l (x_in == nullptr: x_in = 0).
+// One sweep on level l: r = b - A x, then x += corrections (in place).
+// With x_zero the iterate is known to be zero, so r = b and the update
+// writes every DoF of x without reading it.
 template <typename T>
-void fused_sweep_t(vkmg_ctx* c, int l, const T* b, const T* xin, T* xout, hipStream_t s) {
+void sweep_t(vkmg_ctx* c, int l, const T* b, T* x, bool x_zero, hipStream_t s) {
     LevelBuf& L = c->lev[l];
+    const T* r = b;
+    if (!x_zero) {
+        Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
+        launch_residual<T, T>(L.g, b, x, static_cast<T*>(L.r), 0, s);
+        r = static_cast<const T*>(L.r);
+    }
     Timed t(c, VKMG_KERNEL_VANKA, s, l);
-    launch_vanka_sweep<T>(L.g, b, xin, xout, static_cast<const T*>(L.W), static_cast<T*>(L.dbuf),
-                          c->opt.omega, s);
+    launch_vanka_update<T>(L.g, r, x_zero ? nullptr : x, x, static_cast<const T*>(L.W),
+                           static_cast<const T*>(c->mtab), static_cast<T*>(L.dbuf), c->opt.omega,
+                           c->opt.interior_apply == VKMG_APPLY_MATRIX, s);
 }
 
-// MG(l, b) of Algorithm 1 with zero initial guess, result in x.  The sweeps
-// alternate between x and the level's second buffer (a fused sweep reads x
-// with a halo, so it cannot update in place); the first target is chosen so
-// that the last sweep writes x.
+// MG(l, b) of Algorithm 1 with zero initial guess, result in x.
 template <typename T>
 void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
     LevelBuf& L = c->lev[l];
     LevelBuf& Lc = c->lev[l - 1];
     T* r = static_cast<T*>(L.r);
-    T* xt = static_cast<T*>(L.xt);
-    const int total = c->opt.nu_pre + c->opt.nu_post;
-    const T* cur = nullptr;  // current iterate; nullptr while it is zero
-    auto next = [&](void) -> T* {
-        if (cur == nullptr) return (total % 2 == 1) ? x : xt;
-        return cur == x ? xt : x;
-    };
+    bool x_zero = true;
     for (int i = 0; i < c->opt.nu_pre; ++i) {
-        T* dst = next();
-        fused_sweep_t<T>(c, l, b, cur, dst, s);
-        cur = dst;
+        sweep_t<T>(c, l, b, x, x_zero, s);
+        x_zero = false;
     }
     const T* rr = b;
-    if (cur == nullptr) {
+    if (x_zero) {
         launch_fill_zero<T>(x, L.g.n, s);
-        cur = x;
     } else {
         Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
-        launch_residual<T, T>(L.g, b, cur, r, 0, s);
+        launch_residual<T, T>(L.g, b, x, r, 0, s);
         rr = r;
     }
     T* bc = static_cast<T*>(Lc.b);
@@ -190,17 +188,11 @@ void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
     } else {
         mg_t<T>(c, l - 1, bc, xc, s);
     }
-    T* cw = const_cast<T*>(cur);
     {
         Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
-        launch_prolong_add<T>(L.g, Lc.g, xc, cw, s);
+        launch_prolong_add<T>(L.g, Lc.g, xc, x, s);
     }
-    for (int i = 0; i < c->opt.nu_post; ++i) {
-        T* dst = next();
-        fused_sweep_t<T>(c, l, b, cur, dst, s);
-        cur = dst;
-    }
-    if (cur != x) (void)hipMemcpyAsync(x, cur, sizeof(T) * L.g.n, hipMemcpyDeviceToDevice, s);
+    for (int i = 0; i < c->opt.nu_post; ++i) sweep_t<T>(c, l, b, x, false, s);
 }
 
 void vcycle_impl(vkmg_ctx* c, const double* r, double* z, hipStream_t s) {
@@ -276,6 +268,7 @@ vkmg_options vkmg_default_options(void) {
     o.nu_post = 2;
     o.omega = 0.5;
     o.mg_precision = VKMG_FP64;
+    o.interior_apply = VKMG_APPLY_VECTOR;
     return o;
 }
 
@@ -338,6 +331,8 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         return fail(VKMG_ERR_INVALID_ARG, "setup: omega must be in (0, 2]");
     if (o.mg_precision != VKMG_FP64 && o.mg_precision != VKMG_FP32)
         return fail(VKMG_ERR_INVALID_ARG, "setup: bad mg_precision");
+    if (o.interior_apply != VKMG_APPLY_MATRIX && o.interior_apply != VKMG_APPLY_VECTOR)
+        return fail(VKMG_ERR_INVALID_ARG, "setup: bad interior_apply");
 
     // host work first (no GPU needed to detect singular patches)
     double B1[651];
@@ -371,6 +366,9 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
                 for (int j = i + 1; j < kSlots; ++j) std::swap(Wc[i * kSlots + j], Wc[j * kSlots + i]);
         }
     }
+    std::vector<double> Mh(kMfmaTable);
+    mfma_interior_table(B1, o.mg_precision == VKMG_FP64, Mh.data());
+    std::vector<float> Mf(Mh.begin(), Mh.end());
     std::vector<double> Ch;
     if (!coarse_bordered_inverse(N0, nu, Ch))
         return fail(VKMG_ERR_SINGULAR_PATCH, "setup: singular coarse matrix");
@@ -391,7 +389,6 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         if (st == VKMG_OK) st = alloc(c.get(), &L.r, es * L.g.n);
         if (st == VKMG_OK && l >= 1)
             st = alloc(c.get(), &L.dbuf, es * size_t(vanka_boundary_scratch(L.g.N)));
-        if (st == VKMG_OK && l >= 1) st = alloc(c.get(), &L.xt, es * L.g.n);
         if (st == VKMG_OK && l >= 1) {
             const size_t nw = size_t(kLevelTable);
             st = alloc(c.get(), &L.W, es * nw);
@@ -407,6 +404,13 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
                 }
             }
         }
+    }
+    if (st == VKMG_OK) st = alloc(c.get(), &c->mtab, es * kMfmaTable);
+    if (st == VKMG_OK) {
+        const void* src = o.mg_precision == VKMG_FP64 ? static_cast<const void*>(Mh.data())
+                                                      : static_cast<const void*>(Mf.data());
+        hipError_t e = hipMemcpyAsync(c->mtab, src, es * kMfmaTable, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) st = fail(VKMG_ERR_HIP, "setup: upload of interior operands");
     }
     if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->C), Ch.size() * 8);
     if (st == VKMG_OK) {
@@ -499,18 +503,11 @@ vkmg_status vkmg_vanka_sweep(vkmg_ctx* ctx, int32_t level, void* x, const void* 
     if (x == b) return fail(VKMG_ERR_INVALID_ARG, "vanka_sweep: b must not alias x");
     VKMG_HIP(hipSetDevice(ctx->device));
     hipStream_t s = as_stream(stream);
-    // the fused sweep the V-cycle runs, into the level's second buffer, then
-    // copied back (the sweep reads x with a halo, so it cannot run in place)
-    LevelBuf& L = ctx->lev[level];
-    const size_t bytes = (ctx->opt.mg_precision == VKMG_FP64 ? sizeof(double) : sizeof(float)) * L.g.n;
     if (ctx->opt.mg_precision == VKMG_FP64)
-        fused_sweep_t<double>(ctx, level, static_cast<const double*>(b), static_cast<const double*>(x),
-                              static_cast<double*>(L.xt), s);
+        sweep_t<double>(ctx, level, static_cast<const double*>(b), static_cast<double*>(x), false, s);
     else
-        fused_sweep_t<float>(ctx, level, static_cast<const float*>(b), static_cast<const float*>(x),
-                             static_cast<float*>(L.xt), s);
+        sweep_t<float>(ctx, level, static_cast<const float*>(b), static_cast<float*>(x), false, s);
     VKMG_HIP(hipGetLastError());
-    VKMG_HIP(hipMemcpyAsync(x, L.xt, bytes, hipMemcpyDeviceToDevice, s));
     return VKMG_OK;
 }
 

@@ -21,6 +21,7 @@
 #include <cstring>
 
 #include "symmetry.h"
+#include "mfma_patch.h"
 #include "vkmg_internal.h"
 
 namespace vkmg {
@@ -340,6 +341,28 @@ bool universal_interior_blocks(double* B1) {
     std::vector<double> W(kSlots * kSlots);
     weighted_inverse(N, kInteriorClass, 1.0, inv.data(), pres, W.data());
     return interior_symmetry_blocks(W.data(), B1, 1e-12);
+}
+
+void mfma_interior_table(const double* B1, bool fp64_layout, double* A) {
+    // member index of transformed slot t within its block
+    int member[kSlots];
+    for (int blk = 0; blk < kSymBlocks; ++blk)
+        for (int k = 0; k < sym_block_size(blk); ++k) member[sym_member(blk, k)] = k;
+    for (int blk = 0; blk < kSymBlocks; ++blk) {
+        const int n = sym_block_size(blk), off = sym_block_offset(blk);
+        for (int c = 0; c < 4; ++c)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int i = lane % 16, k = lane / 16;
+                // output row i sits in quarter i / 4, element i % 4 (FP32)
+                // or in quarter i % 4, element i / 4 (FP64)
+                const int qr = fp64_layout ? i % 4 : i / 4, vr = fp64_layout ? i / 4 : i % 4;
+                const int tr = quarter_item_tslot(blk, qr, vr);
+                const int tc = quarter_item_tslot(blk, k, c);
+                double v = 0.0;
+                if (tr >= 0 && tc >= 0) v = B1[off + member[tr] * n + member[tc]];
+                A[(blk * 4 + c) * 64 + lane] = v;
+            }
+    }
 }
 
 double universal_mismatch(const double* Blevel, const double* B1, double omega, double nu,

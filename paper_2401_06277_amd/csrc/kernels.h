@@ -16,23 +16,20 @@ void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hip
 // b = M f - A_FD g on free rows, g on Dirichlet rows, -B_pD g on pressure rows.
 void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hipStream_t s);
 
-// One Vanka update given the residual r of x: x += sum_i V_i^T W_i A_i^{-1} V_i r.
-// `table` is the level's patch-operator table (kLevelTable values: the 25
-// weighted inverses stored transposed, then the interior reflection
-// blocks, which the kernels take from compile-time constants instead);
-// `dbuf` is scratch for the boundary patches
-// (vanka_boundary_scratch(N) values).
+// One Vanka update given the residual r of x_in:
+// x_out = x_in + sum_i V_i^T W_i A_i^{-1} V_i r (x_out == x_in allowed;
+// x_in == nullptr means x_in = 0, so r = b).  `table` is the level's
+// patch-operator table (kLevelTable values: the 25 weighted inverses stored
+// transposed, then the interior reflection blocks, which the kernels take
+// from compile-time constants instead); `dbuf` is scratch for the boundary
+// patches (vanka_boundary_scratch(N) values).  The interior patches are
+// applied on the matrix instructions with the operand table `mtab`
+// (kMfmaTable values, mfma_interior_table) when `mfma`, else on the vector
+// ALUs with the compile-time constants.
 template <typename T>
-void launch_vanka_update(const Geom& g, const T* r, T* x, const T* table, T* dbuf, double omega,
-                         hipStream_t s);
+void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const T* table,
+                         const T* mtab, T* dbuf, double omega, bool mfma, hipStream_t s);
 int64_t vanka_boundary_scratch(int N);
-
-// One fused sweep: r = b - A x formed in LDS per tile, then the update,
-// written to x_out (x_out must not alias x_in; x_in == nullptr means x = 0
-// and then r = b).  Every DoF of x_out is written.
-template <typename T>
-void launch_vanka_sweep(const Geom& g, const T* b, const T* xin, T* xout, const T* table, T* dbuf,
-                        double omega, hipStream_t s);
 
 // Transfers between the fine level gf and the coarse level gc (gf.N == 2 gc.N).
 template <typename T>

@@ -8,6 +8,7 @@
 #include "stencil.h"
 #include "interior_blocks.h"
 #include "symmetry.h"
+#include "mfma_patch.h"
 
 namespace vkmg {
 
@@ -105,30 +106,66 @@ __global__ __launch_bounds__(256) void residual_kernel(Geom g, const T* __restri
     if (tlin >= ntile) return;
     const int E0x = (tlin % tiles) * RT, E0y = (tlin / tiles) * RT;
     const int ox = 2 * E0x - 2, oy = 2 * E0y - 2;
+    // every load of the tile is issued before the first is used: addresses
+    // of nodes outside the staged set are clamped to node 0 and the values
+    // replaced by zero afterwards
+    constexpr int kIt2 = (RQ2 * RQ2 + 255) / 256, kIt1 = (RQ1 * RQ1 + 255) / 256;
+    Tx v0[kIt2], v1[kIt2], vp[kIt1];
+    bool f2[kIt2], f1[kIt1];
 #pragma unroll
-    for (int it = 0; it < (RQ2 * RQ2 + 255) / 256; ++it) {
+    for (int it = 0; it < kIt2; ++it) {
         const int t = threadIdx.x + it * 256;
-        if (t < RQ2 * RQ2) {
-            const int qi = ox + t % RQ2, qj = oy + t / RQ2;
-            const bool free = qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
-            const int64_t q = int64_t(qj) * g.s2 + qi;
-            s_u[0][t] = free ? T(x[q]) : T(0);
-            s_u[1][t] = free ? T(x[g.nq2 + q]) : T(0);
-        }
+        const int qi = ox + t % RQ2, qj = oy + t / RQ2;
+        f2[it] = t < RQ2 * RQ2 && qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
+        const int64_t q = f2[it] ? int64_t(qj) * g.s2 + qi : 0;
+        v0[it] = x[q];
+        v1[it] = x[g.nq2 + q];
     }
 #pragma unroll
-    for (int it = 0; it < (RQ1 * RQ1 + 255) / 256; ++it) {
+    for (int it = 0; it < kIt1; ++it) {
         const int t = threadIdx.x + it * 256;
-        if (t < RQ1 * RQ1) {
-            const int I = E0x - 1 + t % RQ1, J = E0y - 1 + t / RQ1;
-            const bool in = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
-            s_p[t] = in ? T(x[2 * g.nq2 + int64_t(J) * g.s1 + I]) : T(0);
-        }
+        const int I = E0x - 1 + t % RQ1, J = E0y - 1 + t / RQ1;
+        f1[it] = t < RQ1 * RQ1 && I >= 0 && J >= 0 && I <= g.N && J <= g.N;
+        vp[it] = x[2 * g.nq2 + (f1[it] ? int64_t(J) * g.s1 + I : 0)];
     }
-    __syncthreads();
+    // this thread's rows: b and (for Dirichlet rows) x at its four Q2 nodes
     const int tx = threadIdx.x % RT, ty = threadIdx.x / RT;
     const int ex = E0x + tx, ey = E0y + ty;
-    if (ex > g.N || ey > g.N) return;
+    const bool cell = ex <= g.N && ey <= g.N;
+    int64_t qn[2][2];
+    T bx[2][2], by[2][2];
+    Tx xx[2][2], xy[2][2];
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) {
+            const int i = 2 * ex + aa, j = 2 * ey + bb;
+            qn[bb][aa] = (cell && i < g.s2 && j < g.s2) ? int64_t(j) * g.s2 + i : -1;
+            const int64_t q = qn[bb][aa] >= 0 ? qn[bb][aa] : 0;
+            xx[bb][aa] = x[q];
+            xy[bb][aa] = x[g.nq2 + q];
+            if (MODE == 0) {
+                bx[bb][aa] = b[q];
+                by[bb][aa] = b[g.nq2 + q];
+            }
+        }
+    const int64_t qp = 2 * g.nq2 + (cell ? int64_t(ey) * g.s1 + ex : 0);
+    const T bp = (MODE == 0) ? b[qp] : T(0);
+#pragma unroll
+    for (int it = 0; it < kIt2; ++it) {
+        const int t = threadIdx.x + it * 256;
+        if (t < RQ2 * RQ2) {
+            s_u[0][t] = f2[it] ? T(v0[it]) : T(0);
+            s_u[1][t] = f2[it] ? T(v1[it]) : T(0);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < kIt1; ++it) {
+        const int t = threadIdx.x + it * 256;
+        if (t < RQ1 * RQ1) s_p[t] = f1[it] ? T(vp[it]) : T(0);
+    }
+    __syncthreads();
+    if (!cell) return;
     T ax[2][2], ay[2][2], ap;
     cell_rows<RQ2, RQ1>(s_u[0], s_u[1], s_p, (2 * ty + 2) * RQ2 + 2 * tx + 2,
                         (ty + 1) * RQ1 + tx + 1, T(g.nu / 90.0), T(-g.h / 36.0), ax, ay, ap);
@@ -136,25 +173,24 @@ __global__ __launch_bounds__(256) void residual_kernel(Geom g, const T* __restri
     for (int bb = 0; bb < 2; ++bb) {
 #pragma unroll
         for (int aa = 0; aa < 2; ++aa) {
+            const int64_t q = qn[bb][aa];
+            if (q < 0) continue;
             const int i = 2 * ex + aa, j = 2 * ey + bb;
-            if (i >= g.s2 || j >= g.s2) continue;
-            const int64_t q = int64_t(j) * g.s2 + i;
             T vx = ax[bb][aa], vy = ay[bb][aa];
             if (i == 0 || j == 0 || i == g.s2 - 1 || j == g.s2 - 1) {
-                vx = T(x[q]);  // Dirichlet row: identity
-                vy = T(x[g.nq2 + q]);
+                vx = T(xx[bb][aa]);  // Dirichlet row: identity
+                vy = T(xy[bb][aa]);
             }
             if (MODE == 0) {
-                r[q] = b[q] - vx;
-                r[g.nq2 + q] = b[g.nq2 + q] - vy;
+                r[q] = bx[bb][aa] - vx;
+                r[g.nq2 + q] = by[bb][aa] - vy;
             } else {
                 r[q] = vx;
                 r[g.nq2 + q] = vy;
             }
         }
     }
-    const int64_t qp = 2 * g.nq2 + int64_t(ey) * g.s1 + ex;
-    r[qp] = (MODE == 0) ? b[qp] - ap : ap;
+    r[qp] = (MODE == 0) ? bp - ap : ap;
 }
 
 // ---------------------------------------------------------------------------
@@ -395,63 +431,13 @@ __device__ __forceinline__ int64_t slot_index(const Geom& g, int I, int J, int s
     return int64_t(f) * g.nq2 + int64_t(qj) * g.s2 + qi;
 }
 
-// Residual b - A x at patch slot s of the patch at Q1 node (I, J), read from
-// global memory (used for the O(N) boundary patches).  Dirichlet and absent
-// slots give 0: their weighted-inverse rows and columns vanish.
+// One wavefront per boundary patch: lane s gathers the patch residual at
+// slot s, then computes row s of the class's weighted inverse (stored
+// transposed, so the lanes read consecutive addresses) against the residual
+// broadcast from LDS.  The residual and all 51 coefficient loads are issued
+// together (inactive lanes read valid addresses and are discarded).
 template <typename T>
-__device__ T slot_residual(const Geom& g, const T* __restrict__ b, const T* __restrict__ x, int I,
-                           int J, int s) {
-    const T* ux = x;
-    const T* uy = x + g.nq2;
-    const T* p = x + 2 * g.nq2;
-    auto uval = [&](const T* u, int qi, int qj) -> T {
-        const bool free = qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
-        return free ? u[int64_t(qj) * g.s2 + qi] : T(0);
-    };
-    const T cl = T(g.nu / 90.0), cb = T(-g.h / 36.0);
-    if (s == 50) {
-        T acc = 0;
-        for (int oy = -2; oy <= 2; ++oy)
-            for (int ox = -2; ox <= 2; ++ox) {
-                const int cx = st_Mq(oy) * st_G(ox), cy = st_G(oy) * st_Mq(ox);
-                if (cx == 0 && cy == 0) continue;
-                const int qi = 2 * I + ox, qj = 2 * J + oy;
-                acc += T(cx) * uval(ux, qi, qj) + T(cy) * uval(uy, qi, qj);
-            }
-        const int64_t q = 2 * g.nq2 + int64_t(J) * g.s1 + I;
-        return b[q] - cb * acc;
-    }
-    const int f = s / 25, l = s % 25;
-    const int qi = 2 * I - 2 + l % 5, qj = 2 * J - 2 + l / 5;
-    if (qi <= 0 || qj <= 0 || qi >= g.s2 - 1 || qj >= g.s2 - 1) return T(0);
-    const int px = qi & 1, py = qj & 1;
-    const T* u = f ? uy : ux;
-    T lacc = 0;
-    for (int dy = -2; dy <= 2; ++dy)
-        for (int dx = -2; dx <= 2; ++dx) {
-            const int c = st_L(py, px, dy, dx);
-            if (c != 0) lacc += T(c) * uval(u, qi + dx, qj + dy);
-        }
-    T bacc = 0;
-    for (int oy = -2; oy <= 2; ++oy) {
-        if (((oy - py) & 1) != 0) continue;
-        for (int ox = -2; ox <= 2; ++ox) {
-            if (((ox - px) & 1) != 0) continue;
-            const int c = f ? st_G(oy) * st_Mq(ox) : st_Mq(oy) * st_G(ox);
-            if (c == 0) continue;
-            bacc += T(c) * p[int64_t((qj - oy) / 2) * g.s1 + (qi - ox) / 2];
-        }
-    }
-    return b[int64_t(f) * g.nq2 + int64_t(qj) * g.s2 + qi] - (cl * lacc + cb * bacc);
-}
-
-// One wavefront per boundary patch: lane s forms the patch residual at slot s
-// (gathered from r, or computed from b and x when FROM_X), then computes row
-// s of the class's weighted inverse (stored transposed, so the lanes read
-// consecutive addresses) against the residual broadcast from LDS.
-template <typename T, bool FROM_X>
 __global__ __launch_bounds__(256) void vanka_boundary_kernel(Geom g, const T* __restrict__ rb,
-                                                             const T* __restrict__ x,
                                                              const T* __restrict__ table,
                                                              T* __restrict__ dbuf) {
     __shared__ T s_r[4][64];
@@ -461,23 +447,16 @@ __global__ __launch_bounds__(256) void vanka_boundary_kernel(Geom g, const T* __
     int I = 0, J = 0;
     if (active) boundary_patch(k, g.N, I, J);
     const int cls = 5 * dclass(J, g.N) + dclass(I, g.N);
-    T rv = 0;
-    if (active && lane < kSlots) {
-        if (FROM_X) {
-            rv = slot_residual(g, rb, x, I, J, lane);
-        } else {
-            const int64_t q = slot_index(g, I, J, lane);
-            if (q >= 0) rv = rb[q];
-        }
-    }
-    s_r[w][lane] = rv;
-    __syncthreads();
-    if (!active || lane >= kSlots) return;
+    const int s = lane < kSlots ? lane : 0;
+    const int64_t q = slot_index(g, I, J, s);
+    const T rv = rb[q >= 0 ? q : 0];
     const T* __restrict__ Mt = table + cls * kSlots * kSlots;  // Mt[t][s] = W[s][t]
-    // issue every coefficient load before the first use (one memory round trip)
     T m[kSlots];
 #pragma unroll
-    for (int t = 0; t < kSlots; ++t) m[t] = Mt[t * kSlots + lane];
+    for (int t = 0; t < kSlots; ++t) m[t] = Mt[t * kSlots + s];
+    s_r[w][lane] = (active && lane < kSlots && q >= 0) ? rv : T(0);
+    __syncthreads();
+    if (!active || lane >= kSlots) return;
     T a0 = 0, a1 = 0;
 #pragma unroll
     for (int t = 0; t + 1 < kSlots; t += 2) {
@@ -494,34 +473,103 @@ __global__ __launch_bounds__(256) void vanka_boundary_kernel(Geom g, const T* __
 // shared halos stay in its L2.
 __host__ __device__ inline int vanka_tiles(int N) { return (N + 1 + VT - 1) / VT; }
 
-// Staged regions of the sweep kernel (per tile, Q2 / Q1 nodes per side):
-//   x region: Q2 [2E0-6, 2E0+2VT+4], Q1 [E0-3, E0+VT+2]   (FROM_X only)
+// Staged region of the sweep kernel (per tile, Q2 / Q1 nodes per side):
 //   r region: Q2 [2E0-4, 2E0+2VT+2], Q1 [E0-1, E0+VT]
-constexpr int VX2 = 2 * VT + 11;  // 39
-constexpr int VX1 = VT + 6;       // 20
-constexpr int VR1 = VT + 2;       // 16
-constexpr int kXRegion = 2 * VX2 * VX2 + VX1 * VX1;
+constexpr int VR1 = VT + 2;
 constexpr int kRRegion = 2 * VR * VR + VR1 * VR1;
 constexpr int kExchange = 20 * VNT;
-constexpr int kSweepLdsFromX = (kXRegion + kRRegion > kExchange) ? kXRegion + kRRegion : kExchange;
-constexpr int kSweepLdsGivenR = (kRRegion > kExchange) ? kRRegion : kExchange;
-constexpr int kResidualCells = (VX2 - 3) / 2;  // 18 cells per side cover the r region
+constexpr int kSweepLds = (kRRegion > kExchange) ? kRRegion : kExchange;
 
-// One additive Vanka sweep on a tile.
-//   FROM_X:  r = b - A x is computed in LDS from x (staged with its halo) and
-//            b; x_out = x_in + corrections (x_in and x_out distinct).
-//   !FROM_X: r is read from `rb`; x_out = x_in + corrections, with x_in ==
-//            x_out allowed (in place) and x_in == nullptr meaning x_in = 0.
-// Every DoF a tile owns is written (Dirichlet DoFs keep x_in).  The interior
-// operator is applied to the residual scaled by omega/nu (pressure also by
-// t = nu/h), see sym_apply.
-template <typename T, bool FROM_X>
+// Stage the scaled residual of a tile's r region in LDS (velocity scaled
+// by `scale`, pressure by `scale * t`, nodes outside the mesh zero).  All
+// global loads are issued before the first is used.
+template <typename T>
+__device__ __forceinline__ void stage_residual_region(const Geom& g, const T* __restrict__ rb,
+                                                      int E0x, int E0y, T scale, T t,
+                                                      T* __restrict__ sr0, T* __restrict__ sr1,
+                                                      T* __restrict__ srp) {
+    constexpr int kIt = (VR * VR + VNT - 1) / VNT;
+    const int ox = 2 * E0x - 4, oy = 2 * E0y - 4;
+    T v0[kIt], v1[kIt];
+    bool in[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int k = threadIdx.x + it * VNT;
+        const int qi = ox + k % VR, qj = oy + k / VR;
+        in[it] = k < VR * VR && qi >= 0 && qj >= 0 && qi < g.s2 && qj < g.s2;
+        const int64_t q = in[it] ? int64_t(qj) * g.s2 + qi : 0;
+        v0[it] = rb[q];
+        v1[it] = rb[g.nq2 + q];
+    }
+    const int I = E0x - 1 + threadIdx.x % VP, J = E0y - 1 + threadIdx.x / VP;
+    const bool valid = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
+    const T vp = rb[2 * g.nq2 + (valid ? int64_t(J) * g.s1 + I : 0)];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int k = threadIdx.x + it * VNT;
+        if (k < VR * VR) {
+            sr0[k] = in[it] ? scale * v0[it] : T(0);
+            sr1[k] = in[it] ? scale * v1[it] : T(0);
+        }
+    }
+    srp[threadIdx.x] = valid ? (scale * t) * vp : T(0);
+}
+
+// Owner update of a tile from the LDS row sums xs (entry e = (b*2 + c)*2 +
+// parity at xs[e * VNT + patch]): thread (tx, ty) < VT owns the Q2 nodes
+// (2E0+2tx+px, 2E0+2ty+py); Dirichlet nodes keep x_in.  Loads first.
+template <typename T>
+__device__ __forceinline__ void owner_update_velocity(const Geom& g, const T* __restrict__ xs,
+                                                      int E0x, int E0y, const T* xin, T* xout) {
+    const int tx = threadIdx.x % VP, ty = threadIdx.x / VP;
+    if (tx >= VT || ty >= VT) return;
+    const int gi0 = 2 * E0x + 2 * tx, gj0 = 2 * E0y + 2 * ty;
+    int64_t qn[2][2][2];
+    T base[2][2][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int px = 0; px < 2; ++px)
+#pragma unroll
+            for (int py = 0; py < 2; ++py) {
+                const int gi = gi0 + px, gj = gj0 + py;
+                const bool in = gi < g.s2 && gj < g.s2;
+                qn[c][px][py] = in ? int64_t(c) * g.nq2 + int64_t(gj) * g.s2 + gi : -1;
+                base[c][px][py] = xin ? xin[in ? qn[c][px][py] : 0] : T(0);
+            }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int px = 0; px < 2; ++px) {
+            auto at = [&](int b, int dty) {
+                return xs[((b * 2 + c) * 2 + px) * VNT + threadIdx.x + dty * VP];
+            };
+            const T even_row = at(4, 0) + at(2, 1) + at(0, 2);
+            const T odd_row = at(3, 1) + at(1, 2);
+            const int gi = gi0 + px;
+#pragma unroll
+            for (int py = 0; py < 2; ++py) {
+                const int gj = gj0 + py;
+                if (qn[c][px][py] < 0) continue;
+                const bool free = gi > 0 && gj > 0 && gi < g.s2 - 1 && gj < g.s2 - 1;
+                xout[qn[c][px][py]] = free ? base[c][px][py] + (py ? odd_row : even_row)
+                                           : base[c][px][py];
+            }
+        }
+}
+
+// One additive Vanka sweep on a tile given the residual r (`rb`) of x_in:
+// x_out = x_in + corrections, with x_in == x_out allowed (in place) and
+// x_in == nullptr meaning x_in = 0.  Every DoF a tile owns is written
+// (Dirichlet DoFs keep x_in).  The interior operator is applied to the
+// residual scaled by omega/nu (pressure also by t = nu/h), see sym_apply.
+template <typename T>
 __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __restrict__ rb,
                                                              const T* xin, T* xout,
                                                              const T* __restrict__ dbuf, T scale,
                                                              T t) {
-    __shared__ T s_buf[FROM_X ? kSweepLdsFromX : kSweepLdsGivenR];
-    T* const sr0 = s_buf + (FROM_X ? kXRegion : 0);
+    __shared__ T s_buf[kSweepLds];
+    T* const sr0 = s_buf;
     T* const sr1 = sr0 + VR * VR;
     T* const srp = sr1 + VR * VR;
     const int tiles = vanka_tiles(g.N);
@@ -534,81 +582,7 @@ __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __
     const int I = E0x - 1 + tx, J = E0y - 1 + ty;
     const bool valid = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
 
-    if (FROM_X) {
-        // stage x (Dirichlet columns and outside nodes zeroed)
-        T* const sx0 = s_buf;
-        T* const sx1 = s_buf + VX2 * VX2;
-        T* const sxp = s_buf + 2 * VX2 * VX2;
-        const int ox = 2 * E0x - 6, oy = 2 * E0y - 6;
-#pragma unroll
-        for (int it = 0; it < (VX2 * VX2 + VNT - 1) / VNT; ++it) {
-            const int k = threadIdx.x + it * VNT;
-            if (k < VX2 * VX2) {
-                const int qi = ox + k % VX2, qj = oy + k / VX2;
-                const bool free = qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
-                const int64_t q = int64_t(qj) * g.s2 + qi;
-                sx0[k] = free ? xin[q] : T(0);
-                sx1[k] = free ? xin[g.nq2 + q] : T(0);
-            }
-        }
-#pragma unroll
-        for (int it = 0; it < (VX1 * VX1 + VNT - 1) / VNT; ++it) {
-            const int k = threadIdx.x + it * VNT;
-            if (k < VX1 * VX1) {
-                const int Iq = E0x - 3 + k % VX1, Jq = E0y - 3 + k / VX1;
-                const bool in = Iq >= 0 && Jq >= 0 && Iq <= g.N && Jq <= g.N;
-                sxp[k] = in ? xin[2 * g.nq2 + int64_t(Jq) * g.s1 + Iq] : T(0);
-            }
-        }
-        __syncthreads();
-        // residual on the r region, one 2x2-node cell per thread and pass;
-        // cell (cx, cy) has its vertex at r-region node (2cx, 2cy)
-        const T cl = T(g.nu / 90.0), cb = T(-g.h / 36.0);
-        for (int c = threadIdx.x; c < kResidualCells * kResidualCells; c += VNT) {
-            const int cx = c % kResidualCells, cy = c / kResidualCells;
-            T ax[2][2], ay[2][2], ap;
-            cell_rows<VX2, VX1>(sx0, sx1, sxp, (2 * cy + 2) * VX2 + 2 * cx + 2,
-                                (cy + 1) * VX1 + cx + 1, cl, cb, ax, ay, ap);
-#pragma unroll
-            for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-                for (int aa = 0; aa < 2; ++aa) {
-                    const int u = 2 * cx + aa, v = 2 * cy + bb;
-                    if (u >= VR || v >= VR) continue;
-                    const int qi = 2 * E0x - 4 + u, qj = 2 * E0y - 4 + v;
-                    const bool free = qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
-                    T r0 = 0, r1 = 0;
-                    if (free) {
-                        const int64_t q = int64_t(qj) * g.s2 + qi;
-                        r0 = scale * (rb[q] - ax[bb][aa]);
-                        r1 = scale * (rb[g.nq2 + q] - ay[bb][aa]);
-                    }
-                    sr0[v * VR + u] = r0;
-                    sr1[v * VR + u] = r1;
-                }
-            if (cx >= 1 && cx <= VR1 && cy >= 1 && cy <= VR1) {
-                const int Iq = E0x - 2 + cx, Jq = E0y - 2 + cy;
-                T rp = 0;
-                if (Iq >= 0 && Jq >= 0 && Iq <= g.N && Jq <= g.N)
-                    rp = (scale * t) * (rb[2 * g.nq2 + int64_t(Jq) * g.s1 + Iq] - ap);
-                srp[(cy - 1) * VR1 + (cx - 1)] = rp;
-            }
-        }
-    } else {
-        const int ox = 2 * E0x - 4, oy = 2 * E0y - 4;
-#pragma unroll
-        for (int it = 0; it < (VR * VR + VNT - 1) / VNT; ++it) {
-            const int k = threadIdx.x + it * VNT;
-            if (k < VR * VR) {
-                const int qi = ox + k % VR, qj = oy + k / VR;
-                const bool in = qi >= 0 && qj >= 0 && qi < g.s2 && qj < g.s2;
-                const int64_t q = int64_t(qj) * g.s2 + qi;
-                sr0[k] = in ? scale * rb[q] : T(0);
-                sr1[k] = in ? scale * rb[g.nq2 + q] : T(0);
-            }
-        }
-        srp[threadIdx.x] = valid ? (scale * t) * rb[2 * g.nq2 + int64_t(J) * g.s1 + I] : T(0);
-    }
+    stage_residual_region(g, rb, E0x, E0y, scale, t, sr0, sr1, srp);
     __syncthreads();
 
     T rv[kSlots];
@@ -647,29 +621,7 @@ __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __
             xs[base + VNT + threadIdx.x] = od;
         }
     __syncthreads();
-    if (tx < VT && ty < VT) {
-        const int gi0 = 2 * E0x + 2 * tx, gj0 = 2 * E0y + 2 * ty;
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int px = 0; px < 2; ++px) {
-                auto at = [&](int b, int dty) {
-                    return xs[((b * 2 + c) * 2 + px) * VNT + threadIdx.x + dty * VP];
-                };
-                const T even_row = at(4, 0) + at(2, 1) + at(0, 2);
-                const T odd_row = at(3, 1) + at(1, 2);
-                const int gi = gi0 + px;
-#pragma unroll
-                for (int py = 0; py < 2; ++py) {
-                    const int gj = gj0 + py;
-                    if (gi >= g.s2 || gj >= g.s2) continue;
-                    const int64_t q = int64_t(c) * g.nq2 + int64_t(gj) * g.s2 + gi;
-                    const bool free = gi > 0 && gj > 0 && gi < g.s2 - 1 && gj < g.s2 - 1;
-                    const T base = xin ? xin[q] : T(0);
-                    xout[q] = free ? base + (py ? odd_row : even_row) : base;
-                }
-            }
-    }
+    owner_update_velocity(g, xs, E0x, E0y, xin, xout);
     if (valid && tx >= 1 && tx <= VT && ty >= 1 && ty <= VT) {
         const int64_t q = 2 * g.nq2 + int64_t(J) * g.s1 + I;
         xout[q] = (xin ? xin[q] : T(0)) + rv[50];
@@ -677,23 +629,184 @@ __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __
 }
 
 // ---------------------------------------------------------------------------
+// Vanka update with the interior apply on the 16x16x4 matrix instructions
+// (mfma_patch.h).  Same tile, staging, boundary handling and owner sums as
+// vanka_sweep_kernel; wave w processes the patch rows 4w..4w+3 of the tile
+// in four rounds of 16 patches, lane l serving patch column l % 16 and
+// quarter q = l / 16 of the patch slots.  After the inverse butterflies a
+// quarter holds complete rows of its component (u_x rows b, 4-b for q < 2;
+// u_y rows b, 4-b for q >= 2 with the centre column taken from quarter
+// q - 2 by a cross-half shuffle) or the centre row 2 pieces (q >= 2), so
+// the x-sums are DPP row shifts as before; each lane then writes six of the
+// 21 per-patch row sums (and unused values to a dummy entry) into the LDS
+// exchange, which the owners read after one barrier.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct Mfma16;
+template <>
+struct Mfma16<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 step(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma16<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 step(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int kExchangeEntries = 22;  // 20 row sums, pressure, dummy
+constexpr int kMfmaLds = kRRegion + kExchangeEntries * VNT;
+
+template <typename T>
+__global__ __launch_bounds__(VNT, 2) void vanka_mfma_kernel(Geom g, const T* __restrict__ rb,
+                                                            const T* xin, T* xout,
+                                                            const T* __restrict__ dbuf,
+                                                            const T* __restrict__ mtab, T scale,
+                                                            T t) {
+    __shared__ T s_buf[kMfmaLds];
+    T* const sr0 = s_buf;
+    T* const sr1 = sr0 + VR * VR;
+    T* const srp = sr1 + VR * VR;
+    T* const xs = s_buf + kRRegion;
+    const int tiles = vanka_tiles(g.N);
+    const int ntile = tiles * tiles;
+    const int per_xcd = (ntile + 7) / 8;
+    const int tlin = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (tlin >= ntile) return;
+    const int E0x = (tlin % tiles) * VT, E0y = (tlin / tiles) * VT;
+
+    // operands of the universal interior operator (one per lane and step)
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T a_op[4][4];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a_op[blk][c] = mtab[(blk * 4 + c) * 64 + lane];
+
+    stage_residual_region(g, rb, E0x, E0y, scale, t, sr0, sr1, srp);
+
+    // per-lane LDS offsets of the quarter's 15 slots for the first round
+    // (patch row 4w); later rounds add 2 VR (velocity) or VP (pressure)
+    const int j = lane & 15, q = lane >> 4;
+    int off[kQuarterValues], slot[kQuarterValues];
+#pragma unroll
+    for (int k = 0; k < kQuarterValues; ++k) {
+        slot[k] = quarter_slot(q, k);
+        if (k == 12) {
+            off[k] = 2 * VR * VR + (4 * w) * VP + j;  // the pressure slot
+        } else {
+            const int f = slot[k] / 25, rem = slot[k] % 25;
+            off[k] = f * VR * VR + (2 * (4 * w) + rem / 5) * VR + 2 * j + rem % 5;
+        }
+    }
+    // exchange entries written by this quarter: rows b and 4-b of its
+    // component (even, odd), then two row-2 pieces, pressure or dummy
+    const int fq = q >> 1, bq = q & 1;
+    int ent[6];
+    ent[0] = (bq * 2 + fq) * 2;
+    ent[1] = ent[0] + 1;
+    ent[2] = ((4 - bq) * 2 + fq) * 2;
+    ent[3] = ent[2] + 1;
+    ent[4] = q == 0 ? 20 : q == 1 ? 21 : (2 * 2 + 0) * 2 + (q - 2);
+    ent[5] = q < 2 ? 21 : (2 * 2 + 1) * 2 + (q - 2);
+    __syncthreads();
+
+    typedef typename Mfma16<T>::v4 v4;
+#pragma unroll
+    for (int rho = 0; rho < 4; ++rho) {
+        const int ty = 4 * w + rho;
+        T in[kQuarterValues];
+#pragma unroll
+        for (int k = 0; k < kQuarterValues; ++k)
+            in[k] = s_buf[off[k] + rho * (k == 12 ? VP : 2 * VR)];
+        T B[4][4];
+        quarter_forward(q, in, B);
+        T D[4][4];
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) {
+            v4 acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc = Mfma16<T>::step(a_op[blk][c], B[blk][c], acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) D[blk][v] = acc[v];
+        }
+        T out[kQuarterValues];
+        quarter_inverse(q, D, t, out);
+
+        const int I = E0x - 1 + j, J = E0y - 1 + ty;
+        const bool valid = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
+        const bool interior = valid && I >= 2 && J >= 2 && I <= g.N - 2 && J <= g.N - 2;
+        if (!interior) {
+            // boundary patch: corrections precomputed; outside the domain:
+            // none (patch 0's values, which exist, times zero)
+            const int bi = valid ? boundary_index(I, J, g.N) : 0;
+            const T m = valid ? T(1) : T(0);
+            const T* __restrict__ src = dbuf + int64_t(bi) * 64;
+#pragma unroll
+            for (int k = 0; k < kQuarterValues; ++k) out[k] = m * src[slot[k]];
+        }
+        // centre column of rows b, 4-b: own u_x values (q < 2) or the u_y
+        // values of quarter q - 2; centre node of row 2 from quarter 0
+        const T o10 = __shfl_xor(out[10], 32);
+        const T o11 = __shfl_xor(out[11], 32);
+        const T cx = __shfl_xor(q == 0 ? out[13] : T(0), 32);
+        const T cy = __shfl_xor(q == 0 ? out[14] : T(0), 32);
+        const T c1 = q < 2 ? out[8] : o10;
+        const T c2 = q < 2 ? out[9] : o11;
+        T val[6];
+        val[0] = out[1] + row_shl<1>(c1) + row_shl<2>(out[0]);
+        val[1] = row_shl<1>(out[5]) + row_shl<2>(out[4]);
+        val[2] = out[3] + row_shl<1>(c2) + row_shl<2>(out[2]);
+        val[3] = row_shl<1>(out[7]) + row_shl<2>(out[6]);
+        const T sh9 = row_shl<1>(out[9]), sh11 = row_shl<1>(out[11]);
+        const T rx = row_shl<2>(out[8]) + (q == 2 ? out[9] : sh9) + row_shl<1>(cx);
+        const T ry = row_shl<2>(out[10]) + (q == 2 ? out[11] : sh11) + row_shl<1>(cy);
+        val[4] = q == 0 ? out[12] : rx;
+        val[5] = ry;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) xs[ent[m] * VNT + ty * VP + j] = val[m];
+    }
+    __syncthreads();
+
+    owner_update_velocity(g, xs, E0x, E0y, xin, xout);
+    const int tx = threadIdx.x % VP, ty = threadIdx.x / VP;
+    const int I = E0x - 1 + tx, J = E0y - 1 + ty;
+    const bool valid = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
+    if (valid && tx >= 1 && tx <= VT && ty >= 1 && ty <= VT) {
+        const int64_t qn = 2 * g.nq2 + int64_t(J) * g.s1 + I;
+        xout[qn] = (xin ? xin[qn] : T(0)) + xs[20 * VNT + threadIdx.x];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Transfers
 // ---------------------------------------------------------------------------
 
-// 1D restriction weights of coarse Q2 node ic from fine offsets.
-__device__ __forceinline__ int q2_restrict_taps(int ic, int (&off)[5], double (&w)[5]) {
+// Transfer kernels issue every load before the first use: taps are padded
+// to a fixed count with zero weights, and taps that fall on Dirichlet or
+// outside nodes read node 0 and get weight zero.
+
+// 1D restriction taps of coarse Q2 node ic: fine offsets and weights (the
+// transpose of the Q2 interpolation), padded to five.
+__device__ __forceinline__ void q2_restrict_taps(int ic, int (&off)[5], double (&w)[5]) {
     if ((ic & 1) == 0) {
         off[0] = -3; w[0] = -0.125;
         off[1] = -1; w[1] = 0.375;
         off[2] = 0;  w[2] = 1.0;
         off[3] = 1;  w[3] = 0.375;
         off[4] = 3;  w[4] = -0.125;
-        return 5;
+    } else {
+        off[0] = -1; w[0] = 0.75;
+        off[1] = 0;  w[1] = 1.0;
+        off[2] = 1;  w[2] = 0.75;
+        off[3] = 0;  w[3] = 0.0;
+        off[4] = 0;  w[4] = 0.0;
     }
-    off[0] = -1; w[0] = 0.75;
-    off[1] = 0;  w[1] = 1.0;
-    off[2] = 1;  w[2] = 0.75;
-    return 3;
 }
 
 template <typename T>
@@ -703,53 +816,74 @@ __global__ __launch_bounds__(256) void restrict_kernel(Geom gf, Geom gc, const T
     const int jc = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (ic < gc.s2 && jc < gc.s2) {
         const int64_t qc = int64_t(jc) * gc.s2 + ic;
-        T sx = 0, sy = 0;
-        if (!q2_boundary(ic, jc, gc.s2)) {
-            int ox[5], oy[5];
-            double wx[5], wy[5];
-            const int nx = q2_restrict_taps(ic, ox, wx);
-            const int ny = q2_restrict_taps(jc, oy, wy);
-            for (int b = 0; b < ny; ++b) {
-                const int jf = 2 * jc + oy[b];
-                T tx = 0, ty = 0;
-                for (int a = 0; a < nx; ++a) {
-                    const int i_f = 2 * ic + ox[a];
-                    if (q2_boundary(i_f, jf, gf.s2)) continue;
-                    const int64_t qf = int64_t(jf) * gf.s2 + i_f;
-                    tx += T(wx[a]) * rf[qf];
-                    ty += T(wx[a]) * rf[gf.nq2 + qf];
-                }
-                sx += T(wy[b]) * tx;
-                sy += T(wy[b]) * ty;
+        const bool inner = !q2_boundary(ic, jc, gc.s2);
+        int ox[5], oy[5];
+        double wx[5], wy[5];
+        q2_restrict_taps(ic, ox, wx);
+        q2_restrict_taps(jc, oy, wy);
+        T vx[5][5], vy[5][5];
+        bool ok[5][5];
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                const int i_f = 2 * ic + ox[a], jf = 2 * jc + oy[b];
+                ok[b][a] = inner && i_f > 0 && jf > 0 && i_f < gf.s2 - 1 && jf < gf.s2 - 1;
+                const int64_t qf = ok[b][a] ? int64_t(jf) * gf.s2 + i_f : 0;
+                vx[b][a] = rf[qf];
+                vy[b][a] = rf[gf.nq2 + qf];
             }
+        T sx = 0, sy = 0;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            T tx = 0, ty = 0;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                const T wa = ok[b][a] ? T(wx[a]) : T(0);
+                tx += wa * vx[b][a];
+                ty += wa * vy[b][a];
+            }
+            sx += T(wy[b]) * tx;
+            sy += T(wy[b]) * ty;
         }
         bc[qc] = sx;
         bc[gc.nq2 + qc] = sy;
     }
     if (ic < gc.s1 && jc < gc.s1) {
-        T s = 0;
-        for (int oyy = -1; oyy <= 1; ++oyy) {
-            const int jf = 2 * jc + oyy;
-            if (jf < 0 || jf >= gf.s1) continue;
-            const T wy = oyy == 0 ? T(1) : T(0.5);
-            T t = 0;
-            for (int oxx = -1; oxx <= 1; ++oxx) {
-                const int i_f = 2 * ic + oxx;
-                if (i_f < 0 || i_f >= gf.s1) continue;
-                const T wx = oxx == 0 ? T(1) : T(0.5);
-                t += wx * rf[2 * gf.nq2 + int64_t(jf) * gf.s1 + i_f];
+        T v[3][3];
+        bool ok[3][3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int i_f = 2 * ic + a - 1, jf = 2 * jc + b - 1;
+                ok[b][a] = i_f >= 0 && jf >= 0 && i_f < gf.s1 && jf < gf.s1;
+                v[b][a] = rf[2 * gf.nq2 + (ok[b][a] ? int64_t(jf) * gf.s1 + i_f : 0)];
             }
-            s += wy * t;
+        T s = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const T wyb = b == 1 ? T(1) : T(0.5);
+            T t = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const T wxa = a == 1 ? T(1) : T(0.5);
+                t += ok[b][a] ? wxa * v[b][a] : T(0);
+            }
+            s += wyb * t;
         }
         bc[2 * gc.nq2 + int64_t(jc) * gc.s1 + ic] = s;
     }
 }
 
-// 1D interpolation taps of fine Q2 node i from coarse Q2 nodes.
-__device__ __forceinline__ int q2_prolong_taps(int i, int (&c)[3], double (&w)[3]) {
+// 1D interpolation taps of fine Q2 node i from coarse Q2 nodes, padded to
+// three (a fine node on a coarse node has one tap of weight 1).
+__device__ __forceinline__ void q2_prolong_taps(int i, int (&c)[3], double (&w)[3]) {
     if ((i & 1) == 0) {
         c[0] = i / 2; w[0] = 1.0;
-        return 1;
+        c[1] = i / 2; w[1] = 0.0;
+        c[2] = i / 2; w[2] = 0.0;
+        return;
     }
     const int e = i / 4;  // coarse element
     c[0] = 2 * e; c[1] = 2 * e + 1; c[2] = 2 * e + 2;
@@ -758,7 +892,6 @@ __device__ __forceinline__ int q2_prolong_taps(int i, int (&c)[3], double (&w)[3
     } else {
         w[0] = -0.125; w[1] = 0.75; w[2] = 0.375;
     }
-    return 3;
 }
 
 template <typename T>
@@ -769,39 +902,55 @@ __global__ __launch_bounds__(256) void prolong_kernel(Geom gf, Geom gc, const T*
     if (i < gf.s2 && j < gf.s2 && !q2_boundary(i, j, gf.s2)) {
         int cx[3], cy[3];
         double wx[3], wy[3];
-        const int nx = q2_prolong_taps(i, cx, wx);
-        const int ny = q2_prolong_taps(j, cy, wy);
+        q2_prolong_taps(i, cx, wx);
+        q2_prolong_taps(j, cy, wy);
+        const int64_t q = int64_t(j) * gf.s2 + i;
+        const T x0 = xf[q], x1 = xf[gf.nq2 + q];
+        T vx[3][3], vy[3][3];
+        bool ok[3][3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ok[b][a] = !q2_boundary(cx[a], cy[b], gc.s2);
+                const int64_t qc = ok[b][a] ? int64_t(cy[b]) * gc.s2 + cx[a] : 0;
+                vx[b][a] = ec[qc];
+                vy[b][a] = ec[gc.nq2 + qc];
+            }
         T sx = 0, sy = 0;
-        for (int b = 0; b < ny; ++b) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
             T tx = 0, ty = 0;
-            for (int a = 0; a < nx; ++a) {
-                if (q2_boundary(cx[a], cy[b], gc.s2)) continue;
-                const int64_t qc = int64_t(cy[b]) * gc.s2 + cx[a];
-                tx += T(wx[a]) * ec[qc];
-                ty += T(wx[a]) * ec[gc.nq2 + qc];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const T wa = ok[b][a] ? T(wx[a]) : T(0);
+                tx += wa * vx[b][a];
+                ty += wa * vy[b][a];
             }
             sx += T(wy[b]) * tx;
             sy += T(wy[b]) * ty;
         }
-        const int64_t q = int64_t(j) * gf.s2 + i;
-        xf[q] += sx;
-        xf[gf.nq2 + q] += sy;
+        xf[q] = x0 + sx;
+        xf[gf.nq2 + q] = x1 + sy;
     }
     if (i < gf.s1 && j < gf.s1) {
         const int i0 = i / 2, i1 = (i + 1) / 2, j0 = j / 2, j1 = (j + 1) / 2;
         const T* pc = ec + 2 * gc.nq2;
+        const int64_t qf = 2 * gf.nq2 + int64_t(j) * gf.s1 + i;
+        const T xp = xf[qf];
+        const T p00 = pc[int64_t(j0) * gc.s1 + i0], p01 = pc[int64_t(j0) * gc.s1 + i1];
+        const T p10 = pc[int64_t(j1) * gc.s1 + i0], p11 = pc[int64_t(j1) * gc.s1 + i1];
         T v;
         if ((i & 1) == 0 && (j & 1) == 0) {
-            v = pc[int64_t(j0) * gc.s1 + i0];
+            v = p00;
         } else if ((j & 1) == 0) {
-            v = T(0.5) * (pc[int64_t(j0) * gc.s1 + i0] + pc[int64_t(j0) * gc.s1 + i1]);
+            v = T(0.5) * (p00 + p01);
         } else if ((i & 1) == 0) {
-            v = T(0.5) * (pc[int64_t(j0) * gc.s1 + i0] + pc[int64_t(j1) * gc.s1 + i0]);
+            v = T(0.5) * (p00 + p10);
         } else {
-            v = T(0.25) * ((pc[int64_t(j0) * gc.s1 + i0] + pc[int64_t(j0) * gc.s1 + i1]) +
-                           (pc[int64_t(j1) * gc.s1 + i0] + pc[int64_t(j1) * gc.s1 + i1]));
+            v = T(0.25) * ((p00 + p01) + (p10 + p11));
         }
-        xf[2 * gf.nq2 + int64_t(j) * gf.s1 + i] += v;
+        xf[qf] = xp + v;
     }
 }
 
@@ -1040,41 +1189,25 @@ void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hip
 int64_t vanka_boundary_scratch(int N) { return int64_t(n_boundary_patches(N)) * 64; }
 
 template <typename T>
-void launch_vanka_update(const Geom& g, const T* r, T* x, const T* table, T* dbuf, double omega,
-                         hipStream_t s) {
+void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const T* table,
+                         const T* mtab, T* dbuf, double omega, bool mfma, hipStream_t s) {
     const int nb = n_boundary_patches(g.N);
-    vanka_boundary_kernel<T, false><<<(nb + 3) / 4, 256, 0, s>>>(g, r, nullptr, table, dbuf);
-    const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
-    vanka_sweep_kernel<T, false><<<8 * ((ntile + 7) / 8), VNT, 0, s>>>(
-        g, r, x, x, dbuf, T(omega / g.nu), T(g.nu / g.h));
-}
-
-template <typename T>
-void launch_vanka_sweep(const Geom& g, const T* b, const T* xin, T* xout, const T* table, T* dbuf,
-                        double omega, hipStream_t s) {
-    const int nb = n_boundary_patches(g.N);
+    vanka_boundary_kernel<T><<<(nb + 3) / 4, 256, 0, s>>>(g, r, table, dbuf);
     const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
     const int grid = 8 * ((ntile + 7) / 8);
-    if (xin == nullptr) {
-        // x = 0: the residual is b
-        vanka_boundary_kernel<T, false><<<(nb + 3) / 4, 256, 0, s>>>(g, b, nullptr, table, dbuf);
-        vanka_sweep_kernel<T, false><<<grid, VNT, 0, s>>>(g, b, nullptr, xout, dbuf,
-                                                           T(omega / g.nu), T(g.nu / g.h));
-    } else {
-        vanka_boundary_kernel<T, true><<<(nb + 3) / 4, 256, 0, s>>>(g, b, xin, table, dbuf);
-        vanka_sweep_kernel<T, true><<<grid, VNT, 0, s>>>(g, b, xin, xout, dbuf, T(omega / g.nu),
-                                                          T(g.nu / g.h));
-    }
+    if (mfma)
+        vanka_mfma_kernel<T><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf, mtab, T(omega / g.nu),
+                                                  T(g.nu / g.h));
+    else
+        vanka_sweep_kernel<T><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf, T(omega / g.nu),
+                                                   T(g.nu / g.h));
 }
-template void launch_vanka_sweep<double>(const Geom&, const double*, const double*, double*,
-                                         const double*, double*, double, hipStream_t);
-template void launch_vanka_sweep<float>(const Geom&, const float*, const float*, float*,
-                                        const float*, float*, double, hipStream_t);
-
-template void launch_vanka_update<double>(const Geom&, const double*, double*, const double*,
-                                          double*, double, hipStream_t);
-template void launch_vanka_update<float>(const Geom&, const float*, float*, const float*, float*,
-                                         double, hipStream_t);
+template void launch_vanka_update<double>(const Geom&, const double*, const double*, double*,
+                                          const double*, const double*, double*, double, bool,
+                                          hipStream_t);
+template void launch_vanka_update<float>(const Geom&, const float*, const float*, float*,
+                                         const float*, const float*, float*, double, bool,
+                                         hipStream_t);
 
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, hipStream_t s) {

@@ -68,6 +68,15 @@ bool universal_interior_blocks(double* B1);
 double universal_mismatch(const double* Blevel, const double* B1, double omega, double nu,
                           double h);
 
+// Operand table of the matrix-instruction interior apply (mfma_patch.h):
+// A[(blk * 4 + c) * 64 + lane] = entry (row lane % 16, column 4c + lane / 16)
+// of block blk of W1, rows and columns ordered by quarter items.  The
+// output rows of the 16x16x4 instructions are spread differently over the
+// lanes in FP64 (row i in quarter i % 4, element i / 4) and FP32 (quarter
+// i / 4, element i % 4); the row order follows `fp64_layout`.
+constexpr int kMfmaTable = 4 * 4 * 64;
+void mfma_interior_table(const double* B1, bool fp64_layout, double* A);
+
 // Per-level device table of patch operators: the 25 dense weighted inverses
 // (51 x 51 each) followed by the 651 reflection-block values of the
 // interior one.

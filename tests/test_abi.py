@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options_and_status_strings():
     lib = vk.load_library()
     o = lib.vkmg_default_options()
-    assert (o.nu_pre, o.nu_post, o.omega, o.mg_precision) == (2, 2, 0.5, 0)
+    assert (o.nu_pre, o.nu_post, o.omega, o.mg_precision, o.interior_apply) == (2, 2, 0.5, 0, 0)
     for s in range(8):
         assert lib.vkmg_status_string(s)
 
@@ -57,6 +57,20 @@ def test_setup_rejects_bad_arguments_before_any_gpu_work(kwargs, status):
     assert st == status
     assert lib.vkmg_last_error()
     assert not ctx.value
+
+
+@pytest.mark.parametrize("field,value", [("mg_precision", 2), ("interior_apply", 2),
+                                         ("omega", 0.0), ("nu_pre", -1)])
+def test_setup_rejects_bad_options(field, value):
+    lib = vk.load_library()
+    from paper_2401_06277_amd._vkmg import Grid
+    o = lib.vkmg_default_options()
+    setattr(o, field, value)
+    ctx = ctypes.c_void_p()
+    st = lib.vkmg_setup(ctypes.byref(Grid(16, 16)), 3, 1.0, ctypes.byref(o), None,
+                        ctypes.byref(ctx))
+    assert st == 1 and not ctx.value
+    assert lib.vkmg_last_error()
 
 
 def test_null_arguments_are_rejected():

@@ -54,11 +54,11 @@ def _device():
 _solvers = {}
 
 
-def solver(N=N_FULL, levels=LEVELS_FULL, precision="fp64"):
-    key = (N, levels, precision)
+def solver(N=N_FULL, levels=LEVELS_FULL, precision="fp64", apply="vector"):
+    key = (N, levels, precision, apply)
     if key not in _solvers:
-        note(f"setup N={N} levels={levels} {precision}")
-        _solvers[key] = vk.VkmgSolver(N, levels, precision=precision)
+        note(f"setup N={N} levels={levels} {precision} {apply}")
+        _solvers[key] = vk.VkmgSolver(N, levels, precision=precision, interior_apply=apply)
     return _solvers[key]
 
 
@@ -100,13 +100,14 @@ def test_fullsize_residual_sampled_rows():
     close(r[rows], fem.residual_rows(N_FULL, x, b, rows), 1e-13)
 
 
-@pytest.mark.parametrize("level", [LEVELS_FULL - 1, LEVELS_FULL - 2, 1])
-def test_fullsize_vanka_sweep_sampled(level):
-    s = solver()
+@pytest.mark.parametrize("level,apply", [(LEVELS_FULL - 1, "vector"), (LEVELS_FULL - 2, "vector"),
+                                         (1, "vector"), (LEVELS_FULL - 1, "matrix")])
+def test_fullsize_vanka_sweep_sampled(level, apply):
+    s = solver(apply=apply)
     Nl = N_FULL >> (LEVELS_FULL - 1 - level)
     x, b = dirichlet_consistent_pair(Nl, 110 + level, 120 + level)
     dofs = sample_dofs(Nl, 130 + level, 40)
-    note(f"vanka sweep level={level} N_l={Nl}: {len(dofs)} sampled DoFs")
+    note(f"vanka sweep ({apply}) level={level} N_l={Nl}: {len(dofs)} sampled DoFs")
     xg = dev(x)
     s.vanka_sweep(level, xg, dev(b))
     xn = host(xg)

@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-N", type=int, default=256)
     ap.add_argument("--cpu-levels", type=int, default=6)
-    ap.add_argument("--cpu-vcycles", type=int, default=5)
+    ap.add_argument("--cpu-vcycles", type=int, default=60)
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--interior-apply", choices=["vector", "matrix"], default="vector",
                     help="interior Vanka apply: vector ALUs (default) or matrix cores")

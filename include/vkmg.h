@@ -75,6 +75,11 @@ typedef struct {
     double omega;                /* Vanka damping (default 0.5) */
     vkmg_precision mg_precision; /* arithmetic of the whole V-cycle (default FP64) */
     vkmg_interior_apply interior_apply; /* default VKMG_APPLY_VECTOR */
+    int32_t use_graphs;          /* 1 (default): vkmg_fgmres_solve replays each Arnoldi step
+                                    (V-cycle, A z, Gram-Schmidt kernels) as a HIP graph
+                                    captured at its first use; 0: direct launches.  Graphs
+                                    are bypassed while kernel timing is enabled (events in
+                                    a replayed graph cannot be read back). */
 } vkmg_options;
 
 typedef struct {

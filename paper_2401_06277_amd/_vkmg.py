@@ -53,7 +53,7 @@ class Grid(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("nu_pre", c_int32), ("nu_post", c_int32), ("omega", c_double),
-                ("mg_precision", c_int32), ("interior_apply", c_int32)]
+                ("mg_precision", c_int32), ("interior_apply", c_int32), ("use_graphs", c_int32)]
 
 
 class Layout(ctypes.Structure):
@@ -147,7 +147,8 @@ class VkmgSolver:
     problem on the current HIP device."""
 
     def __init__(self, N: int, levels: int, nu: float = 1.0, nu_pre: int = 2, nu_post: int = 2,
-                 omega: float = 0.5, precision: str = "fp64", interior_apply: str = "vector"):
+                 omega: float = 0.5, precision: str = "fp64", interior_apply: str = "vector",
+                 graphs: bool = True):
         import torch
         lib = load_library()
         self._torch = torch
@@ -156,7 +157,7 @@ class VkmgSolver:
         if interior_apply not in APPLY:
             raise ValueError(f"interior_apply must be one of {sorted(APPLY)}")
         opts = Options(nu_pre, nu_post, omega, FP32 if precision == "fp32" else FP64,
-                       APPLY[interior_apply])
+                       APPLY[interior_apply], 1 if graphs else 0)
         ctx = c_void_p()
         st = lib.vkmg_setup(byref(Grid(N, N)), levels, nu, byref(opts), self._stream(),
                             byref(ctx))

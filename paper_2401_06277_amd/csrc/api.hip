@@ -71,6 +71,10 @@ struct vkmg_ctx {
     };
     std::vector<EventPair> events[VKMG_KERNEL_COUNT];
     std::vector<void*> allocations;
+    // executable graphs of the Arnoldi steps (index j), valid for the
+    // current basis allocation; captured on a private stream
+    std::vector<hipGraphExec_t> step_graphs;
+    hipStream_t capture_stream = nullptr;
 
     size_t esize() const { return opt.mg_precision == VKMG_FP32 ? 4 : 8; }
     const Geom& top() const { return lev.back().g; }
@@ -102,6 +106,12 @@ struct Timed {
     }
 };
 
+void drop_graphs(vkmg_ctx* c) {
+    for (hipGraphExec_t g : c->step_graphs)
+        if (g) (void)hipGraphExecDestroy(g);
+    c->step_graphs.clear();
+}
+
 vkmg_status alloc(vkmg_ctx* c, void** p, size_t bytes) {
     VKMG_HIP(hipMalloc(p, bytes < 256 ? 256 : bytes));
     c->allocations.push_back(*p);
@@ -119,6 +129,9 @@ void free_all(vkmg_ctx* c) {
             (void)hipEventDestroy(e.start);
             (void)hipEventDestroy(e.stop);
         }
+    drop_graphs(c);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    c->capture_stream = nullptr;
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -233,6 +246,8 @@ int64_t basis_stride(int64_t n) { return (n + 63) / 64 * 64; }
 vkmg_status ensure_basis(vkmg_ctx* c, int m) {
     if (m <= c->basis_cap) return VKMG_OK;
     const int64_t n = basis_stride(c->top().n);
+    // captured Arnoldi steps refer to the old basis
+    drop_graphs(c);
     // release the old basis (kept in the allocation list until destroy otherwise)
     for (void* p : {static_cast<void*>(c->V), static_cast<void*>(c->Z)}) {
         if (!p) continue;
@@ -247,6 +262,32 @@ vkmg_status ensure_basis(vkmg_ctx* c, int m) {
     st = alloc(c, reinterpret_cast<void**>(&c->Z), size_t(m) * n * sizeof(double));
     if (st != VKMG_OK) return st;
     c->basis_cap = m;
+    return VKMG_OK;
+}
+
+// Executable graph of Arnoldi step j, captured on the context's private
+// stream the first time it is needed (a graph may then be launched on any
+// stream, including the legacy default one, which cannot be captured).
+template <typename F>
+vkmg_status step_graph(vkmg_ctx* c, int j, F&& step) {
+    if (int(c->step_graphs.size()) <= j) c->step_graphs.resize(j + 1, nullptr);
+    if (c->step_graphs[j]) return VKMG_OK;
+    if (!c->capture_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(VKMG_ERR_HIP, std::string("graph stream: ") + hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(VKMG_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(e));
+    step(j, c->capture_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(c->capture_stream, &graph);
+    if (e != hipSuccess || !graph)
+        return fail(VKMG_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(VKMG_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e));
+    c->step_graphs[j] = exec;
     return VKMG_OK;
 }
 
@@ -269,6 +310,7 @@ vkmg_options vkmg_default_options(void) {
     o.omega = 0.5;
     o.mg_precision = VKMG_FP64;
     o.interior_apply = VKMG_APPLY_VECTOR;
+    o.use_graphs = 1;
     return o;
 }
 
@@ -333,6 +375,8 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         return fail(VKMG_ERR_INVALID_ARG, "setup: bad mg_precision");
     if (o.interior_apply != VKMG_APPLY_MATRIX && o.interior_apply != VKMG_APPLY_VECTOR)
         return fail(VKMG_ERR_INVALID_ARG, "setup: bad interior_apply");
+    if (o.use_graphs != 0 && o.use_graphs != 1)
+        return fail(VKMG_ERR_INVALID_ARG, "setup: use_graphs must be 0 or 1");
 
     // host work first (no GPU needed to detect singular patches)
     double B1[651];
@@ -623,6 +667,46 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
     double est = 1.0;
     double* h1 = ctx->hdev;        // first Gram-Schmidt pass, j+1 values
     double* h2 = ctx->hdev + 300;  // second pass, j+1 values, then ||w||^2 at [j+1]
+    // Device work of Arnoldi step j (no host synchronisation): z_j = M v_j,
+    // w = A z_j, then classical Gram-Schmidt twice (Giraud et al.'s CGS2):
+    //   h1 = V^T w;  w' = w - V h1 with h2 = V^T w' and |w'|^2 in the same
+    //   pass;  v_{j+1} = (w' - V h2) / |w' - V h2| in a third, with
+    //   |w' - V h2|^2 = |w'|^2 - |h2|^2 (V orthonormal).  Beyond 32 basis
+    //   vectors: unfused passes, |w''|^2 into h2[kb], v_{j+1} scaled on host
+    //   request.  Every pointer depends only on j, so the step can be
+    //   captured once per j and replayed.
+    auto arnoldi_step = [&](int j, hipStream_t ss) {
+        double* vj = V + int64_t(j) * ld;
+        double* zj = Z + int64_t(j) * ld;
+        const int kb = j + 1;
+        vcycle_impl(ctx, vj, zj, ss);
+        {
+            Timed t(ctx, VKMG_KERNEL_RESIDUAL, ss);
+            launch_residual<double, double>(g, nullptr, zj, w, 1, ss);
+        }
+        dots_async(ctx, V, ld, kb, w, h1, ss);
+        if (kb <= 32) {
+            Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);
+            launch_update_dot(V, ld, kb, h1, w, n, ctx->part, ss);
+            launch_reduce_partials(ctx->part, kb + 1, h2, ss);
+            launch_normalize(V, ld, kb, h2, h2 + kb, w, V + int64_t(kb) * ld, n, ss);
+        } else {
+            {
+                Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);
+                launch_update(V, ld, kb, h1, w, n, ss);
+            }
+            dots_async(ctx, V, ld, kb, w, h2, ss);
+            {
+                Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);
+                launch_update(V, ld, kb, h2, w, n, ss);
+            }
+            dots_async(ctx, w, 0, 1, w, h2 + kb, ss);
+        }
+    };
+    // graphs replace the ~100 launches of a step by one; bypassed while
+    // kernels are timed (events recorded inside a replayed graph cannot be
+    // read back with hipEventElapsedTime)
+    const bool use_graphs = ctx->opt.use_graphs != 0 && ctx->timing_mask == 0;
     for (;;) {
         {
             Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
@@ -633,40 +717,15 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
         gv[0] = beta;
         int k = 0;
         for (int j = 0; j < m; ++j) {
-            double* vj = V + int64_t(j) * ld;
-            double* zj = Z + int64_t(j) * ld;
-            vcycle_impl(ctx, vj, zj, s);
-            {
-                Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
-                launch_residual<double, double>(g, nullptr, zj, w, 1, s);
-            }
-            // classical Gram-Schmidt, twice (Giraud et al.'s CGS2):
-            //   h1 = V^T w;  w' = w - V h1 with h2 = V^T w' and |w'|^2 in the
-            //   same pass;  v_{j+1} = (w' - V h2) / |w' - V h2| in a third,
-            //   with |w' - V h2|^2 = |w'|^2 - |h2|^2 (V orthonormal).
             const int kb = j + 1;  // basis vectors so far
-            bool normalized = false;
+            const bool normalized = kb <= 32;
             double hnext = 0.0;
-            dots_async(ctx, V, ld, kb, w, h1, s);
-            if (kb <= 32) {
-                {
-                    Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
-                    launch_update_dot(V, ld, kb, h1, w, n, ctx->part, s);
-                    launch_reduce_partials(ctx->part, kb + 1, h2, s);
-                    launch_normalize(V, ld, kb, h2, h2 + kb, w, V + int64_t(kb) * ld, n, s);
-                }
-                normalized = true;
+            if (use_graphs) {
+                st = step_graph(ctx, j, arnoldi_step);
+                if (st != VKMG_OK) return st;
+                VKMG_HIP(hipGraphLaunch(ctx->step_graphs[j], s));
             } else {
-                {
-                    Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
-                    launch_update(V, ld, kb, h1, w, n, s);
-                }
-                dots_async(ctx, V, ld, kb, w, h2, s);
-                {
-                    Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
-                    launch_update(V, ld, kb, h2, w, n, s);
-                }
-                dots_async(ctx, w, 0, 1, w, h2 + kb, s);
+                arnoldi_step(j, s);
             }
             VKMG_HIP(hipMemcpyAsync(ctx->hhost, h1, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
             VKMG_HIP(hipMemcpyAsync(ctx->hhost + 300, h2, sizeof(double) * (kb + 1), hipMemcpyDeviceToHost, s));

@@ -240,6 +240,39 @@ def test_fgmres_iterations_and_solution(N, levels, name):
     assert np.linalg.norm(xa - xo) <= 1e-10 * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fgmres_graph_replays_match_direct_launches(precision):
+    """Each Arnoldi step replayed as a captured graph gives bitwise the same
+    iterates as direct launches, across replays separated by eager work,
+    restart lengths that reallocate the basis (recapture) and steps beyond
+    32 basis vectors (unfused Gram-Schmidt)."""
+    N, levels = 32, 4
+    sg = vk.VkmgSolver(N, levels, precision=precision, graphs=True)
+    sd = vk.VkmgSolver(N, levels, precision=precision, graphs=False)
+    _, b, xl, _ = _manufactured_system(N)
+    bg = dev(b)
+    for rtol, restart, iters in [(1e-10, 8, 200), (0.0, 40, 36), (1e-10, 8, 200), (1e-10, 8, 200)]:
+        note(f"graphs {precision} rtol={rtol} restart={restart}")
+        xg, xd = dev(xl), dev(xl)
+        ig = sg.fgmres_solve(bg, xg, rtol=rtol, restart=restart, max_iters=iters)
+        idr = sd.fgmres_solve(bg, xd, rtol=rtol, restart=restart, max_iters=iters)
+        torch.cuda.synchronize()
+        junk = torch.randn(4096, device="cuda", dtype=torch.float64)
+        assert float((junk * junk).sum()) > 0.0
+        assert ig["iterations"] == idr["iterations"] and ig["restarts"] == idr["restarts"]
+        assert torch.equal(xg, xd)
+    # kernel timing inside graphs counts every replayed Vanka update
+    for s in (sg, sd):
+        s.set_timing(1 << vk.KERNEL_VANKA)
+        x = dev(xl)
+        info = s.fgmres_solve(bg, x, rtol=1e-10, restart=8, max_iters=200)
+        n, ms = s.kernel_timing(vk.KERNEL_VANKA, levels - 1)
+        s.set_timing(0)
+        assert n == 4 * info["iterations"] and ms > 0.0
+    sg.close()
+    sd.close()
+
+
 def test_fgmres_restarts_match_oracle():
     N, levels = 16, 3
     s = solver(N, levels)

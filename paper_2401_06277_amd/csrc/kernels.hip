@@ -24,61 +24,62 @@ __device__ __forceinline__ bool q2_boundary(int qi, int qj, int s2) {
 // staged velocity arrays (row stride SQ2) hold x with Dirichlet columns and
 // outside nodes already zeroed; c2 is the staged index of node (2ex, 2ey);
 // the staged pressure array (row stride SQ1) has c1 at Q1 node (ex, ey).
-// Returns (A x) at the four Q2 nodes (both components; meaningful for free
-// nodes) and (B u) at the Q1 node.
+// cell_row_pair<.., BB> returns (A x) at the two Q2 nodes of row parity BB
+// (both components; meaningful for free nodes) and, for BB = 0, (B u) at
+// the Q1 node.
 // ---------------------------------------------------------------------------
 
-template <int SQ2, int SQ1, typename T>
-__device__ __forceinline__ void cell_rows(const T* __restrict__ su0, const T* __restrict__ su1,
-                                          const T* __restrict__ sp, int c2, int c1, T cl, T cb,
-                                          T (&ax)[2][2], T (&ay)[2][2], T& ap) {
+template <int SQ2, int SQ1, int BB, typename T>
+__device__ __forceinline__ void cell_row_pair(const T* __restrict__ su0, const T* __restrict__ su1,
+                                              const T* __restrict__ sp, int c2, int c1, T cl, T cb,
+                                              T (&ax)[2], T (&ay)[2], T& ap) {
 #pragma unroll
-    for (int bb = 0; bb < 2; ++bb) {
+    for (int aa = 0; aa < 2; ++aa) {
+        T lx = 0, ly = 0, bx = 0, by = 0;
+        const int cn = c2 + BB * SQ2 + aa;
 #pragma unroll
-        for (int aa = 0; aa < 2; ++aa) {
-            T lx = 0, ly = 0, bx = 0, by = 0;
-            const int cn = c2 + bb * SQ2 + aa;
+        for (int dy = -2; dy <= 2; ++dy)
 #pragma unroll
-            for (int dy = -2; dy <= 2; ++dy)
-#pragma unroll
-                for (int dx = -2; dx <= 2; ++dx) {
-                    const int c = st_L(bb, aa, dy, dx);
-                    if (c != 0) {
-                        lx += T(c) * su0[cn + dy * SQ2 + dx];
-                        ly += T(c) * su1[cn + dy * SQ2 + dx];
-                    }
-                }
-            // B^T p: Q1 nodes I with offsets o = i - 2I of the parity of i
-#pragma unroll
-            for (int oy = -2; oy <= 2; ++oy) {
-                if (((oy - bb) & 1) != 0) continue;
-#pragma unroll
-                for (int oxx = -2; oxx <= 2; ++oxx) {
-                    if (((oxx - aa) & 1) != 0) continue;
-                    const int cx = st_Mq(oy) * st_G(oxx);
-                    const int cy = st_G(oy) * st_Mq(oxx);
-                    if (cx == 0 && cy == 0) continue;
-                    const T pv = sp[c1 + ((bb - oy) / 2) * SQ1 + (aa - oxx) / 2];
-                    bx += T(cx) * pv;
-                    by += T(cy) * pv;
+            for (int dx = -2; dx <= 2; ++dx) {
+                const int c = st_L(BB, aa, dy, dx);
+                if (c != 0) {
+                    lx += T(c) * su0[cn + dy * SQ2 + dx];
+                    ly += T(c) * su1[cn + dy * SQ2 + dx];
                 }
             }
-            ax[bb][aa] = cl * lx + cb * bx;
-            ay[bb][aa] = cl * ly + cb * by;
+        // B^T p: Q1 nodes I with offsets o = i - 2I of the parity of i
+#pragma unroll
+        for (int oy = -2; oy <= 2; ++oy) {
+            if (((oy - BB) & 1) != 0) continue;
+#pragma unroll
+            for (int oxx = -2; oxx <= 2; ++oxx) {
+                if (((oxx - aa) & 1) != 0) continue;
+                const int cx = st_Mq(oy) * st_G(oxx);
+                const int cy = st_G(oy) * st_Mq(oxx);
+                if (cx == 0 && cy == 0) continue;
+                const T pv = sp[c1 + ((BB - oy) / 2) * SQ1 + (aa - oxx) / 2];
+                bx += T(cx) * pv;
+                by += T(cy) * pv;
+            }
         }
+        ax[aa] = cl * lx + cb * bx;
+        ay[aa] = cl * ly + cb * by;
     }
-    T sp_ = 0;
+    ap = 0;
+    if (BB == 0) {
+        T sp_ = 0;
 #pragma unroll
-    for (int oy = -2; oy <= 2; ++oy)
+        for (int oy = -2; oy <= 2; ++oy)
 #pragma unroll
-        for (int oxx = -2; oxx <= 2; ++oxx) {
-            const int cx = st_Mq(oy) * st_G(oxx);
-            const int cy = st_G(oy) * st_Mq(oxx);
-            if (cx == 0 && cy == 0) continue;
-            const int cc = c2 + oy * SQ2 + oxx;
-            sp_ += T(cx) * su0[cc] + T(cy) * su1[cc];
-        }
-    ap = cb * sp_;
+            for (int oxx = -2; oxx <= 2; ++oxx) {
+                const int cx = st_Mq(oy) * st_G(oxx);
+                const int cy = st_G(oy) * st_Mq(oxx);
+                if (cx == 0 && cy == 0) continue;
+                const int cc = c2 + oy * SQ2 + oxx;
+                sp_ += T(cx) * su0[cc] + T(cy) * su1[cc];
+            }
+        ap = cb * sp_;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -92,9 +93,10 @@ __device__ __forceinline__ void cell_rows(const T* __restrict__ su0, const T* __
 constexpr int RT = 16;              // cells per tile side
 constexpr int RQ2 = 2 * RT + 4;     // staged Q2 nodes per side
 constexpr int RQ1 = RT + 2;         // staged Q1 nodes per side
+constexpr int RNT = 2 * RT * RT;    // threads: one per cell and Q2 row parity
 
 template <int MODE, typename Tx, typename T>
-__global__ __launch_bounds__(256) void residual_kernel(Geom g, const T* __restrict__ b,
+__global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void residual_kernel(Geom g, const T* __restrict__ b,
                                                        const Tx* __restrict__ x,
                                                        T* __restrict__ r) {
     __shared__ T s_u[2][RQ2 * RQ2];
@@ -109,12 +111,12 @@ __global__ __launch_bounds__(256) void residual_kernel(Geom g, const T* __restri
     // every load of the tile is issued before the first is used: addresses
     // of nodes outside the staged set are clamped to node 0 and the values
     // replaced by zero afterwards
-    constexpr int kIt2 = (RQ2 * RQ2 + 255) / 256, kIt1 = (RQ1 * RQ1 + 255) / 256;
+    constexpr int kIt2 = (RQ2 * RQ2 + RNT - 1) / RNT, kIt1 = (RQ1 * RQ1 + RNT - 1) / RNT;
     Tx v0[kIt2], v1[kIt2], vp[kIt1];
     bool f2[kIt2], f1[kIt1];
 #pragma unroll
     for (int it = 0; it < kIt2; ++it) {
-        const int t = threadIdx.x + it * 256;
+        const int t = threadIdx.x + it * RNT;
         const int qi = ox + t % RQ2, qj = oy + t / RQ2;
         f2[it] = t < RQ2 * RQ2 && qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
         const int64_t q = f2[it] ? int64_t(qj) * g.s2 + qi : 0;
@@ -123,37 +125,14 @@ __global__ __launch_bounds__(256) void residual_kernel(Geom g, const T* __restri
     }
 #pragma unroll
     for (int it = 0; it < kIt1; ++it) {
-        const int t = threadIdx.x + it * 256;
+        const int t = threadIdx.x + it * RNT;
         const int I = E0x - 1 + t % RQ1, J = E0y - 1 + t / RQ1;
         f1[it] = t < RQ1 * RQ1 && I >= 0 && J >= 0 && I <= g.N && J <= g.N;
         vp[it] = x[2 * g.nq2 + (f1[it] ? int64_t(J) * g.s1 + I : 0)];
     }
-    // this thread's rows: b and (for Dirichlet rows) x at its four Q2 nodes
-    const int tx = threadIdx.x % RT, ty = threadIdx.x / RT;
-    const int ex = E0x + tx, ey = E0y + ty;
-    const bool cell = ex <= g.N && ey <= g.N;
-    int64_t qn[2][2];
-    T bx[2][2], by[2][2];
-    Tx xx[2][2], xy[2][2];
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-        for (int aa = 0; aa < 2; ++aa) {
-            const int i = 2 * ex + aa, j = 2 * ey + bb;
-            qn[bb][aa] = (cell && i < g.s2 && j < g.s2) ? int64_t(j) * g.s2 + i : -1;
-            const int64_t q = qn[bb][aa] >= 0 ? qn[bb][aa] : 0;
-            xx[bb][aa] = x[q];
-            xy[bb][aa] = x[g.nq2 + q];
-            if (MODE == 0) {
-                bx[bb][aa] = b[q];
-                by[bb][aa] = b[g.nq2 + q];
-            }
-        }
-    const int64_t qp = 2 * g.nq2 + (cell ? int64_t(ey) * g.s1 + ex : 0);
-    const T bp = (MODE == 0) ? b[qp] : T(0);
 #pragma unroll
     for (int it = 0; it < kIt2; ++it) {
-        const int t = threadIdx.x + it * 256;
+        const int t = threadIdx.x + it * RNT;
         if (t < RQ2 * RQ2) {
             s_u[0][t] = f2[it] ? T(v0[it]) : T(0);
             s_u[1][t] = f2[it] ? T(v1[it]) : T(0);
@@ -161,36 +140,58 @@ __global__ __launch_bounds__(256) void residual_kernel(Geom g, const T* __restri
     }
 #pragma unroll
     for (int it = 0; it < kIt1; ++it) {
-        const int t = threadIdx.x + it * 256;
+        const int t = threadIdx.x + it * RNT;
         if (t < RQ1 * RQ1) s_p[t] = f1[it] ? T(vp[it]) : T(0);
     }
     __syncthreads();
-    if (!cell) return;
-    T ax[2][2], ay[2][2], ap;
-    cell_rows<RQ2, RQ1>(s_u[0], s_u[1], s_p, (2 * ty + 2) * RQ2 + 2 * tx + 2,
-                        (ty + 1) * RQ1 + tx + 1, T(g.nu / 90.0), T(-g.h / 36.0), ax, ay, ap);
+    // this thread: the two Q2 nodes of row parity bb of cell (tx, ty) (and
+    // for bb = 0 the cell's Q1 node); waves 0-3 take bb = 0, waves 4-7 bb = 1
+    const int bb = threadIdx.x / (RT * RT);
+    const int cidx = threadIdx.x % (RT * RT);
+    const int tx = cidx % RT, ty = cidx / RT;
+    const int ex = E0x + tx, ey = E0y + ty;
+    const bool cell = ex <= g.N && ey <= g.N;
+    int64_t qn[2];
+    T bx[2], by[2];
 #pragma unroll
-    for (int bb = 0; bb < 2; ++bb) {
-#pragma unroll
-        for (int aa = 0; aa < 2; ++aa) {
-            const int64_t q = qn[bb][aa];
-            if (q < 0) continue;
-            const int i = 2 * ex + aa, j = 2 * ey + bb;
-            T vx = ax[bb][aa], vy = ay[bb][aa];
-            if (i == 0 || j == 0 || i == g.s2 - 1 || j == g.s2 - 1) {
-                vx = T(xx[bb][aa]);  // Dirichlet row: identity
-                vy = T(xy[bb][aa]);
-            }
-            if (MODE == 0) {
-                r[q] = bx[bb][aa] - vx;
-                r[g.nq2 + q] = by[bb][aa] - vy;
-            } else {
-                r[q] = vx;
-                r[g.nq2 + q] = vy;
-            }
+    for (int aa = 0; aa < 2; ++aa) {
+        const int i = 2 * ex + aa, j = 2 * ey + bb;
+        qn[aa] = (cell && i < g.s2 && j < g.s2) ? int64_t(j) * g.s2 + i : -1;
+        const int64_t q = qn[aa] >= 0 ? qn[aa] : 0;
+        if (MODE == 0) {
+            bx[aa] = b[q];
+            by[aa] = b[g.nq2 + q];
         }
     }
-    r[qp] = (MODE == 0) ? bp - ap : ap;
+    const int64_t qp = 2 * g.nq2 + (cell ? int64_t(ey) * g.s1 + ex : 0);
+    const T bp = (MODE == 0 && bb == 0) ? b[qp] : T(0);
+    if (!cell) return;
+    T ax[2], ay[2], ap;
+    const int c2 = (2 * ty + 2) * RQ2 + 2 * tx + 2, c1 = (ty + 1) * RQ1 + tx + 1;
+    const T cl = T(g.nu / 90.0), cb = T(-g.h / 36.0);
+    if (bb == 0)
+        cell_row_pair<RQ2, RQ1, 0>(s_u[0], s_u[1], s_p, c2, c1, cl, cb, ax, ay, ap);
+    else
+        cell_row_pair<RQ2, RQ1, 1>(s_u[0], s_u[1], s_p, c2, c1, cl, cb, ax, ay, ap);
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa) {
+        const int64_t q = qn[aa];
+        if (q < 0) continue;
+        const int i = 2 * ex + aa, j = 2 * ey + bb;
+        T vx = ax[aa], vy = ay[aa];
+        if (i == 0 || j == 0 || i == g.s2 - 1 || j == g.s2 - 1) {
+            vx = T(x[q]);  // Dirichlet row: identity (edge tiles only)
+            vy = T(x[g.nq2 + q]);
+        }
+        if (MODE == 0) {
+            r[q] = bx[aa] - vx;
+            r[g.nq2 + q] = by[aa] - vy;
+        } else {
+            r[q] = vx;
+            r[g.nq2 + q] = vy;
+        }
+    }
+    if (bb == 0) r[qp] = (MODE == 0) ? bp - ap : ap;
 }
 
 // ---------------------------------------------------------------------------
@@ -812,8 +813,8 @@ __device__ __forceinline__ void q2_restrict_taps(int ic, int (&off)[5], double (
 template <typename T>
 __global__ __launch_bounds__(256) void restrict_kernel(Geom gf, Geom gc, const T* __restrict__ rf,
                                                        T* __restrict__ bc) {
-    const int ic = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int jc = blockIdx.y * 16 + (threadIdx.x >> 4);
+    const int ic = blockIdx.x * 64 + (threadIdx.x & 63);  // 64 x 4 nodes per block:
+    const int jc = blockIdx.y * 4 + (threadIdx.x >> 6);   // a wave reads whole rows
     if (ic < gc.s2 && jc < gc.s2) {
         const int64_t qc = int64_t(jc) * gc.s2 + ic;
         const bool inner = !q2_boundary(ic, jc, gc.s2);
@@ -897,8 +898,8 @@ __device__ __forceinline__ void q2_prolong_taps(int i, int (&c)[3], double (&w)[
 template <typename T>
 __global__ __launch_bounds__(256) void prolong_kernel(Geom gf, Geom gc, const T* __restrict__ ec,
                                                       T* __restrict__ xf) {
-    const int i = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);  // 64 x 4 nodes per block:
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);   // a wave reads whole rows
     if (i < gf.s2 && j < gf.s2 && !q2_boundary(i, j, gf.s2)) {
         int cx[3], cy[3];
         double wx[3], wy[3];
@@ -1172,9 +1173,9 @@ void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hip
     const int tiles = (g.N + 1 + RT - 1) / RT;
     const int grid = 8 * ((tiles * tiles + 7) / 8);
     if (mode == 0)
-        residual_kernel<0, Tx, T><<<grid, 256, 0, s>>>(g, b, x, r);
+        residual_kernel<0, Tx, T><<<grid, RNT, 0, s>>>(g, b, x, r);
     else
-        residual_kernel<1, Tx, T><<<grid, 256, 0, s>>>(g, b, x, r);
+        residual_kernel<1, Tx, T><<<grid, RNT, 0, s>>>(g, b, x, r);
 }
 template void launch_residual<double, double>(const Geom&, const double*, const double*, double*,
                                               int, hipStream_t);
@@ -1211,7 +1212,7 @@ template void launch_vanka_update<float>(const Geom&, const float*, const float*
 
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, hipStream_t s) {
-    const dim3 grid((gc.s2 + 15) / 16, (gc.s2 + 15) / 16);
+    const dim3 grid((gc.s2 + 63) / 64, (gc.s2 + 3) / 4);
     restrict_kernel<T><<<grid, 256, 0, s>>>(gf, gc, rf, bc);
 }
 template void launch_restrict<double>(const Geom&, const Geom&, const double*, double*, hipStream_t);
@@ -1219,7 +1220,7 @@ template void launch_restrict<float>(const Geom&, const Geom&, const float*, flo
 
 template <typename T>
 void launch_prolong_add(const Geom& gf, const Geom& gc, const T* ec, T* xf, hipStream_t s) {
-    const dim3 grid((gf.s2 + 15) / 16, (gf.s2 + 15) / 16);
+    const dim3 grid((gf.s2 + 63) / 64, (gf.s2 + 3) / 4);
     prolong_kernel<T><<<grid, 256, 0, s>>>(gf, gc, ec, xf);
 }
 template void launch_prolong_add<double>(const Geom&, const Geom&, const double*, double*,

@@ -343,6 +343,75 @@ bool universal_interior_blocks(double* B1) {
     return interior_symmetry_blocks(W.data(), B1, 1e-12);
 }
 
+bool interior_d4_blocks(const double* B, double* C, double tol) {
+    // full blocks in transformed coordinates: F[blk][i][j] = B at members i, j
+    auto entry = [&](int blk, int tr, int tc) -> double {
+        const int n = sym_block_size(blk), off = sym_block_offset(blk);
+        int i = -1, j = -1;
+        for (int k = 0; k < n; ++k) {
+            if (sym_member(blk, k) == tr) i = k;
+            if (sym_member(blk, k) == tc) j = k;
+        }
+        return (i < 0 || j < 0) ? 0.0 : B[off + i * n + j];
+    };
+    double scale = 0.0;
+    for (int i = 0; i < kSymTotal; ++i) scale = std::max(scale, std::fabs(B[i]));
+    const D4Table& d = kD4Table;
+    // blocks 0 and 3: Q rows = [p], pair sums, pair differences; D = Q Q^T;
+    // C = D^{-1} Q F Q^T D^{-1} must be even/odd block diagonal
+    auto split = [&](int blk, const int* a, const int* b, bool with_p, double* Ce, double* Co) {
+        const int np = 6, ne = np + (with_p ? 1 : 0), n = ne + np;
+        std::vector<double> Q(size_t(n) * kSlots, 0.0), Dq(n, 0.0);
+        int r = 0;
+        if (with_p) Q[size_t(r++) * kSlots + 50] = 1.0;
+        for (int k = 0; k < np; ++k, ++r) {
+            Q[size_t(r) * kSlots + a[k]] = 1.0;
+            Q[size_t(r) * kSlots + b[k]] = 1.0;
+        }
+        for (int k = 0; k < np; ++k, ++r) {
+            Q[size_t(r) * kSlots + a[k]] = 1.0;
+            Q[size_t(r) * kSlots + b[k]] = -1.0;
+        }
+        for (int i = 0; i < n; ++i)
+            for (int t = 0; t < kSlots; ++t) Dq[i] += Q[size_t(i) * kSlots + t] * Q[size_t(i) * kSlots + t];
+        std::vector<double> M(size_t(n) * n, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double acc = 0.0;
+                for (int t = 0; t < kSlots; ++t) {
+                    const double qi = Q[size_t(i) * kSlots + t];
+                    if (qi == 0.0) continue;
+                    for (int u = 0; u < kSlots; ++u) {
+                        const double qj = Q[size_t(j) * kSlots + u];
+                        if (qj != 0.0) acc += qi * entry(blk, t, u) * qj;
+                    }
+                }
+                M[size_t(i) * n + j] = acc / (Dq[i] * Dq[j]);
+            }
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const bool same = (i < ne) == (j < ne);
+                if (!same && std::fabs(M[size_t(i) * n + j]) > tol * scale) return false;
+            }
+        for (int i = 0; i < ne; ++i)
+            for (int j = 0; j < ne; ++j) Ce[i * ne + j] = M[size_t(i) * n + j];
+        for (int i = 0; i < np; ++i)
+            for (int j = 0; j < np; ++j) Co[i * np + j] = M[size_t(ne + i) * n + ne + j];
+        return true;
+    };
+    if (!split(0, d.a0, d.b0, true, C + kD4Off0e, C + kD4Off0o)) return false;
+    if (!split(3, d.a3, d.b3, false, C + kD4Off3e, C + kD4Off3o)) return false;
+    // blocks 1 and 2: block 2 is block 1 relabelled by the reflection
+    for (int i = 0; i < 13; ++i)
+        for (int k = 0; k < 13; ++k) {
+            const double c1 = entry(1, d.m1[i], d.m1[k]);
+            const double c2 = entry(2, d.m2[i], d.m2[k]);
+            if (std::fabs(c1 - c2) > tol * scale) return false;
+            C[kD4Off1 + i * 13 + k] = c1;
+        }
+    return true;
+}
+
 void mfma_interior_table(const double* B1, bool fp64_layout, double* A) {
     // member index of transformed slot t within its block
     int member[kSlots];

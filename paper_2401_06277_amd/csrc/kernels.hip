@@ -9,6 +9,7 @@
 #include "interior_blocks.h"
 #include "symmetry.h"
 #include "mfma_patch.h"
+#include "d4_apply.h"
 
 namespace vkmg {
 
@@ -307,72 +308,17 @@ constexpr int VP = VT + 2;        // patches per tile side (= DPP row width)
 constexpr int VNT = VP * VP;      // threads per workgroup (256)
 constexpr int VR = 2 * VT + 7;    // staged residual region (Q2 nodes per side)
 
-// 1D reflection butterfly and its transpose on 5 values v[o + k*st].
-template <typename T>
-__device__ __forceinline__ void bfly(T (&v)[kSlots], int o, int st) {
-    const T f0 = v[o], f1 = v[o + st], f3 = v[o + 3 * st], f4 = v[o + 4 * st];
-    v[o] = f0 + f4;
-    v[o + st] = f1 + f3;
-    v[o + 3 * st] = f0 - f4;
-    v[o + 4 * st] = f1 - f3;
-}
-template <typename T>
-__device__ __forceinline__ void bfly_t(T (&v)[kSlots], int o, int st) {
-    const T e0 = v[o], e1 = v[o + st], o0 = v[o + 3 * st], o1 = v[o + 4 * st];
-    v[o] = e0 + o0;
-    v[o + st] = e1 + o1;
-    v[o + 3 * st] = e1 - o1;
-    v[o + 4 * st] = e0 - o0;
-}
-
-// v <- D W1 D v in place, for the universal interior operator W1 (compile-
-// time constants, symmetry.h blocks) and D = diag(I, t) applied to the
-// pressure output here; the caller scales the input (velocity by
-// omega/nu, pressure by t omega/nu with t = nu/h).
+// Interior operator: v <- D W1 D v in place for the universal interior
+// operator W1 in the dihedral coordinates of symmetry.h (d4_apply.h; 495
+// multiply-adds on compile-time constants) with D = diag(I, t) applied to
+// the pressure output; the caller scales the input (velocity by omega/nu,
+// pressure by t omega/nu with t = nu/h).
+struct InteriorD4 {
+    __device__ constexpr double operator()(int i) const { return kInteriorD4[i]; }
+};
 template <typename T>
 __device__ __forceinline__ void sym_apply(T (&v)[kSlots], T t) {
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-#pragma unroll
-        for (int b = 0; b < 5; ++b) bfly(v, 25 * f + 5 * b, 1);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) bfly(v, 25 * f + q, 5);
-    }
-#pragma unroll
-    for (int blk = 0; blk < kSymBlocks; ++blk) {
-        constexpr int nmax = 13;
-        const int n = sym_block_size(blk);
-        const int off = sym_block_offset(blk);
-        T y[nmax];
-#pragma unroll
-        for (int i = 0; i < nmax; ++i) {
-            if (i >= n) break;
-            T a0 = 0, a1 = 0;
-#pragma unroll
-            for (int j = 0; j < nmax; ++j) {
-                if (j >= n) break;
-                const T c = T(kInteriorW1[off + i * n + j]);
-                if (j & 1)
-                    a1 += c * v[kSymTable.m[blk][j]];
-                else
-                    a0 += c * v[kSymTable.m[blk][j]];
-            }
-            y[i] = a0 + a1;
-        }
-#pragma unroll
-        for (int i = 0; i < nmax; ++i) {
-            if (i >= n) break;
-            v[kSymTable.m[blk][i]] = y[i];
-        }
-    }
-    v[50] *= t;
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) bfly_t(v, 25 * f + q, 5);
-#pragma unroll
-        for (int b = 0; b < 5; ++b) bfly_t(v, 25 * f + 5 * b, 1);
-    }
+    d4_apply(v, t, InteriorD4{});
 }
 
 // Value of lane (l + S) of the same 16-lane row, 0 past the row end

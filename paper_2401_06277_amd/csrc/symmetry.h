@@ -74,6 +74,60 @@ constexpr SymTable make_sym_table() {
 }
 constexpr SymTable kSymTable = make_sym_table();
 
+// Diagonal reflection (x, y) -> (y, x) about the patch node.  It maps
+// u_x(a, b) -> u_y(b, a), u_y(a, b) -> u_x(b, a), p -> p, so in the
+// transformed coordinates (U1 is the same in x and y) t = 25 f + 5 qb + qa
+// goes to 25 (1 - f) + 5 qa + qb, a plain permutation.  It swaps blocks 1
+// and 2 and maps blocks 0 and 3 onto themselves; the interior operator
+// commutes with it, so
+//   * block 2 is block 1 with rows and columns relabelled by the
+//     reflection (one set of constants serves both), and
+//   * blocks 0 and 3 split further into reflection-even coordinates
+//     (x_t + x_dt for the pairs t < dt, and p) and reflection-odd ones
+//     (x_t - x_dt): 13 = 7 + 6 and 12 = 6 + 6.
+// Together with the x/y reflections this is the dihedral group of the
+// square; 7^2 + 6^2 + 13^2 + 6^2 + 6^2 = 326 constants and 49 + 36 + 2 x
+// 169 + 36 + 36 = 495 multiply-adds per patch.
+constexpr int sym_delta(int t) {
+    if (t == 50) return 50;
+    const int f = t / 25, q = t % 25;
+    return 25 * (1 - f) + 5 * (q % 5) + q / 5;
+}
+
+constexpr int kD4Total = 7 * 7 + 6 * 6 + 13 * 13 + 6 * 6 + 6 * 6;  // 326
+// offsets of the D4 blocks: 0-even (7), 0-odd (6), 1 (13, shared by 2),
+// 3-even (6), 3-odd (6)
+constexpr int kD4Off0e = 0, kD4Off0o = 49, kD4Off1 = 85, kD4Off3e = 254, kD4Off3o = 290;
+
+struct D4Table {
+    int a0[6], b0[6];  // block-0 pairs (a < b = delta(a)), increasing a
+    int a3[6], b3[6];  // block-3 pairs
+    int m1[13], m2[13];  // block-1 members and their images in block 2
+};
+constexpr D4Table make_d4_table() {
+    D4Table d{};
+    int n0 = 0, n3 = 0, n1 = 0;
+    for (int t = 0; t < 50; ++t) {
+        const int u = sym_delta(t);
+        const int blk = sym_block_of(t);
+        if (blk == 0 && t < u) {
+            d.a0[n0] = t;
+            d.b0[n0] = u;
+            ++n0;
+        } else if (blk == 3 && t < u) {
+            d.a3[n3] = t;
+            d.b3[n3] = u;
+            ++n3;
+        } else if (blk == 1) {
+            d.m1[n1] = t;
+            d.m2[n1] = u;
+            ++n1;
+        }
+    }
+    return d;
+}
+constexpr D4Table kD4Table = make_d4_table();
+
 // Entry (row qa/qb, column a/b) of the 1D forward transform U1.
 constexpr int sym_u1(int q, int a) {
     return q == 0 ? ((a == 0 || a == 4) ? 1 : 0)

@@ -68,6 +68,12 @@ bool universal_interior_blocks(double* B1);
 double universal_mismatch(const double* Blevel, const double* B1, double omega, double nu,
                           double h);
 
+// The reflection blocks (651 values) refined by the diagonal reflection
+// (symmetry.h kD4Table): kD4Total = 326 values at the kD4Off* offsets.
+// Returns false if the blocks do not have that structure to within `tol`
+// relative to their largest entry.
+bool interior_d4_blocks(const double* B, double* C, double tol);
+
 // Operand table of the matrix-instruction interior apply (mfma_patch.h):
 // A[(blk * 4 + c) * 64 + lane] = entry (row lane % 16, column 4c + lane / 16)
 // of block blk of W1, rows and columns ordered by quarter items.  The

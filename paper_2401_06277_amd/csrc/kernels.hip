@@ -4,6 +4,8 @@
 // Q1 block of (N+1)^2 values, row-major (index j*side + i).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "kernels.h"
 #include "stencil.h"
 #include "interior_blocks.h"
@@ -342,8 +344,9 @@ __device__ __forceinline__ int dclass(int i, int N) {
 }
 
 // Boundary patches (Q1 nodes within one element of the boundary, 8N - 8 of
-// them, N >= 4) in a fixed order: rows 0, 1, N-1, N in full, then for rows
-// 2..N-2 the columns 0, 1, N-1, N.
+// them, N >= 4) in an order that groups patches of one class: rows 0, 1,
+// N-1, N in full, then the columns 0, 1, N-1, N of the rows 2..N-2, one
+// column after the other (each such column is a single class).
 __host__ __device__ inline int n_boundary_patches(int N) { return 8 * N - 8; }
 
 __device__ __forceinline__ void boundary_patch(int k, int N, int& I, int& J) {
@@ -354,8 +357,8 @@ __device__ __forceinline__ void boundary_patch(int k, int N, int& I, int& J) {
         I = k % w;
     } else {
         k -= 4 * w;
-        J = 2 + k / 4;
-        const int c = k % 4;
+        const int c = k / (N - 3);
+        J = 2 + k % (N - 3);
         I = c < 2 ? c : N - 3 + c;
     }
 }
@@ -365,7 +368,7 @@ __device__ __forceinline__ int boundary_index(int I, int J, int N) {
     if (J <= 1) return J * w + I;
     if (J >= N - 1) return (J - N + 3) * w + I;
     const int c = I <= 1 ? I : I - N + 3;
-    return 4 * w + (J - 2) * 4 + c;
+    return 4 * w + c * (N - 3) + (J - 2);
 }
 
 // Global index of patch slot s of the patch at Q1 node (I, J), or -1 if the
@@ -378,40 +381,64 @@ __device__ __forceinline__ int64_t slot_index(const Geom& g, int I, int J, int s
     return int64_t(f) * g.nq2 + int64_t(qj) * g.s2 + qi;
 }
 
-// One wavefront per boundary patch: lane s gathers the patch residual at
-// slot s, then computes row s of the class's weighted inverse (stored
-// transposed, so the lanes read consecutive addresses) against the residual
-// broadcast from LDS.  The residual and all 51 coefficient loads are issued
-// together (inactive lanes read valid addresses and are discarded).
-template <typename T>
+// Boundary patches, KBP consecutive ones (in the class-grouped order) per
+// wavefront: lane s gathers slot s of every patch, then computes row s of
+// the class's weighted inverse (stored transposed, so the lanes read
+// consecutive addresses) against each patch residual broadcast from LDS.
+// The coefficient row stays in registers while the class does not change,
+// so a wavefront usually loads it once for all its patches.  Gathers and
+// the first class's coefficients are issued together (inactive lanes read
+// valid addresses and are discarded).  Several patches per wavefront cut
+// the coefficient traffic (51 x 51 values per patch otherwise) on the large
+// levels; one per wavefront keeps the dependent chain short on the small
+// ones (boundary_patches_per_wave).
+template <typename T, int KBP>
 __global__ __launch_bounds__(256) void vanka_boundary_kernel(Geom g, const T* __restrict__ rb,
                                                              const T* __restrict__ table,
                                                              T* __restrict__ dbuf) {
-    __shared__ T s_r[4][64];
+    constexpr int kBP = KBP;
+    __shared__ T s_r[4][kBP][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int k = blockIdx.x * 4 + w;
-    const bool active = k < n_boundary_patches(g.N);
-    int I = 0, J = 0;
-    if (active) boundary_patch(k, g.N, I, J);
-    const int cls = 5 * dclass(J, g.N) + dclass(I, g.N);
+    const int nb = n_boundary_patches(g.N);
+    const int k0 = (blockIdx.x * 4 + w) * kBP;
     const int s = lane < kSlots ? lane : 0;
-    const int64_t q = slot_index(g, I, J, s);
-    const T rv = rb[q >= 0 ? q : 0];
-    const T* __restrict__ Mt = table + cls * kSlots * kSlots;  // Mt[t][s] = W[s][t]
-    T m[kSlots];
+    int cls[kBP];
+    T rv[kBP];
+    bool ok[kBP];
 #pragma unroll
-    for (int t = 0; t < kSlots; ++t) m[t] = Mt[t * kSlots + s];
-    s_r[w][lane] = (active && lane < kSlots && q >= 0) ? rv : T(0);
-    __syncthreads();
-    if (!active || lane >= kSlots) return;
-    T a0 = 0, a1 = 0;
-#pragma unroll
-    for (int t = 0; t + 1 < kSlots; t += 2) {
-        a0 += m[t] * s_r[w][t];
-        a1 += m[t + 1] * s_r[w][t + 1];
+    for (int p = 0; p < kBP; ++p) {
+        int I = 0, J = 0;
+        const bool active = k0 + p < nb;
+        if (active) boundary_patch(k0 + p, g.N, I, J);
+        cls[p] = 5 * dclass(J, g.N) + dclass(I, g.N);
+        const int64_t q = slot_index(g, I, J, s);
+        ok[p] = active && lane < kSlots && q >= 0;
+        rv[p] = rb[q >= 0 ? q : 0];
     }
-    a0 += m[kSlots - 1] * s_r[w][kSlots - 1];
-    dbuf[int64_t(k) * 64 + lane] = a0 + a1;
+    T m[kSlots];
+    int cur = cls[0];
+#pragma unroll
+    for (int t = 0; t < kSlots; ++t) m[t] = table[(cur * kSlots + t) * kSlots + s];
+#pragma unroll
+    for (int p = 0; p < kBP; ++p) s_r[w][p][lane] = ok[p] ? rv[p] : T(0);
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kBP; ++p) {
+        if (k0 + p >= nb) break;
+        if (cls[p] != cur) {  // uniform over the wavefront
+            cur = cls[p];
+#pragma unroll
+            for (int t = 0; t < kSlots; ++t) m[t] = table[(cur * kSlots + t) * kSlots + s];
+        }
+        T a0 = 0, a1 = 0;
+#pragma unroll
+        for (int t = 0; t + 1 < kSlots; t += 2) {
+            a0 += m[t] * s_r[w][p][t];
+            a1 += m[t + 1] * s_r[w][p][t + 1];
+        }
+        a0 += m[kSlots - 1] * s_r[w][p][kSlots - 1];
+        if (lane < kSlots) dbuf[int64_t(k0 + p) * 64 + lane] = a0 + a1;
+    }
 }
 
 // Tile grid and the XCD-aware tile order: consecutive workgroup ids are
@@ -1103,6 +1130,24 @@ __global__ __launch_bounds__(256) void axpy_multi_kernel(const double* __restric
     }
 }
 
+int boundary_per_wave_override() {
+    static const int v = [] {
+        const char* e = std::getenv("VKMG_BOUNDARY_PER_WAVE");
+        const int x = e ? std::atoi(e) : 0;
+        return (x == 1 || x == 2 || x == 4 || x == 8) ? x : 0;
+    }();
+    return v;
+}
+
+// Boundary patches per wavefront: about one wavefront per SIMD (1024) on
+// the large levels, where the coefficient rows dominate the traffic.
+int boundary_patches_per_wave(int nb) {
+    const int env = boundary_per_wave_override();
+    if (env > 0) return env;
+    const int q = nb / 1024;
+    return q >= 8 ? 8 : q >= 4 ? 4 : q >= 2 ? 2 : 1;
+}
+
 int elementwise_blocks(int64_t n) {
     int64_t b = (n + 255) / 256;
     return int(b < 4096 ? (b > 0 ? b : 1) : 4096);
@@ -1139,7 +1184,16 @@ template <typename T>
 void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const T* table,
                          const T* mtab, T* dbuf, double omega, bool mfma, hipStream_t s) {
     const int nb = n_boundary_patches(g.N);
-    vanka_boundary_kernel<T><<<(nb + 3) / 4, 256, 0, s>>>(g, r, table, dbuf);
+    const int per = boundary_patches_per_wave(nb);
+    const int nblk = (nb + 4 * per - 1) / (4 * per);
+    if (per == 8)
+        vanka_boundary_kernel<T, 8><<<nblk, 256, 0, s>>>(g, r, table, dbuf);
+    else if (per == 4)
+        vanka_boundary_kernel<T, 4><<<nblk, 256, 0, s>>>(g, r, table, dbuf);
+    else if (per == 2)
+        vanka_boundary_kernel<T, 2><<<nblk, 256, 0, s>>>(g, r, table, dbuf);
+    else
+        vanka_boundary_kernel<T, 1><<<nblk, 256, 0, s>>>(g, r, table, dbuf);
     const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
     const int grid = 8 * ((ntile + 7) / 8);
     if (mfma)

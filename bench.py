@@ -18,10 +18,16 @@ V-cycle in FP32 (FGMRES, Arnoldi and the coarse solve kept in FP64) is
 reported under "fp32_mg".
 
 Prints one JSON line.  The roofline object is for the dominant kernel, the
-finest-level Vanka update, timed with HIP events on its launch stream during
-the FP64 timed loop.  The cpu_baseline object times the CPU oracle (plain
+finest-level Vanka update, timed with HIP events on its launch stream in an
+event-timed pass of the same K solves (kernel events bypass the captured
+graphs); that pass also gives the per-class kernel time per solve
+(kernel_ms_per_solve, krylov_share).  "c2_256" reports, at 256 x 256 with 6
+levels, the standalone sweep rates (apply only given r, and residual +
+update given x and b) and the manufactured-solution solve, in both
+precisions.  The cpu_baseline object times the CPU oracle (plain
 NumPy/SciPy FP64) on a bounded sample: V-cycles of the same method at
-256 x 256 elements.
+256 x 256 elements; it also solves the 256 x 256 manufactured problem with
+the oracle and reports the GPU solutions' distance to it.
 """
 
 from __future__ import annotations
@@ -67,6 +73,8 @@ def parse():
     ap.add_argument("--cpu-levels", type=int, default=6)
     ap.add_argument("--cpu-vcycles", type=int, default=60)
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--skip-c2", action="store_true",
+                    help="skip the 256x256 sweep and solve measurements")
     ap.add_argument("--interior-apply", choices=["vector", "matrix"], default="vector",
                     help="interior Vanka apply: vector ALUs (default) or matrix cores")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -91,8 +99,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(N, levels, nvc):
-    """Oracle V-cycles at N x N (setup excluded), patch-updates/s."""
+def cpu_baseline(N, levels, nvc, c2=None):
+    """Oracle V-cycles at N x N (setup excluded), patch-updates/s.  With the
+    256 x 256 GPU solutions, also the oracle's own FGMRES solve of that
+    problem and the GPU solutions' distance to it."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -111,6 +121,23 @@ def cpu_baseline(N, levels, nvc):
     dt = time.perf_counter() - t0
     ups = H.patch_updates_per_cycle() * nvc / dt
     blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    extra = {}
+    if c2 is not None and N == 256:
+        from oracle import fgmres
+        from stokes_inputs import manufactured_boundary_values, manufactured_nodal_force
+        gd = manufactured_boundary_values(N, "trig")
+        A, bo, _, xl = fem.stokes_system(N, 1.0, f_nodal=manufactured_nodal_force(N, "trig"),
+                                         g_nodal=gd)
+        t0 = time.perf_counter()
+        ro = fgmres.fgmres(A, bo, xl, H.vcycle, rtol=1e-8, restart=30, max_iters=500)
+        t_solve = time.perf_counter() - t0
+        xo = fem.normalise_pressure(N, ro.x)
+        extra["oracle_solve_256"] = {"seconds": t_solve, "iterations": ro.iterations}
+        for prec, xg in c2["_solutions"].items():
+            xa = fem.normalise_pressure(N, xg.astype(np.float64))
+            extra["oracle_solve_256"][f"{prec}_rel_err_vs_oracle"] = float(
+                np.linalg.norm(xa - xo) / np.linalg.norm(xo))
+            extra["oracle_solve_256"][f"{prec}_iterations"] = c2[f"solve_{prec}"]["iterations"]
     return {
         "value": ups,
         "unit": "patch-updates/s",
@@ -121,7 +148,74 @@ def cpu_baseline(N, levels, nvc):
                    f"{blas_threads} threads, sparse matvecs single-threaded; host has "
                    f"{os.cpu_count()} logical CPUs"),
         "seconds_per_vcycle": dt / nvc,
+        **extra,
     }
+
+
+def bench_c2(a, vk, torch, np):
+    """256 x 256, 6 levels: standalone sweep rates (apply only, given r; and
+    residual + update, given x and b) in both precisions, and the
+    manufactured-solution solve (trigonometric solution, Dirichlet lifting
+    as initial guess) in both precisions."""
+    from stokes_inputs import (dirichlet_consistent_pair, grid_sizes, manufactured_boundary_values,
+                               manufactured_nodal_force, uniform_vector, velocity_dirichlet_mask)
+
+    N2, L2 = 256, 6
+    g = grid_sizes(N2)
+    top = L2 - 1
+    mask = velocity_dirichlet_mask(N2)
+    rin = uniform_vector(g.n, 2)
+    rin[mask] = 0.0
+    xin, bin_ = dirichlet_consistent_pair(N2, 3, 4)
+    res = {"config": "256x256 elements, 6 levels, V(2,2) omega=0.5; sweeps on the finest level"}
+
+    def timed(fn, reps=20, warm=5):
+        for _ in range(warm):
+            fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    fn2 = manufactured_nodal_force(N2, "trig")
+    gd2 = manufactured_boundary_values(N2, "trig")
+    sol = {}
+    for prec in ("fp64", "fp32"):
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        s = vk.VkmgSolver(N2, L2, precision=prec, interior_apply=a.interior_apply)
+        r_d = torch.from_numpy(rin).to(dt).cuda()
+        x_d = torch.zeros(g.n, dtype=dt, device="cuda")
+        t_apply = timed(lambda: s.vanka_update(top, x_d, r_d))
+        x_d = torch.from_numpy(xin).to(dt).cuda()
+        b_d = torch.from_numpy(bin_).to(dt).cuda()
+        t_full = timed(lambda: s.vanka_sweep(top, x_d, b_d))
+        res[f"sweep_apply_only_{prec}"] = {"us": t_apply * 1e6,
+                                           "patch_updates_per_s": (N2 + 1) ** 2 / t_apply}
+        res[f"sweep_full_{prec}"] = {"us": t_full * 1e6,
+                                     "patch_updates_per_s": (N2 + 1) ** 2 / t_full}
+        b = s.assemble_rhs(torch.from_numpy(fn2.ravel()).cuda(),
+                           torch.from_numpy(gd2.ravel()).cuda())
+        x0 = torch.where(torch.from_numpy(mask).cuda(), b, torch.zeros_like(b))
+        x = x0.clone()
+        s.fgmres_solve(b, x, rtol=1e-8)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = x0.clone()
+        info = s.fgmres_solve(b, x, rtol=1e-8)
+        torch.cuda.synchronize()
+        res[f"solve_{prec}"] = {"time_to_1e8_s": time.perf_counter() - t0,
+                                "iterations": info["iterations"],
+                                "true_rel_res": info["true_rel_res"]}
+        sol[prec] = x.cpu().numpy()
+        s.close()
+    res["_solutions"] = sol
+    return res
 
 
 def main():
@@ -176,9 +270,13 @@ def main():
     # the solve's stream, in a second pass of the same solves (events bypass
     # the captured graphs, so this pass launches kernel by kernel)
     log("[bench] fp64 event-timed pass")
-    s64.set_timing(1 << vk.KERNEL_VANKA)
+    classes = {"vanka": vk.KERNEL_VANKA, "residual": vk.KERNEL_RESIDUAL,
+               "transfer": vk.KERNEL_TRANSFER, "coarse": vk.KERNEL_COARSE,
+               "krylov": vk.KERNEL_KRYLOV}
+    s64.set_timing(sum(1 << c for c in classes.values()))
     dt64_ev, _, _ = run_solves(s64, b, x, a.steps, True)
     nl, ms = s64.kernel_timing(vk.KERNEL_VANKA, L - 1)
+    breakdown = {k: s64.kernel_timing(c)[1] / a.steps for k, c in classes.items()}
     s64.set_timing(0)
     for inf in inf64:
         if inf["status_name"] != "VKMG_OK":
@@ -195,7 +293,7 @@ def main():
     # standalone V-cycle rate (median of 20)
     r = torch.randn(n, dtype=torch.float64, device="cuda")
     z = torch.empty_like(r)
-    for _ in range(3):
+    for _ in range(5):
         s64.vcycle(r, z)
     ts = []
     for _ in range(20):
@@ -229,6 +327,8 @@ def main():
         },
         "time_to_1e8_s": dt64 / a.steps,
         "time_to_1e8_s_without_graphs": dt64_ev / a.steps,
+        "kernel_ms_per_solve": breakdown,
+        "krylov_share": breakdown["krylov"] / max(sum(breakdown.values()), 1e-300),
         "fgmres_iterations": it64[0],
         "true_rel_res": inf64[-1]["true_rel_res"],
         "vcycle_s": vcycle_s,
@@ -277,9 +377,15 @@ def main():
         }
         s32.close()
 
+    c2 = None
+    if not a.skip_c2:
+        log("[bench] 256x256 sweeps and solves")
+        c2 = bench_c2(a, vk, torch, np)
+        out["c2_256"] = {k: v for k, v in c2.items() if not k.startswith("_")}
+
     if not a.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(a.cpu_N, a.cpu_levels, a.cpu_vcycles)
+        out["cpu_baseline"] = cpu_baseline(a.cpu_N, a.cpu_levels, a.cpu_vcycles, c2)
     print(json.dumps(out), flush=True)
 
 

@@ -29,7 +29,7 @@
  *
  * Streams: every entry point that takes `stream` (a hipStream_t, NULL =
  * the legacy default stream) enqueues all its GPU work on it.
- * vkmg_residual, vkmg_apply, vkmg_vanka_sweep, vkmg_restrict,
+ * vkmg_residual, vkmg_apply, vkmg_vanka_sweep, vkmg_vanka_update, vkmg_restrict,
  * vkmg_prolong_add, vkmg_coarse_solve, vkmg_vcycle and vkmg_assemble_rhs are
  * asynchronous; vkmg_fgmres_solve synchronises (one small device-to-host
  * copy per Arnoldi step) and its vkmg_info is valid on return.
@@ -168,6 +168,16 @@ vkmg_status vkmg_assemble_rhs(vkmg_ctx* ctx, const double* f, const double* g, d
  * updated in place; b is read-only and must not alias x.
  */
 vkmg_status vkmg_vanka_sweep(vkmg_ctx* ctx, int32_t level, void* x, const void* b, void* stream);
+
+/*
+ * The update half of a sweep, given the residual: x += sum_i V_i^T W_i
+ * A_i^{-1} V_i r (patch gather, patch-inverse apply and weighted scatter of
+ * Algorithm 3, without forming r).  Same level range, precision and
+ * operator as vkmg_vanka_sweep; r is read-only and must not alias x; r
+ * must vanish on Dirichlet DoFs for the result to equal a sweep (their
+ * weights are zero, so they are never read into a correction).
+ */
+vkmg_status vkmg_vanka_update(vkmg_ctx* ctx, int32_t level, void* x, const void* r, void* stream);
 
 /*
  * Grid transfers of Algorithm 1 in the multigrid precision:

@@ -34,6 +34,7 @@ STATUS = {
 EXPORTED = [
     "vkmg_default_options", "vkmg_setup", "vkmg_destroy", "vkmg_layout_of", "vkmg_level_layout",
     "vkmg_num_levels", "vkmg_residual", "vkmg_apply", "vkmg_assemble_rhs", "vkmg_vanka_sweep",
+    "vkmg_vanka_update",
     "vkmg_restrict", "vkmg_prolong_add", "vkmg_coarse_solve", "vkmg_vcycle",
     "vkmg_fgmres_solve", "vkmg_set_timing", "vkmg_kernel_timing", "vkmg_host_patch_matrix",
     "vkmg_status_string", "vkmg_last_error",
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
         "vkmg_apply": (c_int32, [P, P, P, P]),
         "vkmg_assemble_rhs": (c_int32, [P, P, P, P, P]),
         "vkmg_vanka_sweep": (c_int32, [P, c_int32, P, P, P]),
+        "vkmg_vanka_update": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_restrict": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_prolong_add": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_coarse_solve": (c_int32, [P, P, P, P]),
@@ -254,6 +256,14 @@ class VkmgSolver:
         st = _lib.vkmg_vanka_sweep(self._ctx, level, self._ptr(x, self.mg_dtype, n, "x"),
                                    self._ptr(b, self.mg_dtype, n, "b"), self._stream())
         _check(st, "vkmg_vanka_sweep")
+        return x
+
+    def vanka_update(self, level: int, x, r):
+        """x += sum_i V_i^T W_i A_i^{-1} V_i r (the update half of a sweep)."""
+        n = self.level_layout(level)["n"]
+        st = _lib.vkmg_vanka_update(self._ctx, level, self._ptr(x, self.mg_dtype, n, "x"),
+                                    self._ptr(r, self.mg_dtype, n, "r"), self._stream())
+        _check(st, "vkmg_vanka_update")
         return x
 
     def restrict(self, level: int, r_fine, b_coarse=None):

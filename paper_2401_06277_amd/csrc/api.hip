@@ -555,6 +555,29 @@ vkmg_status vkmg_vanka_sweep(vkmg_ctx* ctx, int32_t level, void* x, const void* 
     return VKMG_OK;
 }
 
+vkmg_status vkmg_vanka_update(vkmg_ctx* ctx, int32_t level, void* x, const void* r, void* stream) {
+    if (!x || !r || !check_level(ctx, level, true))
+        return fail(VKMG_ERR_INVALID_ARG, "vanka_update: NULL argument or level not in [1, levels)");
+    if (x == r) return fail(VKMG_ERR_INVALID_ARG, "vanka_update: r must not alias x");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    LevelBuf& L = ctx->lev[level];
+    const bool mfma = ctx->opt.interior_apply == VKMG_APPLY_MATRIX;
+    Timed t(ctx, VKMG_KERNEL_VANKA, s, level);
+    if (ctx->opt.mg_precision == VKMG_FP64)
+        launch_vanka_update<double>(L.g, static_cast<const double*>(r), static_cast<double*>(x),
+                                    static_cast<double*>(x), static_cast<const double*>(L.W),
+                                    static_cast<const double*>(ctx->mtab),
+                                    static_cast<double*>(L.dbuf), ctx->opt.omega, mfma, s);
+    else
+        launch_vanka_update<float>(L.g, static_cast<const float*>(r), static_cast<float*>(x),
+                                   static_cast<float*>(x), static_cast<const float*>(L.W),
+                                   static_cast<const float*>(ctx->mtab),
+                                   static_cast<float*>(L.dbuf), ctx->opt.omega, mfma, s);
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
 vkmg_status vkmg_restrict(vkmg_ctx* ctx, int32_t level, const void* r_fine, void* b_coarse,
                           void* stream) {
     if (!r_fine || !b_coarse || !check_level(ctx, level, true))

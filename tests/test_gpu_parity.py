@@ -142,6 +142,23 @@ def test_interior_apply_variants_agree(precision, tol):
             assert rel(host(xg), lev.smoother.sweep(x, b)) < tol
 
 
+@pytest.mark.parametrize("apply", ["vector", "matrix"])
+def test_vanka_update_given_residual(apply):
+    """The update half of a sweep: x + S (b - A x) with the residual formed
+    by the oracle equals the oracle sweep."""
+    N, levels = 40, 3
+    s = solver(N, levels, apply=apply)
+    H = hierarchy(N, levels)
+    lev = H.levels[-1]
+    x, b = dirichlet_consistent_pair(N, 160, 161)
+    r = b - lev.A @ x
+    xg = dev(x)
+    s.vanka_update(levels - 1, xg, dev(r))
+    assert rel(host(xg), lev.smoother.sweep(x, b)) < 1e-12
+    with pytest.raises(vk.VkmgError):
+        s.vanka_update(levels - 1, xg, xg)
+
+
 def test_vanka_sweep_is_bitwise_reproducible():
     s = solver(40, 3)
     x, b = dirichlet_consistent_pair(40, 5, 6)

@@ -74,6 +74,7 @@ struct vkmg_ctx {
     // executable graphs of the Arnoldi steps (index j), valid for the
     // current basis allocation; captured on a private stream
     std::vector<hipGraphExec_t> step_graphs;
+    int graphs_scheme = -1;  // orthogonalisation scheme the graphs were captured for
     hipStream_t capture_stream = nullptr;
 
     size_t esize() const { return opt.mg_precision == VKMG_FP32 ? 4 : 8; }
@@ -83,6 +84,9 @@ struct vkmg_ctx {
 namespace {
 
 constexpr int kHostScratch = 1024;  // doubles in the pinned host buffer
+// largest restart length orthogonalised by the delayed scheme (its
+// kernels hold up to 32 basis coefficients in registers)
+constexpr int kDelayedMaxRestart = 32;
 
 // Brackets one kernel launch with events when the class is being timed.
 struct Timed {
@@ -685,19 +689,56 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
     const double target = rtol * beta0;
     int total = 0, restarts = 0;
     double beta = beta0;
-    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
-    auto Hij = [&](int i, int j) -> double& { return H[size_t(i) * m + j]; };
+    // Hu: the Hessenberg matrix as built; R: its columns after the Givens
+    // rotations; gbase: the right-hand side beta e1 after the rotations of
+    // the columns before the previous one (whose rotation is redone each
+    // step, as the delayed scheme finalises that column one step late)
+    std::vector<double> Hu(size_t(m + 1) * m), R(size_t(m + 1) * m), cs(m), sn(m), gbase(m + 1),
+        gv(m + 1), y(m);
+    auto Hij = [&](int i, int j) -> double& { return Hu[size_t(i) * m + j]; };
+    auto Rij = [&](int i, int j) -> double& { return R[size_t(i) * m + j]; };
+    auto rotate_column = [&](int j) {
+        for (int i = 0; i <= j + 1; ++i) Rij(i, j) = Hij(i, j);
+        for (int i = 0; i < j; ++i) {
+            const double t = cs[i] * Rij(i, j) + sn[i] * Rij(i + 1, j);
+            Rij(i + 1, j) = -sn[i] * Rij(i, j) + cs[i] * Rij(i + 1, j);
+            Rij(i, j) = t;
+        }
+        const double denom = std::hypot(Rij(j, j), Rij(j + 1, j));
+        cs[j] = Rij(j, j) / denom;
+        sn[j] = Rij(j + 1, j) / denom;
+        Rij(j, j) = denom;
+        Rij(j + 1, j) = 0.0;
+    };
+    auto rotate_rhs = [&](std::vector<double>& g, int j) {
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+    };
     double est = 1.0;
     double* h1 = ctx->hdev;        // first Gram-Schmidt pass, j+1 values
     double* h2 = ctx->hdev + 300;  // second pass, j+1 values, then ||w||^2 at [j+1]
-    // Device work of Arnoldi step j (no host synchronisation): z_j = M v_j,
-    // w = A z_j, then classical Gram-Schmidt twice (Giraud et al.'s CGS2):
-    //   h1 = V^T w;  w' = w - V h1 with h2 = V^T w' and |w'|^2 in the same
-    //   pass;  v_{j+1} = (w' - V h2) / |w' - V h2| in a third, with
-    //   |w' - V h2|^2 = |w'|^2 - |h2|^2 (V orthonormal).  Beyond 32 basis
-    //   vectors: unfused passes, |w''|^2 into h2[kb], v_{j+1} scaled on host
-    //   request.  Every pointer depends only on j, so the step can be
-    //   captured once per j and replayed.
+    // Both schemes are classical Gram-Schmidt with one reorthogonalisation
+    // (orthogonal to working accuracy; multi-vector passes over the basis).
+    // Delayed (restart <= 32): the reorthogonalisation of basis vector j
+    // shares the sweep that first orthogonalises w = A z_j, two passes per
+    // step.  Step j sees final v_0..v_{j-1} and u_j in slot j, the
+    // once-orthogonalised successor of step j-1 scaled by sigma_{j-1};
+    // pass 1 takes V^T w, V^T u, u.u, u.w, w.w, pass 2 writes
+    // v_j = (u_j - V s) / alpha over slot j and u_{j+1} into slot j+1.
+    // Column j-1 of H becomes final in step j (H(i,j-1) += s_i / sigma_{j-1},
+    // H(j,j-1) = alpha_j / sigma_{j-1}); column j is provisional with
+    // H(j+1,j) = sqrt(d), which the stopping test uses.
+    // Classical (restart > 32, Giraud et al.'s CGS2): h1 = V^T w;
+    // w' = w - V h1 with h2 = V^T w' and |w'|^2 in the same pass;
+    // v_{j+1} = (w' - V h2) / |w' - V h2| in a third, with
+    // |w' - V h2|^2 = |w'|^2 - |h2|^2 (V orthonormal).  Beyond 32 basis
+    // vectors: unfused passes, |w''|^2 into h2[kb], v_{j+1} scaled on host
+    // request.
+    // Every pointer depends only on j, so a step can be captured once per j
+    // and replayed.
+    const bool delayed = m <= kDelayedMaxRestart;
+    double* dco = ctx->hdev;       // delayed: 2j+3 reduced values of pass 1
+    double* dcf = ctx->hdev + 300;  // delayed: alpha, gamma, d, sigma
     auto arnoldi_step = [&](int j, hipStream_t ss) {
         double* vj = V + int64_t(j) * ld;
         double* zj = Z + int64_t(j) * ld;
@@ -706,6 +747,13 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
         {
             Timed t(ctx, VKMG_KERNEL_RESIDUAL, ss);
             launch_residual<double, double>(g, nullptr, zj, w, 1, ss);
+        }
+        if (delayed) {
+            Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);
+            launch_dcgs_dots(V, ld, j, vj, w, n, ctx->part, ss);
+            launch_reduce_partials(ctx->part, 2 * j + 3, dco, ss);
+            launch_dcgs_update(V, ld, j, dco, vj, w, V + int64_t(kb) * ld, n, dcf, ss);
+            return;
         }
         dots_async(ctx, V, ld, kb, w, h1, ss);
         if (kb <= 32) {
@@ -730,15 +778,20 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
     // kernels are timed (events recorded inside a replayed graph cannot be
     // read back with hipEventElapsedTime)
     const bool use_graphs = ctx->opt.use_graphs != 0 && ctx->timing_mask == 0;
+    if (use_graphs && ctx->graphs_scheme != int(delayed)) {
+        drop_graphs(ctx);
+        ctx->graphs_scheme = int(delayed);
+    }
     for (;;) {
         {
             Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
             launch_scale(r, 1.0 / beta, V, n, s);
         }
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(gv.begin(), gv.end(), 0.0);
-        gv[0] = beta;
+        std::fill(Hu.begin(), Hu.end(), 0.0);
+        std::fill(gbase.begin(), gbase.end(), 0.0);
+        gbase[0] = beta;
         int k = 0;
+        double sigma_prev = 0.0;
         for (int j = 0; j < m; ++j) {
             const int kb = j + 1;  // basis vectors so far
             const bool normalized = kb <= 32;
@@ -750,43 +803,56 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
             } else {
                 arnoldi_step(j, s);
             }
-            VKMG_HIP(hipMemcpyAsync(ctx->hhost, h1, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
-            VKMG_HIP(hipMemcpyAsync(ctx->hhost + 300, h2, sizeof(double) * (kb + 1), hipMemcpyDeviceToHost, s));
-            VKMG_HIP(hipStreamSynchronize(s));
             bool finite = true;
-            double hh = 0.0;
-            for (int i = 0; i <= j; ++i) {
-                Hij(i, j) = ctx->hhost[i] + ctx->hhost[300 + i];
-                finite = finite && std::isfinite(Hij(i, j));
-                hh += ctx->hhost[300 + i] * ctx->hhost[300 + i];
-            }
-            if (normalized) {
-                // the formula of the normalisation kernel
-                const double d = ctx->hhost[300 + kb] - hh;
+            if (delayed) {
+                VKMG_HIP(hipMemcpyAsync(ctx->hhost, dco, sizeof(double) * (2 * j + 3), hipMemcpyDeviceToHost, s));
+                VKMG_HIP(hipMemcpyAsync(ctx->hhost + 300, dcf, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
+                VKMG_HIP(hipStreamSynchronize(s));
+                const double* c = ctx->hhost;
+                const double alpha = ctx->hhost[300], gamma = ctx->hhost[301];
+                const double d = ctx->hhost[302], sigma = ctx->hhost[303];
+                if (j > 0) {  // finalise column j-1
+                    for (int i = 0; i < j; ++i) Hij(i, j - 1) += c[j + i] / sigma_prev;
+                    Hij(j, j - 1) = alpha / sigma_prev;
+                    for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(Hij(i, j - 1));
+                }
+                for (int i = 0; i < j; ++i) Hij(i, j) = c[i];
+                Hij(j, j) = gamma;
                 hnext = d > 0.0 ? std::sqrt(d) : 0.0;
+                sigma_prev = sigma;
             } else {
-                hnext = std::sqrt(ctx->hhost[300 + kb]);
+                VKMG_HIP(hipMemcpyAsync(ctx->hhost, h1, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
+                VKMG_HIP(hipMemcpyAsync(ctx->hhost + 300, h2, sizeof(double) * (kb + 1), hipMemcpyDeviceToHost, s));
+                VKMG_HIP(hipStreamSynchronize(s));
+                double hh = 0.0;
+                for (int i = 0; i <= j; ++i) {
+                    Hij(i, j) = ctx->hhost[i] + ctx->hhost[300 + i];
+                    hh += ctx->hhost[300 + i] * ctx->hhost[300 + i];
+                }
+                if (normalized) {
+                    // the formula of the normalisation kernel
+                    const double d = ctx->hhost[300 + kb] - hh;
+                    hnext = d > 0.0 ? std::sqrt(d) : 0.0;
+                } else {
+                    hnext = std::sqrt(ctx->hhost[300 + kb]);
+                }
             }
+            for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(Hij(i, j));
             Hij(j + 1, j) = hnext;
             if (!finite || !std::isfinite(hnext))
                 return finish(VKMG_ERR_NONFINITE, total, restarts, NAN, NAN);
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
-                Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
-                Hij(i, j) = t;
+            if (j > 0) {
+                rotate_column(j - 1);
+                rotate_rhs(gbase, j - 1);
             }
-            const double denom = std::hypot(Hij(j, j), hnext);
-            cs[j] = Hij(j, j) / denom;
-            sn[j] = hnext / denom;
+            rotate_column(j);
+            gv = gbase;
+            rotate_rhs(gv, j);
             const bool breakdown = hnext == 0.0;
-            if (!breakdown && !normalized) {
+            if (!delayed && !breakdown && !normalized) {
                 Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
                 launch_scale(w, 1.0 / hnext, V + int64_t(j + 1) * ld, n, s);
             }
-            Hij(j, j) = denom;
-            Hij(j + 1, j) = 0.0;
-            gv[j + 1] = -sn[j] * gv[j];
-            gv[j] = cs[j] * gv[j];
             ++total;
             k = j + 1;
             est = std::fabs(gv[j + 1]) / beta0;
@@ -796,8 +862,8 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
         // y = H^{-1} g (upper triangular)
         for (int i = k - 1; i >= 0; --i) {
             double acc = gv[i];
-            for (int l = i + 1; l < k; ++l) acc -= Hij(i, l) * y[l];
-            y[i] = acc / Hij(i, i);
+            for (int l = i + 1; l < k; ++l) acc -= Rij(i, l) * y[l];
+            y[i] = acc / Rij(i, i);
         }
         std::memcpy(ctx->hhost + 600, y.data(), sizeof(double) * k);
         VKMG_HIP(hipMemcpyAsync(ctx->hdev + 600, ctx->hhost + 600, sizeof(double) * k, hipMemcpyHostToDevice, s));

@@ -64,6 +64,14 @@ void launch_update_dot(const double* V, int64_t ldv, int k, const double* h, dou
 // out = (w - V h2) / sqrt(nrm2[0] - |h2|^2); k <= 32
 void launch_normalize(const double* V, int64_t ldv, int k, const double* h2, const double* nrm2,
                       const double* w, double* out, int64_t n, hipStream_t s);
+// Delayed CGS2, pass 1 (j < 32 final vectors V, unnormalised u, w):
+// partials of V^T w (j rows), V^T u (j rows), u.u, u.w, w.w into part
+void launch_dcgs_dots(const double* V, int64_t ldv, int j, const double* u, const double* w,
+                      int64_t n, double* part, hipStream_t s);
+// Delayed CGS2, pass 2 from the 2j+3 reduced values c: u <- v_j (final),
+// next <- normalised successor; cf = (alpha, gamma, d, 1/sqrt(d))
+void launch_dcgs_update(const double* V, int64_t ldv, int j, const double* c, double* u,
+                        const double* w, double* next, int64_t n, double* cf, hipStream_t s);
 // x += sum_v y[v] Z_v
 void launch_axpy_multi(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t n,
                        hipStream_t s);

@@ -1095,6 +1095,119 @@ __global__ __launch_bounds__(256) void normalize_kernel(const double* __restrict
     }
 }
 
+// Delayed classical Gram-Schmidt with reorthogonalisation (the DCGS2 of
+// Bielich, Langou, Thomas, Swirydowicz, Yamazaki and Boman): the second
+// pass for basis vector j shares its sweep with the first pass for
+// w = A z_j.  V holds the j final vectors, u the once-orthogonalised,
+// unnormalised vector j.  Pass 1 leaves partials (G = gridDim.x) of
+//   rows [0, j)   V^T w  (h)        rows [j, 2j)  V^T u  (s)
+//   row 2j  u.u,  row 2j+1  u.w,  row 2j+2  w.w
+// in part[row * G + blk].
+template <int KMAX>
+__global__ __launch_bounds__(256) void dcgs_dots_kernel(const double* __restrict__ V, int64_t ldv,
+                                                        int j, const double* __restrict__ u,
+                                                        const double* __restrict__ w, int64_t n,
+                                                        double* __restrict__ part) {
+    double aw[KMAX], au[KMAX];
+    double uu = 0.0, uw = 0.0, ww = 0.0;
+#pragma unroll
+    for (int v = 0; v < KMAX; ++v) aw[v] = au[v] = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * 256) {
+        double vv[KMAX];
+#pragma unroll
+        for (int v = 0; v < KMAX; ++v) vv[v] = v < j ? V[v * ldv + i] : 0.0;
+        const double ui = u[i], wi = w[i];
+        uu += ui * ui;
+        uw += ui * wi;
+        ww += wi * wi;
+#pragma unroll
+        for (int v = 0; v < KMAX; ++v) {
+            aw[v] += vv[v] * wi;
+            au[v] += vv[v] * ui;
+        }
+    }
+    __shared__ double red[2 * KMAX + 3][4];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < KMAX; ++v) {
+        if (v >= j) break;
+        const double a = wave_sum(aw[v]), b = wave_sum(au[v]);
+        if (lane == 0) {
+            red[v][wv] = a;
+            red[KMAX + v][wv] = b;
+        }
+    }
+    {
+        const double a = wave_sum(uu), b = wave_sum(uw), c = wave_sum(ww);
+        if (lane == 0) {
+            red[2 * KMAX][wv] = a;
+            red[2 * KMAX + 1][wv] = b;
+            red[2 * KMAX + 2][wv] = c;
+        }
+    }
+    __syncthreads();
+    const int row = threadIdx.x;
+    if (row < 2 * j + 3) {
+        const int r = row < j ? row : row < 2 * j ? KMAX + row - j : 2 * KMAX + row - 2 * j;
+        part[int64_t(row) * gridDim.x + blockIdx.x] = (red[r][0] + red[r][1]) + (red[r][2] + red[r][3]);
+    }
+}
+
+// Pass 2 of the delayed scheme from the reduced values c of pass 1:
+//   alpha = sqrt(u.u - |s|^2),  v_j = (u - V s) / alpha   (written over u)
+//   gamma = v_j . w = (u.w - s.h) / alpha
+//   d = |w - V h - gamma v_j|^2 = w.w - |h|^2 - gamma^2
+//   next = (w - V h - gamma v_j) / sqrt(d)   (zeros if d <= 0)
+// Every block derives the same coefficients; block 0 stores
+// (alpha, gamma, d, 1/sqrt(d)) in cf for the Hessenberg matrix.
+template <int KMAX>
+__global__ __launch_bounds__(256) void dcgs_update_kernel(const double* __restrict__ V, int64_t ldv,
+                                                          int j, const double* __restrict__ c,
+                                                          double* uv, const double* __restrict__ w,
+                                                          double* __restrict__ next, int64_t n,
+                                                          double* __restrict__ cf) {
+    double hv[KMAX], sv[KMAX];
+    double ss = 0.0, hh = 0.0, sh = 0.0;
+#pragma unroll
+    for (int v = 0; v < KMAX; ++v) {
+        hv[v] = v < j ? c[v] : 0.0;
+        sv[v] = v < j ? c[j + v] : 0.0;
+        ss += sv[v] * sv[v];
+        hh += hv[v] * hv[v];
+        sh += sv[v] * hv[v];
+    }
+    const double uu = c[2 * j], uw = c[2 * j + 1], ww = c[2 * j + 2];
+    const double a2 = uu - ss;
+    const double alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
+    const double ra = alpha > 0.0 ? 1.0 / alpha : 0.0;
+    const double gamma = (uw - sh) * ra;
+    const double d = ww - hh - gamma * gamma;
+    const double sigma = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cf[0] = alpha;
+        cf[1] = gamma;
+        cf[2] = d;
+        cf[3] = sigma;
+    }
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * 256) {
+        double vv[KMAX];
+#pragma unroll
+        for (int v = 0; v < KMAX; ++v) vv[v] = v < j ? V[v * ldv + i] : 0.0;
+        const double ui = uv[i], wi = w[i];
+        double ps = 0.0, ph = 0.0;
+#pragma unroll
+        for (int v = 0; v < KMAX; ++v) {
+            ps += sv[v] * vv[v];
+            ph += hv[v] * vv[v];
+        }
+        const double vj = (ui - ps) * ra;
+        uv[i] = vj;
+        next[i] = ((wi - ph) - gamma * vj) * sigma;
+    }
+}
+
 // w <- w - V h (no reduction)
 template <int KMAX>
 __global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ V, int64_t ldv,
@@ -1295,6 +1408,16 @@ void launch_update_dot(const double* V, int64_t ldv, int k, const double* h, dou
 void launch_normalize(const double* V, int64_t ldv, int k, const double* h2, const double* nrm2,
                       const double* w, double* out, int64_t n, hipStream_t s) {
     VKMG_KDISPATCH(k, normalize_kernel, V, ldv, k, h2, nrm2, w, out, n);
+}
+
+void launch_dcgs_dots(const double* V, int64_t ldv, int j, const double* u, const double* w,
+                      int64_t n, double* part, hipStream_t s) {
+    VKMG_KDISPATCH(j, dcgs_dots_kernel, V, ldv, j, u, w, n, part);
+}
+
+void launch_dcgs_update(const double* V, int64_t ldv, int j, const double* c, double* u,
+                        const double* w, double* next, int64_t n, double* cf, hipStream_t s) {
+    VKMG_KDISPATCH(j, dcgs_update_kernel, V, ldv, j, c, u, w, next, n, cf);
 }
 
 void launch_axpy_multi(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t n,

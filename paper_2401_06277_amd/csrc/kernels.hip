@@ -783,70 +783,97 @@ __device__ __forceinline__ void q2_restrict_taps(int ic, int (&off)[5], double (
     }
 }
 
+// Restriction, one thread per coarse Q2 column ic and coarse element row
+// jg: the coarse rows 2jg (vertex row) and 2jg+1 (midpoint row), which
+// need the fine rows 4jg + {-3, -1, 0, 1, 2, 3}; each fine row is first
+// restricted along x (five padded taps), then the rows are combined with
+// the 1D weights along y.  The last element row also writes the top
+// coarse boundary row (zero).  Pressure: coarse row jg (and Nc on the last
+// row) from the 3x3 fine neighbourhood with weights (1/2, 1, 1/2)^2.
 template <typename T>
 __global__ __launch_bounds__(256) void restrict_kernel(Geom gf, Geom gc, const T* __restrict__ rf,
                                                        T* __restrict__ bc) {
-    const int ic = blockIdx.x * 64 + (threadIdx.x & 63);  // 64 x 4 nodes per block:
-    const int jc = blockIdx.y * 4 + (threadIdx.x >> 6);   // a wave reads whole rows
-    if (ic < gc.s2 && jc < gc.s2) {
-        const int64_t qc = int64_t(jc) * gc.s2 + ic;
-        const bool inner = !q2_boundary(ic, jc, gc.s2);
-        int ox[5], oy[5];
-        double wx[5], wy[5];
+    const int ic = blockIdx.x * 64 + (threadIdx.x & 63);  // 64 x 4 threads per block:
+    const int jg = blockIdx.y * 4 + (threadIdx.x >> 6);   // a wave reads whole rows
+    if (ic >= gc.s2 || jg >= gc.N) return;
+    const bool last = jg == gc.N - 1;
+    {
+        constexpr int kRow[6] = {-3, -1, 0, 1, 2, 3};
+        int ox[5];
+        double wx[5];
         q2_restrict_taps(ic, ox, wx);
-        q2_restrict_taps(jc, oy, wy);
-        T vx[5][5], vy[5][5];
-        bool ok[5][5];
+        const bool col_in = ic > 0 && ic < gc.s2 - 1;
+        T vx[6][5], vy[6][5];
+        bool ok[6][5];
 #pragma unroll
-        for (int b = 0; b < 5; ++b)
-#pragma unroll
-            for (int a = 0; a < 5; ++a) {
-                const int i_f = 2 * ic + ox[a], jf = 2 * jc + oy[b];
-                ok[b][a] = inner && i_f > 0 && jf > 0 && i_f < gf.s2 - 1 && jf < gf.s2 - 1;
-                const int64_t qf = ok[b][a] ? int64_t(jf) * gf.s2 + i_f : 0;
-                vx[b][a] = rf[qf];
-                vy[b][a] = rf[gf.nq2 + qf];
-            }
-        T sx = 0, sy = 0;
-#pragma unroll
-        for (int b = 0; b < 5; ++b) {
-            T tx = 0, ty = 0;
+        for (int r = 0; r < 6; ++r)
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
-                const T wa = ok[b][a] ? T(wx[a]) : T(0);
-                tx += wa * vx[b][a];
-                ty += wa * vy[b][a];
+                const int i_f = 2 * ic + ox[a], jf = 4 * jg + kRow[r];
+                ok[r][a] = col_in && i_f > 0 && jf > 0 && i_f < gf.s2 - 1 && jf < gf.s2 - 1;
+                const int64_t qf = ok[r][a] ? int64_t(jf) * gf.s2 + i_f : 0;
+                vx[r][a] = rf[qf];
+                vy[r][a] = rf[gf.nq2 + qf];
             }
-            sx += T(wy[b]) * tx;
-            sy += T(wy[b]) * ty;
+        T tx[6], ty[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            tx[r] = 0;
+            ty[r] = 0;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                const T wa = ok[r][a] ? T(wx[a]) : T(0);
+                tx[r] += wa * vx[r][a];
+                ty[r] += wa * vy[r][a];
+            }
         }
-        bc[qc] = sx;
-        bc[gc.nq2 + qc] = sy;
+        // vertex row 2jg: fine rows -3, -1, 0, 1, 3 with -1/8, 3/8, 1, 3/8, -1/8
+        // midpoint row 2jg+1: fine rows 1, 2, 3 with 3/4, 1, 3/4
+        const bool vrow_in = jg > 0;
+        const T sxv = T(-0.125) * tx[0] + T(0.375) * tx[1] + tx[2] + T(0.375) * tx[3] +
+                      T(-0.125) * tx[5];
+        const T syv = T(-0.125) * ty[0] + T(0.375) * ty[1] + ty[2] + T(0.375) * ty[3] +
+                      T(-0.125) * ty[5];
+        const T sxm = T(0.75) * tx[3] + tx[4] + T(0.75) * tx[5];
+        const T sym = T(0.75) * ty[3] + ty[4] + T(0.75) * ty[5];
+        const int64_t q0 = int64_t(2 * jg) * gc.s2 + ic;
+        bc[q0] = vrow_in ? sxv : T(0);
+        bc[gc.nq2 + q0] = vrow_in ? syv : T(0);
+        bc[q0 + gc.s2] = sxm;
+        bc[gc.nq2 + q0 + gc.s2] = sym;
+        if (last) {
+            bc[q0 + 2 * gc.s2] = T(0);
+            bc[gc.nq2 + q0 + 2 * gc.s2] = T(0);
+        }
     }
-    if (ic < gc.s1 && jc < gc.s1) {
-        T v[3][3];
-        bool ok[3][3];
+    if (ic < gc.s1) {
+        const T* pf = rf + 2 * gf.nq2;
+        T* pc = bc + 2 * gc.nq2;
+        for (int jc = jg; jc <= (last ? jg + 1 : jg); ++jc) {
+            T v[3][3];
+            bool ok[3][3];
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
+            for (int b = 0; b < 3; ++b)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int i_f = 2 * ic + a - 1, jf = 2 * jc + b - 1;
-                ok[b][a] = i_f >= 0 && jf >= 0 && i_f < gf.s1 && jf < gf.s1;
-                v[b][a] = rf[2 * gf.nq2 + (ok[b][a] ? int64_t(jf) * gf.s1 + i_f : 0)];
+                for (int a = 0; a < 3; ++a) {
+                    const int i_f = 2 * ic + a - 1, jf = 2 * jc + b - 1;
+                    ok[b][a] = i_f >= 0 && jf >= 0 && i_f < gf.s1 && jf < gf.s1;
+                    v[b][a] = pf[ok[b][a] ? int64_t(jf) * gf.s1 + i_f : 0];
+                }
+            T sp = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const T wyb = b == 1 ? T(1) : T(0.5);
+                T t = 0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const T wxa = a == 1 ? T(1) : T(0.5);
+                    t += ok[b][a] ? wxa * v[b][a] : T(0);
+                }
+                sp += wyb * t;
             }
-        T s = 0;
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const T wyb = b == 1 ? T(1) : T(0.5);
-            T t = 0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const T wxa = a == 1 ? T(1) : T(0.5);
-                t += ok[b][a] ? wxa * v[b][a] : T(0);
-            }
-            s += wyb * t;
+            pc[int64_t(jc) * gc.s1 + ic] = sp;
         }
-        bc[2 * gc.nq2 + int64_t(jc) * gc.s1 + ic] = s;
     }
 }
 
@@ -868,63 +895,84 @@ __device__ __forceinline__ void q2_prolong_taps(int i, int (&c)[3], double (&w)[
     }
 }
 
+// Prolongation (x_f += P e_c), one thread per fine Q2 column i and coarse
+// element row jg: the fine rows 4jg..4jg+3 interpolate the coarse rows
+// 2jg..2jg+2 (each first interpolated along x at column i) with the 1D
+// weights of offsets 0..3 in the coarse element.  The top fine row is
+// Dirichlet and no thread writes it.  Pressure: fine rows 2jg, 2jg+1 (and
+// 2Nc on the last row) at column i, bilinear from the coarse rows jg,
+// jg+1.
 template <typename T>
 __global__ __launch_bounds__(256) void prolong_kernel(Geom gf, Geom gc, const T* __restrict__ ec,
                                                       T* __restrict__ xf) {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);  // 64 x 4 nodes per block:
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);   // a wave reads whole rows
-    if (i < gf.s2 && j < gf.s2 && !q2_boundary(i, j, gf.s2)) {
-        int cx[3], cy[3];
-        double wx[3], wy[3];
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);  // 64 x 4 threads per block:
+    const int jg = blockIdx.y * 4 + (threadIdx.x >> 6);  // a wave reads whole rows
+    if (i >= gf.s2 || jg >= gc.N) return;
+    {
+        int cx[3];
+        double wx[3];
         q2_prolong_taps(i, cx, wx);
-        q2_prolong_taps(j, cy, wy);
-        const int64_t q = int64_t(j) * gf.s2 + i;
-        const T x0 = xf[q], x1 = xf[gf.nq2 + q];
+        const bool col_free = i > 0 && i < gf.s2 - 1;
         T vx[3][3], vy[3][3];
         bool ok[3][3];
+        T f0[4], f1[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int64_t q = int64_t(4 * jg + p) * gf.s2 + i;
+            f0[p] = xf[q];
+            f1[p] = xf[gf.nq2 + q];
+        }
 #pragma unroll
         for (int b = 0; b < 3; ++b)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                ok[b][a] = !q2_boundary(cx[a], cy[b], gc.s2);
-                const int64_t qc = ok[b][a] ? int64_t(cy[b]) * gc.s2 + cx[a] : 0;
+                ok[b][a] = !q2_boundary(cx[a], 2 * jg + b, gc.s2);
+                const int64_t qc = ok[b][a] ? int64_t(2 * jg + b) * gc.s2 + cx[a] : 0;
                 vx[b][a] = ec[qc];
                 vy[b][a] = ec[gc.nq2 + qc];
             }
-        T sx = 0, sy = 0;
+        T tx[3], ty[3];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            T tx = 0, ty = 0;
+            tx[b] = 0;
+            ty[b] = 0;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const T wa = ok[b][a] ? T(wx[a]) : T(0);
-                tx += wa * vx[b][a];
-                ty += wa * vy[b][a];
+                tx[b] += wa * vx[b][a];
+                ty[b] += wa * vy[b][a];
             }
-            sx += T(wy[b]) * tx;
-            sy += T(wy[b]) * ty;
         }
-        xf[q] = x0 + sx;
-        xf[gf.nq2 + q] = x1 + sy;
+        // offsets 0..3 of the coarse element: 1D quadratic interpolation
+        const T sx[4] = {tx[0], T(0.375) * tx[0] + T(0.75) * tx[1] + T(-0.125) * tx[2], tx[1],
+                         T(-0.125) * tx[0] + T(0.75) * tx[1] + T(0.375) * tx[2]};
+        const T sy[4] = {ty[0], T(0.375) * ty[0] + T(0.75) * ty[1] + T(-0.125) * ty[2], ty[1],
+                         T(-0.125) * ty[0] + T(0.75) * ty[1] + T(0.375) * ty[2]};
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            if (!col_free || (jg == 0 && p == 0)) continue;
+            const int64_t q = int64_t(4 * jg + p) * gf.s2 + i;
+            xf[q] = f0[p] + sx[p];
+            xf[gf.nq2 + q] = f1[p] + sy[p];
+        }
     }
-    if (i < gf.s1 && j < gf.s1) {
-        const int i0 = i / 2, i1 = (i + 1) / 2, j0 = j / 2, j1 = (j + 1) / 2;
+    if (i < gf.s1) {
         const T* pc = ec + 2 * gc.nq2;
-        const int64_t qf = 2 * gf.nq2 + int64_t(j) * gf.s1 + i;
-        const T xp = xf[qf];
-        const T p00 = pc[int64_t(j0) * gc.s1 + i0], p01 = pc[int64_t(j0) * gc.s1 + i1];
-        const T p10 = pc[int64_t(j1) * gc.s1 + i0], p11 = pc[int64_t(j1) * gc.s1 + i1];
-        T v;
-        if ((i & 1) == 0 && (j & 1) == 0) {
-            v = p00;
-        } else if ((j & 1) == 0) {
-            v = T(0.5) * (p00 + p01);
-        } else if ((i & 1) == 0) {
-            v = T(0.5) * (p00 + p10);
-        } else {
-            v = T(0.25) * ((p00 + p01) + (p10 + p11));
-        }
-        xf[qf] = xp + v;
+        T* pf = xf + 2 * gf.nq2;
+        const int i0 = i / 2, i1 = (i + 1) / 2;
+        const bool last = jg == gc.N - 1;
+        const int nrow = last ? 3 : 2;
+        T fp[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            fp[r] = pf[int64_t(r < nrow ? 2 * jg + r : 2 * jg) * gf.s1 + i];
+        const T p00 = pc[int64_t(jg) * gc.s1 + i0], p01 = pc[int64_t(jg) * gc.s1 + i1];
+        const T p10 = pc[int64_t(jg + 1) * gc.s1 + i0], p11 = pc[int64_t(jg + 1) * gc.s1 + i1];
+        const T r0 = (i & 1) ? T(0.5) * (p00 + p01) : p00;
+        const T r1 = (i & 1) ? T(0.5) * (p10 + p11) : p10;
+        pf[int64_t(2 * jg) * gf.s1 + i] = fp[0] + r0;
+        pf[int64_t(2 * jg + 1) * gf.s1 + i] = fp[1] + T(0.5) * (r0 + r1);
+        if (last) pf[int64_t(2 * jg + 2) * gf.s1 + i] = fp[2] + r1;
     }
 }
 
@@ -1325,7 +1373,7 @@ template void launch_vanka_update<float>(const Geom&, const float*, const float*
 
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, hipStream_t s) {
-    const dim3 grid((gc.s2 + 63) / 64, (gc.s2 + 3) / 4);
+    const dim3 grid((gc.s2 + 63) / 64, (gc.N + 3) / 4);
     restrict_kernel<T><<<grid, 256, 0, s>>>(gf, gc, rf, bc);
 }
 template void launch_restrict<double>(const Geom&, const Geom&, const double*, double*, hipStream_t);
@@ -1333,7 +1381,7 @@ template void launch_restrict<float>(const Geom&, const Geom&, const float*, flo
 
 template <typename T>
 void launch_prolong_add(const Geom& gf, const Geom& gc, const T* ec, T* xf, hipStream_t s) {
-    const dim3 grid((gf.s2 + 63) / 64, (gf.s2 + 3) / 4);
+    const dim3 grid((gf.s2 + 63) / 64, (gc.N + 3) / 4);
     prolong_kernel<T><<<grid, 256, 0, s>>>(gf, gc, ec, xf);
 }
 template void launch_prolong_add<double>(const Geom&, const Geom&, const double*, double*,

@@ -80,6 +80,8 @@ typedef struct {
                                     captured at its first use; 0: direct launches.  Graphs
                                     are bypassed while kernel timing is enabled (events in
                                     a replayed graph cannot be read back). */
+    int32_t batch;               /* right-hand sides handled together (1..64, default 1);
+                                    see "Batches" below */
 } vkmg_options;
 
 typedef struct {
@@ -107,7 +109,19 @@ typedef enum {
     VKMG_KERNEL_COUNT = 5
 } vkmg_kernel_class;
 
-/* {2, 2, 0.5, VKMG_FP64}: V(2,2) cycles of additive Vanka damped by 0.5. */
+/*
+ * Batches.  A context set up with batch = B > 1 treats B independent
+ * right-hand sides of the same operator together: every vector argument
+ * of the entry points below then holds B vectors of that argument's size,
+ * back to back (right-hand side k at offset k times the single size; for
+ * vkmg_assemble_rhs f and g hold B blocks of 2 (2N+1)^2 values), and one
+ * kernel launch serves all B (so the coarse levels, whose single launches
+ * cannot fill the GPU, do B times the work per launch).  The results equal
+ * those of B separate single-right-hand-side calls up to rounding order.
+ */
+
+/* {2, 2, 0.5, VKMG_FP64, VKMG_APPLY_VECTOR, 1, 1}: V(2,2) cycles of additive
+ * Vanka damped by 0.5, one right-hand side. */
 vkmg_options vkmg_default_options(void);
 
 /*
@@ -122,7 +136,7 @@ vkmg_options vkmg_default_options(void);
  * uploads and is synchronised before return.
  * Requirements: nx == ny; levels >= 2; nx divisible by 2^(levels-1);
  * coarsest mesh at least 2 x 2; nu > 0 and finite; opts NULL or with
- * nu_pre, nu_post in [0, 16], 0 < omega <= 2.  Violations give
+ * nu_pre, nu_post in [0, 16], 0 < omega <= 2, batch in [1, 64].  Violations give
  * VKMG_ERR_INVALID_ARG; a singular patch gives VKMG_ERR_SINGULAR_PATCH.
  */
 vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu,
@@ -219,6 +233,13 @@ vkmg_status vkmg_vcycle(vkmg_ctx* ctx, const double* r, double* z, void* stream)
  * restart cycle whose estimate met rtol left the recomputed residual above
  * it and not halved, i.e. rtol is below the rounding floor of the system)
  * or VKMG_ERR_NONFINITE; `info` (may be NULL) is filled in every case.
+ * Batched contexts (batch B > 1) solve the B systems independently (own
+ * Krylov bases, rotations, stopping tests and restarts; one batched launch
+ * per kernel for all of them, steps of right-hand sides that have already
+ * converged are computed and discarded); `info` then points to B entries,
+ * max_iters bounds the Arnoldi steps of each, restart must be <= 32
+ * (VKMG_ERR_UNSUPPORTED otherwise), and the return value is VKMG_OK if all
+ * B converged, else the status of the first that did not.
  */
 vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double rtol,
                               int32_t restart, int32_t max_iters, vkmg_info* info, void* stream);

@@ -54,7 +54,8 @@ class Grid(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("nu_pre", c_int32), ("nu_post", c_int32), ("omega", c_double),
-                ("mg_precision", c_int32), ("interior_apply", c_int32), ("use_graphs", c_int32)]
+                ("mg_precision", c_int32), ("interior_apply", c_int32), ("use_graphs", c_int32),
+                ("batch", c_int32)]
 
 
 class Layout(ctypes.Structure):
@@ -146,11 +147,14 @@ def default_options():
 
 class VkmgSolver:
     """One vkmg context: the multigrid hierarchy of an N x N Q2-Q1 Stokes
-    problem on the current HIP device."""
+    problem on the current HIP device.  With ``batch`` > 1 every vector
+    argument holds ``batch`` vectors back to back (a tensor of batch * size
+    elements, e.g. shape (batch, size)) and fgmres_solve returns a list of
+    info dicts."""
 
     def __init__(self, N: int, levels: int, nu: float = 1.0, nu_pre: int = 2, nu_post: int = 2,
                  omega: float = 0.5, precision: str = "fp64", interior_apply: str = "vector",
-                 graphs: bool = True):
+                 graphs: bool = True, batch: int = 1):
         import torch
         lib = load_library()
         self._torch = torch
@@ -159,13 +163,13 @@ class VkmgSolver:
         if interior_apply not in APPLY:
             raise ValueError(f"interior_apply must be one of {sorted(APPLY)}")
         opts = Options(nu_pre, nu_post, omega, FP32 if precision == "fp32" else FP64,
-                       APPLY[interior_apply], 1 if graphs else 0)
+                       APPLY[interior_apply], 1 if graphs else 0, batch)
         ctx = c_void_p()
         st = lib.vkmg_setup(byref(Grid(N, N)), levels, nu, byref(opts), self._stream(),
                             byref(ctx))
         _check(st, "vkmg_setup")
         self._ctx = ctx
-        self.N, self.levels, self.nu = N, levels, nu
+        self.N, self.levels, self.nu, self.batch = N, levels, nu, batch
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.mg_dtype = torch.float32 if precision == "fp32" else torch.float64
 
@@ -225,7 +229,7 @@ class VkmgSolver:
 
     # ---------------------------------------------------------------- operations
     def residual(self, b, x, r=None):
-        n = self.layout["n"]
+        n = self.layout["n"] * self.batch
         r = self._empty(n, self._torch.float64) if r is None else r
         st = _lib.vkmg_residual(self._ctx, self._ptr(b, self._torch.float64, n, "b"),
                                 self._ptr(x, self._torch.float64, n, "x"),
@@ -234,7 +238,7 @@ class VkmgSolver:
         return r
 
     def apply(self, x, y=None):
-        n = self.layout["n"]
+        n = self.layout["n"] * self.batch
         y = self._empty(n, self._torch.float64) if y is None else y
         st = _lib.vkmg_apply(self._ctx, self._ptr(x, self._torch.float64, n, "x"),
                              self._ptr(y, self._torch.float64, n, "y"), self._stream())
@@ -243,16 +247,19 @@ class VkmgSolver:
 
     def assemble_rhs(self, f, g=None, b=None):
         lay = self.layout
-        b = self._empty(lay["n"], self._torch.float64) if b is None else b
-        gp = c_void_p(None) if g is None else self._ptr(g, self._torch.float64, lay["n_vel"], "g")
-        st = _lib.vkmg_assemble_rhs(self._ctx, self._ptr(f, self._torch.float64, lay["n_vel"], "f"),
-                                    gp, self._ptr(b, self._torch.float64, lay["n"], "b"),
+        nb = self.batch
+        b = self._empty(lay["n"] * nb, self._torch.float64) if b is None else b
+        gp = (c_void_p(None) if g is None
+              else self._ptr(g, self._torch.float64, lay["n_vel"] * nb, "g"))
+        st = _lib.vkmg_assemble_rhs(self._ctx,
+                                    self._ptr(f, self._torch.float64, lay["n_vel"] * nb, "f"),
+                                    gp, self._ptr(b, self._torch.float64, lay["n"] * nb, "b"),
                                     self._stream())
         _check(st, "vkmg_assemble_rhs")
         return b
 
     def vanka_sweep(self, level: int, x, b):
-        n = self.level_layout(level)["n"]
+        n = self.level_layout(level)["n"] * self.batch
         st = _lib.vkmg_vanka_sweep(self._ctx, level, self._ptr(x, self.mg_dtype, n, "x"),
                                    self._ptr(b, self.mg_dtype, n, "b"), self._stream())
         _check(st, "vkmg_vanka_sweep")
@@ -260,15 +267,15 @@ class VkmgSolver:
 
     def vanka_update(self, level: int, x, r):
         """x += sum_i V_i^T W_i A_i^{-1} V_i r (the update half of a sweep)."""
-        n = self.level_layout(level)["n"]
+        n = self.level_layout(level)["n"] * self.batch
         st = _lib.vkmg_vanka_update(self._ctx, level, self._ptr(x, self.mg_dtype, n, "x"),
                                     self._ptr(r, self.mg_dtype, n, "r"), self._stream())
         _check(st, "vkmg_vanka_update")
         return x
 
     def restrict(self, level: int, r_fine, b_coarse=None):
-        nf = self.level_layout(level)["n"]
-        nc = self.level_layout(level - 1)["n"]
+        nf = self.level_layout(level)["n"] * self.batch
+        nc = self.level_layout(level - 1)["n"] * self.batch
         b_coarse = self._empty(nc, self.mg_dtype) if b_coarse is None else b_coarse
         st = _lib.vkmg_restrict(self._ctx, level, self._ptr(r_fine, self.mg_dtype, nf, "r_fine"),
                                 self._ptr(b_coarse, self.mg_dtype, nc, "b_coarse"), self._stream())
@@ -276,15 +283,15 @@ class VkmgSolver:
         return b_coarse
 
     def prolong_add(self, level: int, e_coarse, x_fine):
-        nf = self.level_layout(level)["n"]
-        nc = self.level_layout(level - 1)["n"]
+        nf = self.level_layout(level)["n"] * self.batch
+        nc = self.level_layout(level - 1)["n"] * self.batch
         st = _lib.vkmg_prolong_add(self._ctx, level, self._ptr(e_coarse, self.mg_dtype, nc, "e_coarse"),
                                    self._ptr(x_fine, self.mg_dtype, nf, "x_fine"), self._stream())
         _check(st, "vkmg_prolong_add")
         return x_fine
 
     def coarse_solve(self, r, e=None):
-        n0 = self.level_layout(0)["n"]
+        n0 = self.level_layout(0)["n"] * self.batch
         e = self._empty(n0, self.mg_dtype) if e is None else e
         st = _lib.vkmg_coarse_solve(self._ctx, self._ptr(r, self.mg_dtype, n0, "r"),
                                     self._ptr(e, self.mg_dtype, n0, "e"), self._stream())
@@ -292,7 +299,7 @@ class VkmgSolver:
         return e
 
     def vcycle(self, r, z=None):
-        n = self.layout["n"]
+        n = self.layout["n"] * self.batch
         z = self._empty(n, self._torch.float64) if z is None else z
         st = _lib.vkmg_vcycle(self._ctx, self._ptr(r, self._torch.float64, n, "r"),
                               self._ptr(z, self._torch.float64, n, "z"), self._stream())
@@ -303,15 +310,18 @@ class VkmgSolver:
                      raise_on_error: bool = False):
         """Solve in place (x: initial guess in, solution out).  Returns the
         info dict; NOT_CONVERGED and NONFINITE are reported in it (and raised
-        when ``raise_on_error``)."""
-        n = self.layout["n"]
-        info = Info()
+        when ``raise_on_error``).  Batched contexts: a list of ``batch``
+        info dicts, one per right-hand side."""
+        n = self.layout["n"] * self.batch
+        info = (Info * self.batch)()
         st = _lib.vkmg_fgmres_solve(self._ctx, self._ptr(b, self._torch.float64, n, "b"),
                                     self._ptr(x, self._torch.float64, n, "x"), rtol, restart,
-                                    max_iters, byref(info), self._stream())
+                                    max_iters, info, self._stream())
         if st not in (0, 6, 7) or (raise_on_error and st != 0):
             _check(st, "vkmg_fgmres_solve")
-        return info.as_dict()
+        if self.batch == 1:
+            return info[0].as_dict()
+        return [i.as_dict() for i in info]
 
     def set_timing(self, class_mask: int):
         _check(_lib.vkmg_set_timing(self._ctx, class_mask), "vkmg_set_timing")

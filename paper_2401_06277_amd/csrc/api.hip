@@ -78,6 +78,7 @@ struct vkmg_ctx {
     hipStream_t capture_stream = nullptr;
 
     size_t esize() const { return opt.mg_precision == VKMG_FP32 ? 4 : 8; }
+    int nb() const { return opt.batch; }
     const Geom& top() const { return lev.back().g; }
 };
 
@@ -165,13 +166,13 @@ void sweep_t(vkmg_ctx* c, int l, const T* b, T* x, bool x_zero, hipStream_t s) {
     const T* r = b;
     if (!x_zero) {
         Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
-        launch_residual<T, T>(L.g, b, x, static_cast<T*>(L.r), 0, s);
+        launch_residual<T, T>(L.g, b, x, static_cast<T*>(L.r), 0, s, c->nb());
         r = static_cast<const T*>(L.r);
     }
     Timed t(c, VKMG_KERNEL_VANKA, s, l);
     launch_vanka_update<T>(L.g, r, x_zero ? nullptr : x, x, static_cast<const T*>(L.W),
                            static_cast<const T*>(c->mtab), static_cast<T*>(L.dbuf), c->opt.omega,
-                           c->opt.interior_apply == VKMG_APPLY_MATRIX, s);
+                           c->opt.interior_apply == VKMG_APPLY_MATRIX, s, c->nb());
 }
 
 // MG(l, b) of Algorithm 1 with zero initial guess, result in x.
@@ -187,27 +188,27 @@ void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
     }
     const T* rr = b;
     if (x_zero) {
-        launch_fill_zero<T>(x, L.g.n, s);
+        launch_fill_zero<T>(x, L.g.n * c->nb(), s);
     } else {
         Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
-        launch_residual<T, T>(L.g, b, x, r, 0, s);
+        launch_residual<T, T>(L.g, b, x, r, 0, s, c->nb());
         rr = r;
     }
     T* bc = static_cast<T*>(Lc.b);
     T* xc = static_cast<T*>(Lc.x);
     {
         Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
-        launch_restrict<T>(L.g, Lc.g, rr, bc, s);
+        launch_restrict<T>(L.g, Lc.g, rr, bc, s, c->nb());
     }
     if (l - 1 == 0) {
         Timed t(c, VKMG_KERNEL_COARSE, s, 0);
-        launch_coarse_gemv<T>(Lc.g.n, c->C, bc, xc, s);
+        launch_coarse_gemv<T>(Lc.g.n, c->C, bc, xc, s, c->nb());
     } else {
         mg_t<T>(c, l - 1, bc, xc, s);
     }
     {
         Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
-        launch_prolong_add<T>(L.g, Lc.g, xc, x, s);
+        launch_prolong_add<T>(L.g, Lc.g, xc, x, s, c->nb());
     }
     for (int i = 0; i < c->opt.nu_post; ++i) sweep_t<T>(c, l, b, x, false, s);
 }
@@ -218,9 +219,9 @@ void vcycle_impl(vkmg_ctx* c, const double* r, double* z, hipStream_t s) {
         mg_t<double>(c, top, r, z, s);
     } else {
         LevelBuf& L = c->lev[top];
-        launch_cast<double, float>(r, static_cast<float*>(L.b), L.g.n, s);
+        launch_cast<double, float>(r, static_cast<float*>(L.b), L.g.n * c->nb(), s);
         mg_t<float>(c, top, static_cast<const float*>(L.b), static_cast<float*>(L.x), s);
-        launch_cast<float, double>(static_cast<const float*>(L.x), z, L.g.n, s);
+        launch_cast<float, double>(static_cast<const float*>(L.x), z, L.g.n * c->nb(), s);
     }
 }
 
@@ -249,7 +250,8 @@ int64_t basis_stride(int64_t n) { return (n + 63) / 64 * 64; }
 
 vkmg_status ensure_basis(vkmg_ctx* c, int m) {
     if (m <= c->basis_cap) return VKMG_OK;
-    const int64_t n = basis_stride(c->top().n);
+    // a basis slot holds the batch's vectors back to back
+    const int64_t n = basis_stride(c->top().n * c->nb());
     // captured Arnoldi steps refer to the old basis
     drop_graphs(c);
     // release the old basis (kept in the allocation list until destroy otherwise)
@@ -301,6 +303,272 @@ bool check_level(const vkmg_ctx* c, int32_t level, bool relaxed) {
 
 }  // namespace
 
+namespace {
+
+// Restarted FGMRES for the B > 1 independent systems of a batched context:
+// the Arnoldi steps of all B run as one batched launch per kernel (delayed
+// CGS2, the scheme of the single-system solver for restart <= 32), while
+// the Hessenberg matrices, Givens rotations, stopping tests and restarts
+// are kept per system on the host.  A system that has converged (or broken
+// down) keeps riding along in the batched launches until the cycle ends;
+// its values are ignored.  Device coefficient areas: kHostScratch doubles
+// per system (2j+3 reduced values at 0, alpha/gamma/d/sigma at 300, the
+// starting scale at 900, y at 600).
+vkmg_status fgmres_batched(vkmg_ctx* ctx, const double* b, double* x, double rtol, int m,
+                           int max_iters, vkmg_info* info, hipStream_t s) {
+    const int B = ctx->nb();
+    const Geom& g = ctx->top();
+    const int64_t n = g.n;
+    const int64_t S = basis_stride(n * B);  // stride of the basis slots
+    const int64_t HS = kHostScratch;
+    double* r = ctx->r64;
+    double* w = ctx->w64;
+    double* V = ctx->V;
+    double* Z = ctx->Z;
+    double* hd = ctx->hdev;
+    double* hh = ctx->hhost;
+    double* dco = hd;
+    double* dcf = hd + 300;
+    double* yd = hd + 600;
+    double* alph = hd + 900;
+
+    auto norms = [&](const double* v, std::vector<double>& out) -> vkmg_status {
+        {
+            Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+            launch_mdot_partial(v, 0, 1, v, n, ctx->part, s, B, n);
+            launch_reduce_partials(ctx->part, 1, hd, s, B, HS);
+        }
+        VKMG_HIP(hipMemcpy2DAsync(hh, HS * 8, hd, HS * 8, 8, B, hipMemcpyDeviceToHost, s));
+        VKMG_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < B; ++k) out[k] = std::sqrt(hh[k * HS]);
+        return VKMG_OK;
+    };
+    auto residual = [&]() {
+        Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
+        launch_residual<double, double>(g, b, x, r, 0, s, B);
+    };
+    struct Sys {
+        std::vector<double> Hu, R, cs, sn, gbase, gv, y;
+        double beta0 = 0, beta = 0, target = 0, est = 1, true_rel = 0, sigma_prev = 0;
+        int iters = 0, restarts = 0, kdone = 0;
+        bool done = false, active = false, cycled = false;
+        vkmg_status status = VKMG_OK;
+        double& H(int i, int j, int m_) { return Hu[size_t(i) * m_ + j]; }
+        double& RR(int i, int j, int m_) { return R[size_t(i) * m_ + j]; }
+    };
+    std::vector<Sys> sys(B);
+    for (Sys& q : sys) {
+        q.Hu.assign(size_t(m + 1) * m, 0.0);
+        q.R.assign(size_t(m + 1) * m, 0.0);
+        q.cs.assign(m, 0.0);
+        q.sn.assign(m, 0.0);
+        q.gbase.assign(m + 1, 0.0);
+        q.gv.assign(m + 1, 0.0);
+        q.y.assign(m, 0.0);
+    }
+    auto rotate_column = [&](Sys& q, int j) {
+        for (int i = 0; i <= j + 1; ++i) q.RR(i, j, m) = q.H(i, j, m);
+        for (int i = 0; i < j; ++i) {
+            const double t = q.cs[i] * q.RR(i, j, m) + q.sn[i] * q.RR(i + 1, j, m);
+            q.RR(i + 1, j, m) = -q.sn[i] * q.RR(i, j, m) + q.cs[i] * q.RR(i + 1, j, m);
+            q.RR(i, j, m) = t;
+        }
+        const double denom = std::hypot(q.RR(j, j, m), q.RR(j + 1, j, m));
+        q.cs[j] = q.RR(j, j, m) / denom;
+        q.sn[j] = q.RR(j + 1, j, m) / denom;
+        q.RR(j, j, m) = denom;
+        q.RR(j + 1, j, m) = 0.0;
+    };
+    auto rotate_rhs = [&](Sys& q, std::vector<double>& gg, int j) {
+        gg[j + 1] = -q.sn[j] * gg[j];
+        gg[j] = q.cs[j] * gg[j];
+    };
+
+    residual();
+    std::vector<double> nrm(B);
+    vkmg_status st = norms(r, nrm);
+    if (st != VKMG_OK) return st;
+    for (int k = 0; k < B; ++k) {
+        Sys& q = sys[k];
+        q.beta0 = q.beta = nrm[k];
+        q.target = rtol * q.beta0;
+        if (!std::isfinite(q.beta0)) {
+            q.done = true;
+            q.status = VKMG_ERR_NONFINITE;
+            q.est = q.true_rel = NAN;
+        } else if (q.beta0 == 0.0) {
+            q.done = true;
+            q.est = q.true_rel = 0.0;
+        }
+    }
+    auto step = [&](int j, hipStream_t ss) {
+        double* vj = V + int64_t(j) * S;
+        double* zj = Z + int64_t(j) * S;
+        vcycle_impl(ctx, vj, zj, ss);
+        {
+            Timed t(ctx, VKMG_KERNEL_RESIDUAL, ss);
+            launch_residual<double, double>(g, nullptr, zj, w, 1, ss, B);
+        }
+        Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);
+        launch_dcgs_dots(V, S, j, vj, w, n, ctx->part, ss, B, n);
+        launch_reduce_partials(ctx->part, 2 * j + 3, dco, ss, B, HS);
+        launch_dcgs_update(V, S, j, dco, vj, w, V + int64_t(j + 1) * S, n, dcf, ss, B, n, HS);
+    };
+    const bool use_graphs = ctx->opt.use_graphs != 0 && ctx->timing_mask == 0;
+    if (use_graphs && ctx->graphs_scheme != 2) {
+        drop_graphs(ctx);
+        ctx->graphs_scheme = 2;
+    }
+    for (;;) {
+        int nactive = 0;
+        for (int k = 0; k < B; ++k) {
+            Sys& q = sys[k];
+            q.cycled = q.active = !q.done;
+            q.kdone = 0;
+            q.sigma_prev = 0.0;
+            std::fill(q.Hu.begin(), q.Hu.end(), 0.0);
+            std::fill(q.gbase.begin(), q.gbase.end(), 0.0);
+            q.gbase[0] = q.beta;
+            hh[k * HS + 900] = q.active ? 1.0 / q.beta : 0.0;
+            nactive += q.active;
+        }
+        if (nactive == 0) break;
+        VKMG_HIP(hipMemcpy2DAsync(alph, HS * 8, hh + 900, HS * 8, 8, B, hipMemcpyHostToDevice, s));
+        {
+            Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+            launch_scale_batched(r, n, alph, HS, V, n, n, B, s);
+        }
+        for (int j = 0; j < m; ++j) {
+            if (use_graphs) {
+                st = step_graph(ctx, j, step);
+                if (st != VKMG_OK) return st;
+                VKMG_HIP(hipGraphLaunch(ctx->step_graphs[j], s));
+            } else {
+                step(j, s);
+            }
+            VKMG_HIP(hipMemcpy2DAsync(hh, HS * 8, dco, HS * 8, sizeof(double) * (2 * j + 3), B,
+                                      hipMemcpyDeviceToHost, s));
+            VKMG_HIP(hipMemcpy2DAsync(hh + 300, HS * 8, dcf, HS * 8, sizeof(double) * 4, B,
+                                      hipMemcpyDeviceToHost, s));
+            VKMG_HIP(hipStreamSynchronize(s));
+            int still = 0;
+            for (int k = 0; k < B; ++k) {
+                Sys& q = sys[k];
+                if (!q.active) continue;
+                const double* c = hh + k * HS;
+                const double alpha = c[300], gamma = c[301], d = c[302], sigma = c[303];
+                bool finite = true;
+                if (j > 0) {  // finalise column j-1
+                    for (int i = 0; i < j; ++i) q.H(i, j - 1, m) += c[j + i] / q.sigma_prev;
+                    q.H(j, j - 1, m) = alpha / q.sigma_prev;
+                    for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(q.H(i, j - 1, m));
+                }
+                for (int i = 0; i < j; ++i) q.H(i, j, m) = c[i];
+                q.H(j, j, m) = gamma;
+                const double hnext = d > 0.0 ? std::sqrt(d) : 0.0;
+                q.sigma_prev = sigma;
+                for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(q.H(i, j, m));
+                q.H(j + 1, j, m) = hnext;
+                ++q.iters;
+                if (!finite || !std::isfinite(hnext)) {
+                    q.active = q.cycled = false;
+                    q.done = true;
+                    q.status = VKMG_ERR_NONFINITE;
+                    q.est = q.true_rel = NAN;
+                    continue;
+                }
+                if (j > 0) {
+                    rotate_column(q, j - 1);
+                    rotate_rhs(q, q.gbase, j - 1);
+                }
+                rotate_column(q, j);
+                q.gv = q.gbase;
+                rotate_rhs(q, q.gv, j);
+                q.kdone = j + 1;
+                q.est = std::fabs(q.gv[j + 1]) / q.beta0;
+                if (std::fabs(q.gv[j + 1]) <= q.target || hnext == 0.0 || q.iters >= max_iters)
+                    q.active = false;
+                else
+                    ++still;
+            }
+            if (still == 0) break;
+        }
+        // x += Z y per system (zero coefficients beyond its own cycle length)
+        int kmax = 0;
+        for (int k = 0; k < B; ++k) {
+            Sys& q = sys[k];
+            const int kk = q.cycled ? q.kdone : 0;
+            for (int i = kk - 1; i >= 0; --i) {
+                double acc = q.gv[i];
+                for (int l = i + 1; l < kk; ++l) acc -= q.RR(i, l, m) * q.y[l];
+                q.y[i] = acc / q.RR(i, i, m);
+            }
+            kmax = std::max(kmax, kk);
+        }
+        if (kmax > 0) {
+            for (int k = 0; k < B; ++k) {
+                const Sys& q = sys[k];
+                const int kk = q.cycled ? q.kdone : 0;
+                for (int i = 0; i < kmax; ++i) hh[k * HS + 600 + i] = i < kk ? q.y[i] : 0.0;
+            }
+            VKMG_HIP(hipMemcpy2DAsync(yd, HS * 8, hh + 600, HS * 8, sizeof(double) * kmax, B,
+                                      hipMemcpyHostToDevice, s));
+            Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+            launch_axpy_multi(Z, S, kmax, yd, x, n, s, B, n, HS);
+        }
+        residual();
+        st = norms(r, nrm);
+        if (st != VKMG_OK) return st;
+        bool all_done = true;
+        for (int k = 0; k < B; ++k) {
+            Sys& q = sys[k];
+            if (q.cycled) {
+                const double rn = nrm[k];
+                q.true_rel = rn / q.beta0;
+                if (!std::isfinite(rn)) {
+                    q.done = true;
+                    q.status = VKMG_ERR_NONFINITE;
+                } else if (rn <= q.target) {
+                    q.done = true;
+                    q.status = VKMG_OK;
+                } else if (q.iters >= max_iters) {
+                    q.done = true;
+                    q.status = VKMG_ERR_NOT_CONVERGED;
+                } else if (std::fabs(q.gv[q.kdone]) <= q.target && rn > 0.5 * q.beta) {
+                    // estimate met, true residual did not and did not halve:
+                    // below the rounding floor of the system
+                    q.done = true;
+                    q.status = VKMG_ERR_NOT_CONVERGED;
+                } else {
+                    q.beta = rn;
+                    ++q.restarts;
+                }
+            }
+            all_done = all_done && q.done;
+        }
+        if (all_done) break;
+    }
+    vkmg_status first = VKMG_OK;
+    for (int k = 0; k < B; ++k) {
+        const Sys& q = sys[k];
+        if (info) {
+            info[k].iterations = q.iters;
+            info[k].restarts = q.restarts;
+            info[k].est_rel_res = q.est;
+            info[k].true_rel_res = q.true_rel;
+            info[k].status = q.status;
+        }
+        if (first == VKMG_OK && q.status != VKMG_OK) first = q.status;
+    }
+    if (first == VKMG_ERR_NOT_CONVERGED)
+        g_last_error = "fgmres_solve: a right-hand side of the batch did not converge";
+    if (first == VKMG_ERR_NONFINITE)
+        g_last_error = "fgmres_solve: non-finite residual in a right-hand side of the batch";
+    return first;
+}
+
+}  // namespace
+
 // =====================================================================================
 // C ABI
 // =====================================================================================
@@ -315,6 +583,7 @@ vkmg_options vkmg_default_options(void) {
     o.mg_precision = VKMG_FP64;
     o.interior_apply = VKMG_APPLY_VECTOR;
     o.use_graphs = 1;
+    o.batch = 1;
     return o;
 }
 
@@ -381,6 +650,8 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         return fail(VKMG_ERR_INVALID_ARG, "setup: bad interior_apply");
     if (o.use_graphs != 0 && o.use_graphs != 1)
         return fail(VKMG_ERR_INVALID_ARG, "setup: use_graphs must be 0 or 1");
+    if (o.batch < 1 || o.batch > 64)
+        return fail(VKMG_ERR_INVALID_ARG, "setup: batch must be in [1, 64]");
 
     // host work first (no GPU needed to detect singular patches)
     double B1[651];
@@ -432,11 +703,12 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
     for (int l = 0; l < levels && st == VKMG_OK; ++l) {
         LevelBuf& L = c->lev[l];
         L.g = make_geom(N >> (levels - 1 - l), nu);
-        st = alloc(c.get(), &L.x, es * L.g.n);
-        if (st == VKMG_OK) st = alloc(c.get(), &L.b, es * L.g.n);
-        if (st == VKMG_OK) st = alloc(c.get(), &L.r, es * L.g.n);
+        const size_t nbt = size_t(o.batch);
+        st = alloc(c.get(), &L.x, es * L.g.n * nbt);
+        if (st == VKMG_OK) st = alloc(c.get(), &L.b, es * L.g.n * nbt);
+        if (st == VKMG_OK) st = alloc(c.get(), &L.r, es * L.g.n * nbt);
         if (st == VKMG_OK && l >= 1)
-            st = alloc(c.get(), &L.dbuf, es * size_t(vanka_boundary_scratch(L.g.N)));
+            st = alloc(c.get(), &L.dbuf, es * size_t(vanka_boundary_scratch(L.g.N)) * nbt);
         if (st == VKMG_OK && l >= 1) {
             const size_t nw = size_t(kLevelTable);
             st = alloc(c.get(), &L.W, es * nw);
@@ -466,12 +738,17 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         if (e != hipSuccess) st = fail(VKMG_ERR_HIP, "setup: upload of coarse inverse");
     }
     const int64_t n = c->top().n;
-    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->r64), 8 * n);
-    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->w64), 8 * n);
-    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->part), 8 * size_t(kDotBlocks) * 264);
-    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->hdev), 8 * kHostScratch);
+    const size_t nbt = size_t(o.batch);
+    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->r64), 8 * n * nbt);
+    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->w64), 8 * n * nbt);
+    // partials: 264 rows of kDotBlocks, or 65 rows of dot_blocks(B) per batch entry
     if (st == VKMG_OK) {
-        hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->hhost), 8 * kHostScratch, hipHostMallocDefault);
+        const size_t rows = std::max<size_t>(size_t(kDotBlocks) * 264, size_t(dot_blocks(o.batch)) * 65 * nbt);
+        st = alloc(c.get(), reinterpret_cast<void**>(&c->part), 8 * rows);
+    }
+    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->hdev), 8 * kHostScratch * nbt);
+    if (st == VKMG_OK) {
+        hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->hhost), 8 * kHostScratch * nbt, hipHostMallocDefault);
         if (e != hipSuccess) st = fail(VKMG_ERR_OUT_OF_MEMORY, "setup: pinned host buffer");
     }
     if (st == VKMG_OK) {
@@ -519,7 +796,7 @@ vkmg_status vkmg_residual(vkmg_ctx* ctx, const double* b, const double* x, doubl
     VKMG_HIP(hipSetDevice(ctx->device));
     hipStream_t s = as_stream(stream);
     Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
-    launch_residual<double, double>(ctx->top(), b, x, r, 0, s);
+    launch_residual<double, double>(ctx->top(), b, x, r, 0, s, ctx->nb());
     VKMG_HIP(hipGetLastError());
     return VKMG_OK;
 }
@@ -530,7 +807,7 @@ vkmg_status vkmg_apply(vkmg_ctx* ctx, const double* x, double* y, void* stream) 
     VKMG_HIP(hipSetDevice(ctx->device));
     hipStream_t s = as_stream(stream);
     Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
-    launch_residual<double, double>(ctx->top(), nullptr, x, y, 1, s);
+    launch_residual<double, double>(ctx->top(), nullptr, x, y, 1, s, ctx->nb());
     VKMG_HIP(hipGetLastError());
     return VKMG_OK;
 }
@@ -540,7 +817,7 @@ vkmg_status vkmg_assemble_rhs(vkmg_ctx* ctx, const double* f, const double* g, d
     if (!ctx || !f || !b) return fail(VKMG_ERR_INVALID_ARG, "assemble_rhs: NULL f or b");
     if (b == f || b == g) return fail(VKMG_ERR_INVALID_ARG, "assemble_rhs: b must not alias f or g");
     VKMG_HIP(hipSetDevice(ctx->device));
-    launch_rhs(ctx->top(), f, g, b, as_stream(stream));
+    launch_rhs(ctx->top(), f, g, b, as_stream(stream), ctx->nb());
     VKMG_HIP(hipGetLastError());
     return VKMG_OK;
 }
@@ -572,12 +849,14 @@ vkmg_status vkmg_vanka_update(vkmg_ctx* ctx, int32_t level, void* x, const void*
         launch_vanka_update<double>(L.g, static_cast<const double*>(r), static_cast<double*>(x),
                                     static_cast<double*>(x), static_cast<const double*>(L.W),
                                     static_cast<const double*>(ctx->mtab),
-                                    static_cast<double*>(L.dbuf), ctx->opt.omega, mfma, s);
+                                    static_cast<double*>(L.dbuf), ctx->opt.omega, mfma, s,
+                                    ctx->nb());
     else
         launch_vanka_update<float>(L.g, static_cast<const float*>(r), static_cast<float*>(x),
                                    static_cast<float*>(x), static_cast<const float*>(L.W),
                                    static_cast<const float*>(ctx->mtab),
-                                   static_cast<float*>(L.dbuf), ctx->opt.omega, mfma, s);
+                                   static_cast<float*>(L.dbuf), ctx->opt.omega, mfma, s,
+                                   ctx->nb());
     VKMG_HIP(hipGetLastError());
     return VKMG_OK;
 }
@@ -592,9 +871,11 @@ vkmg_status vkmg_restrict(vkmg_ctx* ctx, int32_t level, const void* r_fine, void
     const Geom& gc = ctx->lev[level - 1].g;
     Timed t(ctx, VKMG_KERNEL_TRANSFER, s);
     if (ctx->opt.mg_precision == VKMG_FP64)
-        launch_restrict<double>(gf, gc, static_cast<const double*>(r_fine), static_cast<double*>(b_coarse), s);
+        launch_restrict<double>(gf, gc, static_cast<const double*>(r_fine), static_cast<double*>(b_coarse), s,
+                                ctx->nb());
     else
-        launch_restrict<float>(gf, gc, static_cast<const float*>(r_fine), static_cast<float*>(b_coarse), s);
+        launch_restrict<float>(gf, gc, static_cast<const float*>(r_fine), static_cast<float*>(b_coarse), s,
+                               ctx->nb());
     VKMG_HIP(hipGetLastError());
     return VKMG_OK;
 }
@@ -609,9 +890,11 @@ vkmg_status vkmg_prolong_add(vkmg_ctx* ctx, int32_t level, const void* e_coarse,
     const Geom& gc = ctx->lev[level - 1].g;
     Timed t(ctx, VKMG_KERNEL_TRANSFER, s);
     if (ctx->opt.mg_precision == VKMG_FP64)
-        launch_prolong_add<double>(gf, gc, static_cast<const double*>(e_coarse), static_cast<double*>(x_fine), s);
+        launch_prolong_add<double>(gf, gc, static_cast<const double*>(e_coarse), static_cast<double*>(x_fine), s,
+                                   ctx->nb());
     else
-        launch_prolong_add<float>(gf, gc, static_cast<const float*>(e_coarse), static_cast<float*>(x_fine), s);
+        launch_prolong_add<float>(gf, gc, static_cast<const float*>(e_coarse), static_cast<float*>(x_fine), s,
+                                  ctx->nb());
     VKMG_HIP(hipGetLastError());
     return VKMG_OK;
 }
@@ -623,9 +906,11 @@ vkmg_status vkmg_coarse_solve(vkmg_ctx* ctx, const void* r, void* e, void* strea
     hipStream_t s = as_stream(stream);
     Timed t(ctx, VKMG_KERNEL_COARSE, s);
     if (ctx->opt.mg_precision == VKMG_FP64)
-        launch_coarse_gemv<double>(ctx->lev[0].g.n, ctx->C, static_cast<const double*>(r), static_cast<double*>(e), s);
+        launch_coarse_gemv<double>(ctx->lev[0].g.n, ctx->C, static_cast<const double*>(r), static_cast<double*>(e), s,
+                                   ctx->nb());
     else
-        launch_coarse_gemv<float>(ctx->lev[0].g.n, ctx->C, static_cast<const float*>(r), static_cast<float*>(e), s);
+        launch_coarse_gemv<float>(ctx->lev[0].g.n, ctx->C, static_cast<const float*>(r), static_cast<float*>(e), s,
+                                  ctx->nb());
     VKMG_HIP(hipGetLastError());
     return VKMG_OK;
 }
@@ -642,18 +927,22 @@ vkmg_status vkmg_vcycle(vkmg_ctx* ctx, const double* r, double* z, void* stream)
 vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double rtol,
                               int32_t restart, int32_t max_iters, vkmg_info* info, void* stream) {
     if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->status = VKMG_ERR_INVALID_ARG;
+        const int nbi = ctx ? ctx->nb() : 1;
+        std::memset(info, 0, sizeof(*info) * size_t(nbi));
+        for (int k = 0; k < nbi; ++k) info[k].status = VKMG_ERR_INVALID_ARG;
     }
     if (!ctx || !b || !x) return fail(VKMG_ERR_INVALID_ARG, "fgmres_solve: NULL argument");
     if (b == x) return fail(VKMG_ERR_INVALID_ARG, "fgmres_solve: x must not alias b");
     if (restart < 1 || restart > 256) return fail(VKMG_ERR_INVALID_ARG, "fgmres_solve: restart must be in [1, 256]");
     if (max_iters < 1) return fail(VKMG_ERR_INVALID_ARG, "fgmres_solve: max_iters must be >= 1");
     if (!(rtol >= 0.0) || !std::isfinite(rtol)) return fail(VKMG_ERR_INVALID_ARG, "fgmres_solve: bad rtol");
+    if (ctx->nb() > 1 && restart > kDelayedMaxRestart)
+        return fail(VKMG_ERR_UNSUPPORTED, "fgmres_solve: batched contexts need restart <= 32");
     VKMG_HIP(hipSetDevice(ctx->device));
     hipStream_t s = as_stream(stream);
     vkmg_status st = ensure_basis(ctx, restart);
     if (st != VKMG_OK) return st;
+    if (ctx->nb() > 1) return fgmres_batched(ctx, b, x, rtol, restart, max_iters, info, s);
     const Geom& g = ctx->top();
     const int64_t n = g.n;
     const int64_t ld = basis_stride(n);

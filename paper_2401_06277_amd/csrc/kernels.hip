@@ -109,6 +109,12 @@ __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void r
     const int per_xcd = (ntile + 7) / 8;
     const int tlin = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (tlin >= ntile) return;
+    {  // right-hand side blockIdx.y of a batch (vectors g.n apart)
+        const int64_t bo = int64_t(blockIdx.y) * g.n;
+        if (MODE == 0) b += bo;
+        x += bo;
+        r += bo;
+    }
     const int E0x = (tlin % tiles) * RT, E0y = (tlin / tiles) * RT;
     const int ox = 2 * E0x - 2, oy = 2 * E0y - 2;
     // every load of the tile is issued before the first is used: addresses
@@ -240,6 +246,12 @@ __global__ __launch_bounds__(256) void rhs_kernel(Geom g, const double* __restri
     const int ex = blockIdx.x * 16 + (threadIdx.x & 15);
     const int ey = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (ex > g.N || ey > g.N) return;
+    {  // right-hand side blockIdx.z of a batch
+        const int64_t z = blockIdx.z;
+        f += z * 2 * g.nq2;
+        if (gd) gd += z * 2 * g.nq2;
+        b += z * g.n;
+    }
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb) {
 #pragma unroll
@@ -400,6 +412,8 @@ __global__ __launch_bounds__(256) void vanka_boundary_kernel(Geom g, const T* __
     __shared__ T s_r[4][kBP][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nb = n_boundary_patches(g.N);
+    rb += int64_t(blockIdx.y) * g.n;  // right-hand side blockIdx.y of a batch
+    dbuf += int64_t(blockIdx.y) * nb * 64;
     const int k0 = (blockIdx.x * 4 + w) * kBP;
     const int s = lane < kSlots ? lane : 0;
     int cls[kBP];
@@ -551,6 +565,13 @@ __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __
     const int per_xcd = (ntile + 7) / 8;
     const int tlin = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (tlin >= ntile) return;
+    {  // right-hand side blockIdx.y of a batch
+        const int64_t bo = int64_t(blockIdx.y) * g.n;
+        rb += bo;
+        if (xin) xin += bo;
+        xout += bo;
+        dbuf += int64_t(blockIdx.y) * n_boundary_patches(g.N) * 64;
+    }
     const int E0x = (tlin % tiles) * VT, E0y = (tlin / tiles) * VT;
     const int tx = threadIdx.x % VP, ty = threadIdx.x / VP;
     const int I = E0x - 1 + tx, J = E0y - 1 + ty;
@@ -652,6 +673,13 @@ __global__ __launch_bounds__(VNT, 2) void vanka_mfma_kernel(Geom g, const T* __r
     const int per_xcd = (ntile + 7) / 8;
     const int tlin = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (tlin >= ntile) return;
+    {  // right-hand side blockIdx.y of a batch
+        const int64_t bo = int64_t(blockIdx.y) * g.n;
+        rb += bo;
+        if (xin) xin += bo;
+        xout += bo;
+        dbuf += int64_t(blockIdx.y) * n_boundary_patches(g.N) * 64;
+    }
     const int E0x = (tlin % tiles) * VT, E0y = (tlin / tiles) * VT;
 
     // operands of the universal interior operator (one per lane and step)
@@ -796,6 +824,8 @@ __global__ __launch_bounds__(256) void restrict_kernel(Geom gf, Geom gc, const T
     const int ic = blockIdx.x * 64 + (threadIdx.x & 63);  // 64 x 4 threads per block:
     const int jg = blockIdx.y * 4 + (threadIdx.x >> 6);   // a wave reads whole rows
     if (ic >= gc.s2 || jg >= gc.N) return;
+    rf += int64_t(blockIdx.z) * gf.n;  // right-hand side blockIdx.z of a batch
+    bc += int64_t(blockIdx.z) * gc.n;
     const bool last = jg == gc.N - 1;
     {
         constexpr int kRow[6] = {-3, -1, 0, 1, 2, 3};
@@ -908,6 +938,8 @@ __global__ __launch_bounds__(256) void prolong_kernel(Geom gf, Geom gc, const T*
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);  // 64 x 4 threads per block:
     const int jg = blockIdx.y * 4 + (threadIdx.x >> 6);  // a wave reads whole rows
     if (i >= gf.s2 || jg >= gc.N) return;
+    ec += int64_t(blockIdx.z) * gc.n;  // right-hand side blockIdx.z of a batch
+    xf += int64_t(blockIdx.z) * gf.n;
     {
         int cx[3];
         double wx[3];
@@ -993,6 +1025,8 @@ __global__ __launch_bounds__(256) void coarse_gemv_kernel(int64_t n, const doubl
     const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
+    r += int64_t(blockIdx.y) * n;  // right-hand side blockIdx.y of a batch
+    e += int64_t(blockIdx.y) * n;
     double s = 0.0;
     for (int64_t c = lane; c < n; c += 64) s += C[row * n + c] * double(r[c]);
     s = wave_sum(s);
@@ -1024,16 +1058,34 @@ __global__ void scale_kernel(const double* __restrict__ in, double alpha, double
         out[i] = alpha * in[i];
 }
 
+// out_k = alpha[k * sa] * in_k for the batch vectors k = blockIdx.y
+// (in_k at in + k * sin, out_k at out + k * sout); alpha 0 writes zeros
+__global__ void scale_batched_kernel(const double* __restrict__ in, int64_t sin,
+                                     const double* __restrict__ alpha, int64_t sa,
+                                     double* __restrict__ out, int64_t sout, int64_t n) {
+    const int64_t k = blockIdx.y;
+    const double a = alpha[k * sa];
+    in += k * sin;
+    out += k * sout;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = a == 0.0 ? 0.0 : a * in[i];  // alpha 0: zeros even where in is not finite
+}
+
 // ---------------------------------------------------------------------------
 // Krylov: multi-dot, reduction, update, multi-axpy
 // ---------------------------------------------------------------------------
 
+// Batched over blockIdx.y: V and w advance by sb, part by k * gridDim.x.
 template <int KMAX>
 __global__ __launch_bounds__(256) void mdot_partial_kernel(const double* __restrict__ V,
                                                            int64_t ldv, int k,
                                                            const double* __restrict__ w,
                                                            int64_t n,
-                                                           double* __restrict__ part) {
+                                                           double* __restrict__ part, int64_t sb) {
+    V += int64_t(blockIdx.y) * sb;
+    w += int64_t(blockIdx.y) * sb;
+    part += int64_t(blockIdx.y) * k * gridDim.x;
     double acc[KMAX];
 #pragma unroll
     for (int v = 0; v < KMAX; ++v) acc[v] = 0.0;
@@ -1057,10 +1109,15 @@ __global__ __launch_bounds__(256) void mdot_partial_kernel(const double* __restr
             (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
 }
 
+// out[v] = sum of the nblk partials of row v; batched over blockIdx.y
+// (partials of gridDim.x rows per batch entry, outputs so apart)
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ part,
                                                               int nblk,
-                                                              double* __restrict__ out) {
+                                                              double* __restrict__ out,
+                                                              int64_t so) {
     const int v = blockIdx.x;
+    part += int64_t(blockIdx.y) * gridDim.x * nblk;
+    out += int64_t(blockIdx.y) * so;
     double s = 0.0;
     for (int i = threadIdx.x; i < nblk; i += 256) s += part[int64_t(v) * nblk + i];
     __shared__ double red[4];
@@ -1155,7 +1212,14 @@ template <int KMAX>
 __global__ __launch_bounds__(256) void dcgs_dots_kernel(const double* __restrict__ V, int64_t ldv,
                                                         int j, const double* __restrict__ u,
                                                         const double* __restrict__ w, int64_t n,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, int64_t sb) {
+    {  // batch entry blockIdx.y: vectors sb apart, 2j+3 rows of partials each
+        const int64_t bo = int64_t(blockIdx.y) * sb;
+        V += bo;
+        u += bo;
+        w += bo;
+        part += int64_t(blockIdx.y) * (2 * j + 3) * gridDim.x;
+    }
     double aw[KMAX], au[KMAX];
     double uu = 0.0, uw = 0.0, ww = 0.0;
 #pragma unroll
@@ -1214,7 +1278,17 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(const double* __restri
                                                           int j, const double* __restrict__ c,
                                                           double* uv, const double* __restrict__ w,
                                                           double* __restrict__ next, int64_t n,
-                                                          double* __restrict__ cf) {
+                                                          double* __restrict__ cf, int64_t sb,
+                                                          int64_t sc) {
+    {  // batch entry blockIdx.y: vectors sb apart, coefficients sc apart
+        const int64_t bo = int64_t(blockIdx.y) * sb;
+        V += bo;
+        uv += bo;
+        w += bo;
+        next += bo;
+        c += int64_t(blockIdx.y) * sc;
+        cf += int64_t(blockIdx.y) * sc;
+    }
     double hv[KMAX], sv[KMAX];
     double ss = 0.0, hh = 0.0, sh = 0.0;
 #pragma unroll
@@ -1277,7 +1351,11 @@ __global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ 
 template <int KMAX>
 __global__ __launch_bounds__(256) void axpy_multi_kernel(const double* __restrict__ Z, int64_t ldz,
                                                          int k, const double* __restrict__ y,
-                                                         double* __restrict__ x, int64_t n) {
+                                                         double* __restrict__ x, int64_t n,
+                                                         int64_t sb, int64_t sy) {
+    Z += int64_t(blockIdx.y) * sb;  // batch entry blockIdx.y
+    x += int64_t(blockIdx.y) * sb;
+    y += int64_t(blockIdx.y) * sy;
     double yv[KMAX];
 #pragma unroll
     for (int v = 0; v < KMAX; ++v) yv[v] = v < k ? y[v] : 0.0;
@@ -1321,21 +1399,23 @@ int elementwise_blocks(int64_t n) {
 // ---------------------------------------------------------------------------
 
 template <typename Tx, typename T>
-void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hipStream_t s) {
+void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hipStream_t s,
+                     int nb) {
     const int tiles = (g.N + 1 + RT - 1) / RT;
-    const int grid = 8 * ((tiles * tiles + 7) / 8);
+    const dim3 grid(8 * ((tiles * tiles + 7) / 8), nb);
     if (mode == 0)
         residual_kernel<0, Tx, T><<<grid, RNT, 0, s>>>(g, b, x, r);
     else
         residual_kernel<1, Tx, T><<<grid, RNT, 0, s>>>(g, b, x, r);
 }
 template void launch_residual<double, double>(const Geom&, const double*, const double*, double*,
-                                              int, hipStream_t);
+                                              int, hipStream_t, int);
 template void launch_residual<float, float>(const Geom&, const float*, const float*, float*, int,
-                                            hipStream_t);
+                                            hipStream_t, int);
 
-void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hipStream_t s) {
-    const dim3 grid((g.N + 1 + 15) / 16, (g.N + 1 + 15) / 16);
+void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hipStream_t s,
+                int nb) {
+    const dim3 grid((g.N + 1 + 15) / 16, (g.N + 1 + 15) / 16, nb);
     rhs_kernel<<<grid, 256, 0, s>>>(g, f, gd, b);
 }
 
@@ -1343,20 +1423,21 @@ int64_t vanka_boundary_scratch(int N) { return int64_t(n_boundary_patches(N)) * 
 
 template <typename T>
 void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const T* table,
-                         const T* mtab, T* dbuf, double omega, bool mfma, hipStream_t s) {
+                         const T* mtab, T* dbuf, double omega, bool mfma, hipStream_t s,
+                         int nrhs) {
     const int nb = n_boundary_patches(g.N);
-    const int per = boundary_patches_per_wave(nb);
-    const int nblk = (nb + 4 * per - 1) / (4 * per);
+    const int per = boundary_patches_per_wave(nb * nrhs);
+    const dim3 bgrid((nb + 4 * per - 1) / (4 * per), nrhs);
     if (per == 8)
-        vanka_boundary_kernel<T, 8><<<nblk, 256, 0, s>>>(g, r, table, dbuf);
+        vanka_boundary_kernel<T, 8><<<bgrid, 256, 0, s>>>(g, r, table, dbuf);
     else if (per == 4)
-        vanka_boundary_kernel<T, 4><<<nblk, 256, 0, s>>>(g, r, table, dbuf);
+        vanka_boundary_kernel<T, 4><<<bgrid, 256, 0, s>>>(g, r, table, dbuf);
     else if (per == 2)
-        vanka_boundary_kernel<T, 2><<<nblk, 256, 0, s>>>(g, r, table, dbuf);
+        vanka_boundary_kernel<T, 2><<<bgrid, 256, 0, s>>>(g, r, table, dbuf);
     else
-        vanka_boundary_kernel<T, 1><<<nblk, 256, 0, s>>>(g, r, table, dbuf);
+        vanka_boundary_kernel<T, 1><<<bgrid, 256, 0, s>>>(g, r, table, dbuf);
     const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
-    const int grid = 8 * ((ntile + 7) / 8);
+    const dim3 grid(8 * ((ntile + 7) / 8), nrhs);
     if (mfma)
         vanka_mfma_kernel<T><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf, mtab, T(omega / g.nu),
                                                   T(g.nu / g.h));
@@ -1366,36 +1447,40 @@ void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const
 }
 template void launch_vanka_update<double>(const Geom&, const double*, const double*, double*,
                                           const double*, const double*, double*, double, bool,
-                                          hipStream_t);
+                                          hipStream_t, int);
 template void launch_vanka_update<float>(const Geom&, const float*, const float*, float*,
                                          const float*, const float*, float*, double, bool,
-                                         hipStream_t);
+                                         hipStream_t, int);
 
 template <typename T>
-void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, hipStream_t s) {
-    const dim3 grid((gc.s2 + 63) / 64, (gc.N + 3) / 4);
+void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, hipStream_t s, int nb) {
+    const dim3 grid((gc.s2 + 63) / 64, (gc.N + 3) / 4, nb);
     restrict_kernel<T><<<grid, 256, 0, s>>>(gf, gc, rf, bc);
 }
-template void launch_restrict<double>(const Geom&, const Geom&, const double*, double*, hipStream_t);
-template void launch_restrict<float>(const Geom&, const Geom&, const float*, float*, hipStream_t);
+template void launch_restrict<double>(const Geom&, const Geom&, const double*, double*, hipStream_t,
+                                      int);
+template void launch_restrict<float>(const Geom&, const Geom&, const float*, float*, hipStream_t,
+                                     int);
 
 template <typename T>
-void launch_prolong_add(const Geom& gf, const Geom& gc, const T* ec, T* xf, hipStream_t s) {
-    const dim3 grid((gf.s2 + 63) / 64, (gc.N + 3) / 4);
+void launch_prolong_add(const Geom& gf, const Geom& gc, const T* ec, T* xf, hipStream_t s, int nb) {
+    const dim3 grid((gf.s2 + 63) / 64, (gc.N + 3) / 4, nb);
     prolong_kernel<T><<<grid, 256, 0, s>>>(gf, gc, ec, xf);
 }
 template void launch_prolong_add<double>(const Geom&, const Geom&, const double*, double*,
-                                         hipStream_t);
+                                         hipStream_t, int);
 template void launch_prolong_add<float>(const Geom&, const Geom&, const float*, float*,
-                                        hipStream_t);
+                                        hipStream_t, int);
 
 template <typename T>
-void launch_coarse_gemv(int64_t n, const double* C, const T* r, T* e, hipStream_t s) {
-    coarse_gemv_kernel<T><<<int((n + 3) / 4), 256, 0, s>>>(n, C, r, e);
+void launch_coarse_gemv(int64_t n, const double* C, const T* r, T* e, hipStream_t s, int nb) {
+    const dim3 grid(int((n + 3) / 4), nb);
+    coarse_gemv_kernel<T><<<grid, 256, 0, s>>>(n, C, r, e);
 }
 template void launch_coarse_gemv<double>(int64_t, const double*, const double*, double*,
-                                         hipStream_t);
-template void launch_coarse_gemv<float>(int64_t, const double*, const float*, float*, hipStream_t);
+                                         hipStream_t, int);
+template void launch_coarse_gemv<float>(int64_t, const double*, const float*, float*, hipStream_t,
+                                        int);
 
 template <typename T>
 void launch_fill_zero(T* x, int64_t n, hipStream_t s) {
@@ -1415,33 +1500,49 @@ void launch_scale(const double* in, double alpha, double* out, int64_t n, hipStr
     scale_kernel<<<elementwise_blocks(n), 256, 0, s>>>(in, alpha, out, n);
 }
 
-#define VKMG_KDISPATCH(k, KERNEL, ...)                              \
-    do {                                                            \
-        if ((k) <= 4) KERNEL<4><<<kDotBlocks, 256, 0, s>>>(__VA_ARGS__);        \
-        else if ((k) <= 8) KERNEL<8><<<kDotBlocks, 256, 0, s>>>(__VA_ARGS__);   \
-        else if ((k) <= 16) KERNEL<16><<<kDotBlocks, 256, 0, s>>>(__VA_ARGS__); \
-        else KERNEL<32><<<kDotBlocks, 256, 0, s>>>(__VA_ARGS__);                \
+#define VKMG_KDISPATCH(k, KERNEL, ...)                                     \
+    do {                                                                   \
+        if ((k) <= 4) KERNEL<4><<<kgrid, 256, 0, s>>>(__VA_ARGS__);        \
+        else if ((k) <= 8) KERNEL<8><<<kgrid, 256, 0, s>>>(__VA_ARGS__);   \
+        else if ((k) <= 16) KERNEL<16><<<kgrid, 256, 0, s>>>(__VA_ARGS__); \
+        else KERNEL<32><<<kgrid, 256, 0, s>>>(__VA_ARGS__);                \
     } while (0)
 
 // The Krylov kernels keep up to 32 coefficients in registers; longer
-// bases are processed in chunks of 32 vectors.
+// bases are processed in chunks of 32 vectors (single right-hand side).
 constexpr int kChunk = 32;
 
+int dot_blocks(int nb) {
+    if (nb <= 1) return kDotBlocks;
+    const int b = kDotBlocks / nb;
+    return b < 64 ? 64 : b;
+}
+
+void launch_scale_batched(const double* in, int64_t sin, const double* alpha, int64_t sa,
+                          double* out, int64_t sout, int64_t n, int nb, hipStream_t s) {
+    int bx = elementwise_blocks(n) / nb;
+    const dim3 grid(bx < 1 ? 1 : bx, nb);
+    scale_batched_kernel<<<grid, 256, 0, s>>>(in, sin, alpha, sa, out, sout, n);
+}
+
 void launch_mdot_partial(const double* V, int64_t ldv, int k, const double* w, int64_t n,
-                         double* part, hipStream_t s) {
+                         double* part, hipStream_t s, int nb, int64_t sb) {
+    const dim3 kgrid(dot_blocks(nb), nb);
     for (int c0 = 0; c0 < k; c0 += kChunk) {
         const int kc = k - c0 < kChunk ? k - c0 : kChunk;
         VKMG_KDISPATCH(kc, mdot_partial_kernel, V + c0 * ldv, ldv, kc, w, n,
-                       part + int64_t(c0) * kDotBlocks);
+                       part + int64_t(c0) * kDotBlocks, sb);
     }
 }
 
-void launch_reduce_partials(const double* part, int k, double* out, hipStream_t s) {
-    reduce_partials_kernel<<<k, 256, 0, s>>>(part, kDotBlocks, out);
+void launch_reduce_partials(const double* part, int k, double* out, hipStream_t s, int nb,
+                            int64_t so) {
+    reduce_partials_kernel<<<dim3(k, nb), 256, 0, s>>>(part, dot_blocks(nb), out, so);
 }
 
 void launch_update(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n,
                    hipStream_t s) {
+    const dim3 kgrid(kDotBlocks, 1);
     for (int c0 = 0; c0 < k; c0 += kChunk) {
         const int kc = k - c0 < kChunk ? k - c0 : kChunk;
         VKMG_KDISPATCH(kc, update_kernel, V + c0 * ldv, ldv, kc, h + c0, w, n);
@@ -1450,29 +1551,35 @@ void launch_update(const double* V, int64_t ldv, int k, const double* h, double*
 
 void launch_update_dot(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n,
                        double* part, hipStream_t s) {
+    const dim3 kgrid(kDotBlocks, 1);
     VKMG_KDISPATCH(k, update_dot_kernel, V, ldv, k, h, w, n, part);
 }
 
 void launch_normalize(const double* V, int64_t ldv, int k, const double* h2, const double* nrm2,
                       const double* w, double* out, int64_t n, hipStream_t s) {
+    const dim3 kgrid(kDotBlocks, 1);
     VKMG_KDISPATCH(k, normalize_kernel, V, ldv, k, h2, nrm2, w, out, n);
 }
 
 void launch_dcgs_dots(const double* V, int64_t ldv, int j, const double* u, const double* w,
-                      int64_t n, double* part, hipStream_t s) {
-    VKMG_KDISPATCH(j, dcgs_dots_kernel, V, ldv, j, u, w, n, part);
+                      int64_t n, double* part, hipStream_t s, int nb, int64_t sb) {
+    const dim3 kgrid(dot_blocks(nb), nb);
+    VKMG_KDISPATCH(j, dcgs_dots_kernel, V, ldv, j, u, w, n, part, sb);
 }
 
 void launch_dcgs_update(const double* V, int64_t ldv, int j, const double* c, double* u,
-                        const double* w, double* next, int64_t n, double* cf, hipStream_t s) {
-    VKMG_KDISPATCH(j, dcgs_update_kernel, V, ldv, j, c, u, w, next, n, cf);
+                        const double* w, double* next, int64_t n, double* cf, hipStream_t s,
+                        int nb, int64_t sb, int64_t sc) {
+    const dim3 kgrid(dot_blocks(nb), nb);
+    VKMG_KDISPATCH(j, dcgs_update_kernel, V, ldv, j, c, u, w, next, n, cf, sb, sc);
 }
 
 void launch_axpy_multi(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t n,
-                       hipStream_t s) {
+                       hipStream_t s, int nb, int64_t sb, int64_t sy) {
+    const dim3 kgrid(dot_blocks(nb), nb);
     for (int c0 = 0; c0 < k; c0 += kChunk) {
         const int kc = k - c0 < kChunk ? k - c0 : kChunk;
-        VKMG_KDISPATCH(kc, axpy_multi_kernel, Z + c0 * ldz, ldz, kc, y + c0, x, n);
+        VKMG_KDISPATCH(kc, axpy_multi_kernel, Z + c0 * ldz, ldz, kc, y + c0, x, n, sb, sy);
     }
 }
 

@@ -35,7 +35,7 @@ def test_default_options_and_status_strings():
     lib = vk.load_library()
     o = lib.vkmg_default_options()
     assert (o.nu_pre, o.nu_post, o.omega, o.mg_precision, o.interior_apply,
-            o.use_graphs) == (2, 2, 0.5, 0, 0, 1)
+            o.use_graphs, o.batch) == (2, 2, 0.5, 0, 0, 1, 1)
     for s in range(8):
         assert lib.vkmg_status_string(s)
 
@@ -61,7 +61,8 @@ def test_setup_rejects_bad_arguments_before_any_gpu_work(kwargs, status):
 
 
 @pytest.mark.parametrize("field,value", [("mg_precision", 2), ("interior_apply", 2),
-                                         ("omega", 0.0), ("nu_pre", -1), ("use_graphs", 2)])
+                                         ("omega", 0.0), ("nu_pre", -1), ("use_graphs", 2),
+                                         ("batch", 0), ("batch", 65)])
 def test_setup_rejects_bad_options(field, value):
     lib = vk.load_library()
     from paper_2401_06277_amd._vkmg import Grid

@@ -1,0 +1,250 @@
+"""GPU: batched contexts (several right-hand sides per launch).
+
+Every V-cycle kernel of a batch entry does the arithmetic of the single
+right-hand-side kernel in the same order, so batched residuals, sweeps,
+transfers, coarse solves and V-cycles must equal the single ones bitwise.
+Batched FGMRES reduces its dot products over a different number of blocks,
+so it is compared with the oracle at the tolerances of the single solver
+(iterations +-1 at rtol 1e-8, solution 1e-10 at equal iteration counts).
+Inputs: the trigonometric manufactured solution, Gaussian random body
+forces (seeded) and the lid-driven cavity boundary data.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import fem, fgmres, multigrid
+from stokes_inputs import (gaussian_random_field, lid_boundary_values,
+                           manufactured_boundary_values, manufactured_nodal_force,
+                           uniform_vector, velocity_dirichlet_mask)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2401_06277_amd as vk  # noqa: E402
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+
+
+def _systems(N):
+    """Three systems: manufactured (non-zero Dirichlet data), random body
+    force with homogeneous data, random body force under the lid."""
+    out = []
+    gd = manufactured_boundary_values(N, "trig")
+    A, b, _, xl = fem.stokes_system(N, 1.0, f_nodal=manufactured_nodal_force(N, "trig"), g_nodal=gd)
+    out.append((b, xl))
+    f1 = gaussian_random_field(N, 11)
+    _, b, _, xl = fem.stokes_system(N, 1.0, f_nodal=f1, g_nodal=np.zeros_like(f1))
+    out.append((b, xl))
+    f2 = gaussian_random_field(N, 12)
+    _, b, _, xl = fem.stokes_system(N, 1.0, f_nodal=f2, g_nodal=lid_boundary_values(N))
+    out.append((b, xl))
+    return A, out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("N,levels", [(16, 3), (40, 3)])
+def test_batched_multigrid_steps_equal_single_bitwise(precision, N, levels):
+    note(f"batched steps {precision} N={N}")
+    B = 3
+    sb = vk.VkmgSolver(N, levels, precision=precision, batch=B)
+    s1 = vk.VkmgSolver(N, levels, precision=precision)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    n = s1.layout["n"]
+    mask = velocity_dirichlet_mask(N)
+    rs = []
+    for k in range(B):
+        r = uniform_vector(n, 100 + k)
+        r[mask] = 0.0
+        rs.append(r)
+    rb = dev(np.concatenate(rs))
+    # V-cycle (FP64 interface)
+    zb = host(sb.vcycle(rb)).reshape(B, n)
+    for k in range(B):
+        z1 = host(s1.vcycle(dev(rs[k])))
+        assert np.array_equal(zb[k], z1), k
+    # residual and operator apply
+    xs = [uniform_vector(n, 200 + k) for k in range(B)]
+    xb = dev(np.concatenate(xs))
+    rr = host(sb.residual(rb, xb)).reshape(B, n)
+    ya = host(sb.apply(xb)).reshape(B, n)
+    for k in range(B):
+        assert np.array_equal(rr[k], host(s1.residual(dev(rs[k]), dev(xs[k]))))
+        assert np.array_equal(ya[k], host(s1.apply(dev(xs[k]))))
+    # sweeps, updates and transfers on every relaxed level, coarse solve
+    for level in range(1, levels):
+        nl = s1.level_layout(level)["n"]
+        nc = s1.level_layout(level - 1)["n"]
+        bl = [uniform_vector(nl, 300 + k) for k in range(B)]
+        xl = [uniform_vector(nl, 400 + k) for k in range(B)]
+        xbt = dev(np.concatenate(xl), dt)
+        sb.vanka_sweep(level, xbt, dev(np.concatenate(bl), dt))
+        xu = dev(np.concatenate(xl), dt)
+        sb.vanka_update(level, xu, dev(np.concatenate(bl), dt))
+        rc = sb.restrict(level, dev(np.concatenate(bl), dt))
+        ec = [uniform_vector(nc, 500 + k) for k in range(B)]
+        xp = dev(np.concatenate(xl), dt)
+        sb.prolong_add(level, dev(np.concatenate(ec), dt), xp)
+        got = [host(t).reshape(B, -1) for t in (xbt, xu, rc, xp)]
+        for k in range(B):
+            x1 = dev(xl[k], dt)
+            s1.vanka_sweep(level, x1, dev(bl[k], dt))
+            x2 = dev(xl[k], dt)
+            s1.vanka_update(level, x2, dev(bl[k], dt))
+            r1 = s1.restrict(level, dev(bl[k], dt))
+            x3 = dev(xl[k], dt)
+            s1.prolong_add(level, dev(ec[k], dt), x3)
+            for g, w in zip(got, (x1, x2, r1, x3)):
+                assert np.array_equal(g[k], host(w)), (level, k)
+    n0 = s1.level_layout(0)["n"]
+    cs = [uniform_vector(n0, 600 + k) for k in range(B)]
+    eb = host(sb.coarse_solve(dev(np.concatenate(cs), dt))).reshape(B, n0)
+    for k in range(B):
+        assert np.array_equal(eb[k], host(s1.coarse_solve(dev(cs[k], dt))))
+    sb.close()
+    s1.close()
+
+
+def test_batched_assemble_rhs_equals_single():
+    N, levels, B = 24, 3, 2
+    sb = vk.VkmgSolver(N, levels, batch=B)
+    s1 = vk.VkmgSolver(N, levels)
+    fs = [gaussian_random_field(N, 20 + k).ravel() for k in range(B)]
+    gs = [lid_boundary_values(N).ravel(), manufactured_boundary_values(N, "trig").ravel()]
+    bb = host(sb.assemble_rhs(dev(np.concatenate(fs)), dev(np.concatenate(gs)))).reshape(B, -1)
+    for k in range(B):
+        assert np.array_equal(bb[k], host(s1.assemble_rhs(dev(fs[k]), dev(gs[k]))))
+    sb.close()
+    s1.close()
+
+
+@pytest.mark.parametrize("N,levels", [(16, 3), (32, 4)])
+def test_batched_fgmres_matches_oracle(N, levels):
+    note(f"batched fgmres N={N}")
+    A, systems = _systems(N)
+    B = len(systems)
+    H = multigrid.Hierarchy(N, levels)
+    s = vk.VkmgSolver(N, levels, batch=B)
+    bb = dev(np.concatenate([b for b, _ in systems]))
+    x = dev(np.concatenate([xl for _, xl in systems]))
+    infos = s.fgmres_solve(bb, x, rtol=1e-8, restart=30, max_iters=500)
+    xs = host(x).reshape(B, -1)
+    iters = []
+    for k, (b, xl) in enumerate(systems):
+        ro = fgmres.fgmres(A, b, xl, H.vcycle, rtol=1e-8, restart=30, max_iters=500)
+        assert infos[k]["status_name"] == "VKMG_OK", infos[k]
+        assert abs(infos[k]["iterations"] - ro.iterations) <= 1, (k, infos[k], ro.iterations)
+        assert infos[k]["true_rel_res"] <= 1e-8
+        assert np.linalg.norm(b - A @ xs[k]) <= 1e-8 * np.linalg.norm(b - A @ xl) * 1.01
+        iters.append(ro.iterations)
+    # equal iteration counts: rtol 0 with a cap (every system takes kmin steps)
+    kmin = min(iters)
+    x = dev(np.concatenate([xl for _, xl in systems]))
+    infos = s.fgmres_solve(bb, x, rtol=0.0, restart=30, max_iters=kmin)
+    xs = host(x).reshape(B, -1)
+    for k, (b, xl) in enumerate(systems):
+        assert infos[k]["iterations"] == kmin
+        ok = fgmres.fgmres(A, b, xl, H.vcycle, rtol=0.0, restart=30, fixed_iters=kmin)
+        xa = fem.normalise_pressure(N, xs[k])
+        xo = fem.normalise_pressure(N, ok.x)
+        assert np.linalg.norm(xa - xo) <= 1e-10 * np.linalg.norm(xo), k
+    s.close()
+
+
+def test_batched_fgmres_restarts_and_zero_rhs():
+    """Restarted cycles (restart 4) per system, and a zero right-hand side
+    with a zero initial guess that is done before the first step while the
+    others iterate."""
+    N, levels = 16, 3
+    A, systems = _systems(N)
+    H = multigrid.Hierarchy(N, levels)
+    n = A.shape[0]
+    sysz = [systems[0], (np.zeros(n), np.zeros(n)), systems[2]]
+    B = len(sysz)
+    s = vk.VkmgSolver(N, levels, batch=B)
+    x = dev(np.concatenate([xl for _, xl in sysz]))
+    infos = s.fgmres_solve(dev(np.concatenate([b for b, _ in sysz])), x, rtol=1e-10, restart=4,
+                           max_iters=400)
+    xs = host(x).reshape(B, -1)
+    assert infos[1]["iterations"] == 0 and infos[1]["status_name"] == "VKMG_OK"
+    assert not xs[1].any()
+    for k in (0, 2):
+        b, xl = sysz[k]
+        ro = fgmres.fgmres(A, b, xl, H.vcycle, rtol=1e-10, restart=4, max_iters=400)
+        assert infos[k]["status_name"] == "VKMG_OK"
+        assert abs(infos[k]["iterations"] - ro.iterations) <= 1
+        assert infos[k]["restarts"] >= 1
+        assert infos[k]["true_rel_res"] <= 1e-10
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_fgmres_graph_replays_match_direct_launches(precision):
+    N, levels = 32, 4
+    _, systems = _systems(N)
+    B = len(systems)
+    sg = vk.VkmgSolver(N, levels, precision=precision, graphs=True, batch=B)
+    sd = vk.VkmgSolver(N, levels, precision=precision, graphs=False, batch=B)
+    bb = dev(np.concatenate([b for b, _ in systems]))
+    x0 = np.concatenate([xl for _, xl in systems])
+    for rtol, restart, iters in [(1e-10, 8, 200), (0.0, 12, 20), (1e-10, 8, 200)]:
+        note(f"batched graphs {precision} rtol={rtol} restart={restart}")
+        xg, xd = dev(x0), dev(x0)
+        ig = sg.fgmres_solve(bb, xg, rtol=rtol, restart=restart, max_iters=iters)
+        idr = sd.fgmres_solve(bb, xd, rtol=rtol, restart=restart, max_iters=iters)
+        torch.cuda.synchronize()
+        junk = torch.randn(4096, device="cuda", dtype=torch.float64)
+        assert float((junk * junk).sum()) > 0.0
+        for a, c in zip(ig, idr):
+            assert a["iterations"] == c["iterations"] and a["restarts"] == c["restarts"]
+        assert torch.equal(xg, xd)
+    sg.close()
+    sd.close()
+
+
+def test_batched_fp32_multigrid_reaches_fp64_tolerance():
+    N, levels = 32, 4
+    A, systems = _systems(N)
+    B = len(systems)
+    s = vk.VkmgSolver(N, levels, precision="fp32", batch=B)
+    x = dev(np.concatenate([xl for _, xl in systems]))
+    infos = s.fgmres_solve(dev(np.concatenate([b for b, _ in systems])), x, rtol=1e-8,
+                           restart=30, max_iters=500)
+    xs = host(x).reshape(B, -1)
+    for k, (b, xl) in enumerate(systems):
+        assert infos[k]["status_name"] == "VKMG_OK"
+        assert np.linalg.norm(b - A @ xs[k]) <= 1.01e-8 * np.linalg.norm(b - A @ xl)
+    s.close()
+
+
+def test_batched_fgmres_rejects_long_restarts():
+    s = vk.VkmgSolver(16, 3, batch=2)
+    n = s.layout["n"]
+    b = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    with pytest.raises(vk.VkmgError) as e:
+        s.fgmres_solve(b, x, rtol=1e-8, restart=40, max_iters=10)
+    assert e.value.status_name == "VKMG_ERR_UNSUPPORTED"
+    s.close()

@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-c2", action="store_true",
                     help="skip the 256x256 sweep and solve measurements")
+    ap.add_argument("--skip-c4", action="store_true",
+                    help="skip the 512x512 batched (32 right-hand sides) solves")
+    ap.add_argument("--c4-batch", type=int, default=32)
     ap.add_argument("--interior-apply", choices=["vector", "matrix"], default="vector",
                     help="interior Vanka apply: vector ALUs (default) or matrix cores")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -215,6 +218,87 @@ def bench_c2(a, vk, torch, np):
         sol[prec] = x.cpu().numpy()
         s.close()
     res["_solutions"] = sol
+    return res
+
+
+def bench_c4(a, vk, torch, np):
+    """512 x 512, 7 levels, B = 32 right-hand sides: Gaussian random body
+    forces (unit variance, l = 0.1, seeds 1000 + k) under the lid-driven top
+    boundary, solved to rtol 1e-8 as one batched FGMRES (batched context)
+    and as B sequential single-right-hand-side solves, FP32 and FP64
+    multigrid.  Times exclude setup and the right-hand-side assembly."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from stokes_inputs import gaussian_random_field, lid_boundary_values, velocity_dirichlet_mask
+
+    N4, L4, B = 512, 7, a.c4_batch
+    with ThreadPoolExecutor(8) as ex:
+        fs = list(ex.map(lambda k: gaussian_random_field(N4, 1000 + k).ravel(), range(B)))
+    g = lid_boundary_values(N4).ravel()
+    mask = torch.from_numpy(velocity_dirichlet_mask(N4)).cuda()
+    ups = sum(4 * ((N4 >> (L4 - 1 - l)) + 1) ** 2 for l in range(1, L4))
+    res = {"config": (f"512x512 elements, 7 levels, {B} right-hand sides (GRF body force l=0.1 "
+                      "seeds 1000+k, lid u=(1,0) on the top edge), FGMRES(30) rtol 1e-8, "
+                      "x0 = Dirichlet lifting"),
+           "batch": B, "patch_updates_per_vcycle_per_rhs": ups}
+    fd = torch.from_numpy(np.concatenate(fs)).cuda()
+    gd = torch.from_numpy(np.tile(g, B)).cuda()
+    for prec in ("fp32", "fp64"):
+        log(f"[bench] 512x512 x{B} batched {prec}")
+        s = vk.VkmgSolver(N4, L4, precision=prec, interior_apply=a.interior_apply, batch=B)
+        n = s.layout["n"]
+        b = s.assemble_rhs(fd, gd)
+        x0 = torch.where(mask.repeat(B), b, torch.zeros_like(b))
+        x = x0.clone()
+        s.fgmres_solve(b, x, rtol=1e-8, restart=30, max_iters=500)  # warm (captures graphs)
+        x = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = s.fgmres_solve(b, x, rtol=1e-8, restart=30, max_iters=500)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        its = [i["iterations"] for i in infos]
+        xb = x.view(B, n)
+        res[f"batched_{prec}"] = {
+            "time_s": tb, "time_per_rhs_s": tb / B,
+            "iterations_max": max(its), "iterations_mean": sum(its) / B,
+            "max_true_rel_res": max(i["true_rel_res"] for i in infos),
+            "all_converged": all(i["status_name"] == "VKMG_OK" for i in infos),
+            "patch_updates_per_s": ups * sum(its) / tb,
+        }
+        s.close()
+        log(f"[bench] 512x512 x{B} sequential {prec}")
+        s1 = vk.VkmgSolver(N4, L4, precision=prec, interior_apply=a.interior_apply)
+        bs = [s1.assemble_rhs(fd[k * len(g):(k + 1) * len(g)], gd[:len(g)]) for k in range(B)]
+        x1 = torch.where(mask, bs[0], torch.zeros_like(bs[0]))
+        s1.fgmres_solve(bs[0], x1, rtol=1e-8, restart=30, max_iters=500)  # warm
+        xs, its1 = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(B):
+            x1 = torch.where(mask, bs[k], torch.zeros_like(bs[k]))
+            info = s1.fgmres_solve(bs[k], x1, rtol=1e-8, restart=30, max_iters=500)
+            its1.append(info["iterations"])
+            xs.append(x1)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        off_p = 2 * (2 * N4 + 1) ** 2
+
+        def centred(v):
+            v = v.clone()
+            v[off_p:] -= v[off_p:].mean()
+            return v
+
+        dmax = max(float(torch.linalg.norm(centred(xb[k]) - centred(xs[k]))
+                         / torch.linalg.norm(centred(xs[k]))) for k in range(B))
+        res[f"sequential_{prec}"] = {"time_s": ts, "time_per_rhs_s": ts / B,
+                                     "iterations_max": max(its1),
+                                     "patch_updates_per_s": ups * sum(its1) / ts}
+        res[f"batched_speedup_{prec}"] = ts / tb
+        res[f"batched_vs_sequential_max_rel_diff_{prec}"] = dmax
+        s1.close()
+        del xs, bs, b, x, x0, xb
+        torch.cuda.empty_cache()
     return res
 
 
@@ -382,6 +466,9 @@ def main():
         log("[bench] 256x256 sweeps and solves")
         c2 = bench_c2(a, vk, torch, np)
         out["c2_256"] = {k: v for k, v in c2.items() if not k.startswith("_")}
+
+    if not a.skip_c4:
+        out["c4_512_batched"] = bench_c4(a, vk, torch, np)
 
     if not a.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -7,7 +7,8 @@ from a zero initial guess.
 
 Readings: the coarse operators are rediscretised on each level (equal to
 the Galerkin product P^T A P for constant viscosity, which a test checks);
-the relaxation is the additive Vanka sweep, nu_pre sweeps before and
+the relaxation is the additive Vanka sweep (or, with relaxation="bs", the
+inexact Braess-Sarazin step of braess_sarazin.py), nu_pre sweeps before and
 nu_post after the coarse correction; the level-0 solve is exact, with the
 constant-pressure null space handled by bordering the matrix with
 c = (0, 1_p): [[A_0, c], [c^T, 0]] [e; lambda] = [r; 0], solved by dense
@@ -22,22 +23,30 @@ import scipy.linalg as sla
 from stokes_inputs import grid_sizes
 from .fem import stokes_system
 from .transfer import prolongation
+from .braess_sarazin import BraessSarazinSmoother
 from .vanka import VankaSmoother
 
 
 class Level:
-    def __init__(self, N: int, nu, omega: float, shared, relax: bool):
+    def __init__(self, N: int, nu, omega: float, shared, relax: bool, relaxation: str = "vanka",
+                 bs=None):
         self.N = N
         self.A, _, self.dmask, _ = stokes_system(N, nu)
         self.n = self.A.shape[0]
-        self.smoother = VankaSmoother(self.A, N, self.dmask, omega, shared) if relax else None
+        if not relax:
+            self.smoother = None
+        elif relaxation == "bs":
+            self.smoother = BraessSarazinSmoother(self.A, N, **(bs or {}))
+        else:
+            self.smoother = VankaSmoother(self.A, N, self.dmask, omega, shared)
 
 
 class Hierarchy:
     """Levels l = 0 (coarsest) .. L-1 (finest) with N_l = N / 2^(L-1-l)."""
 
     def __init__(self, N: int, levels: int, nu: float = 1.0, omega: float = 0.5,
-                 nu_pre: int = 2, nu_post: int = 2, shared=None):
+                 nu_pre: int = 2, nu_post: int = 2, shared=None, relaxation: str = "vanka",
+                 bs=None):
         if levels < 2:
             raise ValueError("need at least two levels")
         if N % (1 << (levels - 1)):
@@ -47,7 +56,8 @@ class Hierarchy:
         self.levels = []
         for l in range(levels):
             Nl = N >> (levels - 1 - l)
-            self.levels.append(Level(Nl, nu, omega, shared, relax=(l > 0)))
+            self.levels.append(Level(Nl, nu, omega, shared, relax=(l > 0),
+                                     relaxation=relaxation, bs=bs))
         self.P = [None] + [prolongation(self.levels[l - 1].N) for l in range(1, levels)]
         # bordered coarse matrix
         A0 = self.levels[0].A.toarray()

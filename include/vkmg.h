@@ -29,7 +29,7 @@
  *
  * Streams: every entry point that takes `stream` (a hipStream_t, NULL =
  * the legacy default stream) enqueues all its GPU work on it.
- * vkmg_residual, vkmg_apply, vkmg_vanka_sweep, vkmg_vanka_update, vkmg_restrict,
+ * vkmg_residual, vkmg_apply, vkmg_vanka_sweep, vkmg_vanka_update, vkmg_relax, vkmg_restrict,
  * vkmg_prolong_add, vkmg_coarse_solve, vkmg_vcycle and vkmg_assemble_rhs are
  * asynchronous; vkmg_fgmres_solve synchronises (one small device-to-host
  * copy per Arnoldi step) and its vkmg_info is valid on return.
@@ -65,6 +65,14 @@ typedef enum { VKMG_FP64 = 0, VKMG_FP32 = 1 } vkmg_precision;
  * order. */
 typedef enum { VKMG_APPLY_VECTOR = 0, VKMG_APPLY_MATRIX = 1 } vkmg_interior_apply;
 
+/* Relaxation inside the V-cycle: additive Vanka (paper, "Vanka relaxation
+ * scheme", Algorithm 3; default) or inexact Braess-Sarazin (paper,
+ * "Braess-Sarazin relaxation scheme", Algorithm 2): with D = diag(L) and
+ * S = -(1/t) B D^{-1} B^T, weighted-Jacobi sweeps on
+ * S dp = r_p - (1/t) B D^{-1} r_u from dp = 0, du = (1/t) D^{-1}(r_u - B^T dp),
+ * x += omega_bs (du, dp). */
+typedef enum { VKMG_RELAX_VANKA = 0, VKMG_RELAX_BRAESS_SARAZIN = 1 } vkmg_relaxation;
+
 typedef struct {
     int32_t nx, ny; /* elements per side on [0,1]^2; nx == ny required */
 } vkmg_grid;
@@ -82,6 +90,11 @@ typedef struct {
                                     a replayed graph cannot be read back). */
     int32_t batch;               /* right-hand sides handled together (1..64, default 1);
                                     see "Batches" below */
+    vkmg_relaxation relaxation;  /* default VKMG_RELAX_VANKA */
+    double bs_t;                 /* Braess-Sarazin: scaling t of D (> 0, default 1) */
+    double bs_omega;             /* Braess-Sarazin: damping omega_bs (0, 2], default 1 */
+    double bs_jacobi_weight;     /* Braess-Sarazin: Jacobi weight on S (0, 2], default 1 */
+    int32_t bs_jacobi_sweeps;    /* Braess-Sarazin: Jacobi sweeps on S (1..16, default 2) */
 } vkmg_options;
 
 typedef struct {
@@ -101,7 +114,8 @@ typedef struct {
 
 /* Kernel classes that vkmg_kernel_timing reports. */
 typedef enum {
-    VKMG_KERNEL_VANKA = 0,       /* Vanka sweep (gather, patch-inverse apply, scatter) */
+    VKMG_KERNEL_VANKA = 0,       /* relaxation update: Vanka (gather, patch-inverse apply,
+                                    scatter) or Braess-Sarazin (Schur Jacobi, update) */
     VKMG_KERNEL_RESIDUAL = 1,    /* stencil residual / operator apply */
     VKMG_KERNEL_TRANSFER = 2,    /* restriction and prolongation */
     VKMG_KERNEL_COARSE = 3,      /* coarsest-level dense solve */
@@ -120,8 +134,8 @@ typedef enum {
  * those of B separate single-right-hand-side calls up to rounding order.
  */
 
-/* {2, 2, 0.5, VKMG_FP64, VKMG_APPLY_VECTOR, 1, 1}: V(2,2) cycles of additive
- * Vanka damped by 0.5, one right-hand side. */
+/* {2, 2, 0.5, VKMG_FP64, VKMG_APPLY_VECTOR, 1, 1, VKMG_RELAX_VANKA, 1, 1, 1, 2}:
+ * V(2,2) cycles of additive Vanka damped by 0.5, one right-hand side. */
 vkmg_options vkmg_default_options(void);
 
 /*
@@ -192,6 +206,15 @@ vkmg_status vkmg_vanka_sweep(vkmg_ctx* ctx, int32_t level, void* x, const void* 
  * weights are zero, so they are never read into a correction).
  */
 vkmg_status vkmg_vanka_update(vkmg_ctx* ctx, int32_t level, void* x, const void* r, void* stream);
+
+/*
+ * One sweep of the context's relaxation (opts.relaxation) on `level`
+ * (1 <= level <= levels-1), in the multigrid precision: r = b - A_l x, then
+ * the Vanka update (as vkmg_vanka_sweep) or the Braess-Sarazin update
+ * (paper, Algorithm 2 with the equations bseq1/bseq2; see
+ * vkmg_relaxation).  x is updated in place; b must not alias x.
+ */
+vkmg_status vkmg_relax(vkmg_ctx* ctx, int32_t level, void* x, const void* b, void* stream);
 
 /*
  * Grid transfers of Algorithm 1 in the multigrid precision:

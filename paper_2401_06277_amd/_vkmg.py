@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvkmg.so"
 
 FP64, FP32 = 0, 1
 APPLY = {"vector": 0, "matrix": 1}
+RELAX = {"vanka": 0, "braess_sarazin": 1}
 KERNEL_VANKA, KERNEL_RESIDUAL, KERNEL_TRANSFER, KERNEL_COARSE, KERNEL_KRYLOV = range(5)
 
 STATUS = {
@@ -34,7 +35,7 @@ STATUS = {
 EXPORTED = [
     "vkmg_default_options", "vkmg_setup", "vkmg_destroy", "vkmg_layout_of", "vkmg_level_layout",
     "vkmg_num_levels", "vkmg_residual", "vkmg_apply", "vkmg_assemble_rhs", "vkmg_vanka_sweep",
-    "vkmg_vanka_update",
+    "vkmg_vanka_update", "vkmg_relax",
     "vkmg_restrict", "vkmg_prolong_add", "vkmg_coarse_solve", "vkmg_vcycle",
     "vkmg_fgmres_solve", "vkmg_set_timing", "vkmg_kernel_timing", "vkmg_host_patch_matrix",
     "vkmg_status_string", "vkmg_last_error",
@@ -55,7 +56,9 @@ class Grid(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("nu_pre", c_int32), ("nu_post", c_int32), ("omega", c_double),
                 ("mg_precision", c_int32), ("interior_apply", c_int32), ("use_graphs", c_int32),
-                ("batch", c_int32)]
+                ("batch", c_int32), ("relaxation", c_int32), ("bs_t", c_double),
+                ("bs_omega", c_double), ("bs_jacobi_weight", c_double),
+                ("bs_jacobi_sweeps", c_int32)]
 
 
 class Layout(ctypes.Structure):
@@ -102,6 +105,7 @@ def load_library(path: str = LIB_PATH):
         "vkmg_assemble_rhs": (c_int32, [P, P, P, P, P]),
         "vkmg_vanka_sweep": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_vanka_update": (c_int32, [P, c_int32, P, P, P]),
+        "vkmg_relax": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_restrict": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_prolong_add": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_coarse_solve": (c_int32, [P, P, P, P]),
@@ -154,7 +158,9 @@ class VkmgSolver:
 
     def __init__(self, N: int, levels: int, nu: float = 1.0, nu_pre: int = 2, nu_post: int = 2,
                  omega: float = 0.5, precision: str = "fp64", interior_apply: str = "vector",
-                 graphs: bool = True, batch: int = 1):
+                 graphs: bool = True, batch: int = 1, relaxation: str = "vanka",
+                 bs_t: float = 1.0, bs_omega: float = 1.0, bs_jacobi_weight: float = 1.0,
+                 bs_jacobi_sweeps: int = 2):
         import torch
         lib = load_library()
         self._torch = torch
@@ -162,8 +168,11 @@ class VkmgSolver:
         self.interior_apply = interior_apply
         if interior_apply not in APPLY:
             raise ValueError(f"interior_apply must be one of {sorted(APPLY)}")
+        if relaxation not in RELAX:
+            raise ValueError(f"relaxation must be one of {sorted(RELAX)}")
         opts = Options(nu_pre, nu_post, omega, FP32 if precision == "fp32" else FP64,
-                       APPLY[interior_apply], 1 if graphs else 0, batch)
+                       APPLY[interior_apply], 1 if graphs else 0, batch, RELAX[relaxation],
+                       bs_t, bs_omega, bs_jacobi_weight, bs_jacobi_sweeps)
         ctx = c_void_p()
         st = lib.vkmg_setup(byref(Grid(N, N)), levels, nu, byref(opts), self._stream(),
                             byref(ctx))
@@ -271,6 +280,14 @@ class VkmgSolver:
         st = _lib.vkmg_vanka_update(self._ctx, level, self._ptr(x, self.mg_dtype, n, "x"),
                                     self._ptr(r, self.mg_dtype, n, "r"), self._stream())
         _check(st, "vkmg_vanka_update")
+        return x
+
+    def relax(self, level: int, x, b):
+        """One sweep of the configured relaxation (Vanka or Braess-Sarazin)."""
+        n = self.level_layout(level)["n"] * self.batch
+        st = _lib.vkmg_relax(self._ctx, level, self._ptr(x, self.mg_dtype, n, "x"),
+                             self._ptr(b, self.mg_dtype, n, "b"), self._stream())
+        _check(st, "vkmg_relax")
         return x
 
     def restrict(self, level: int, r_fine, b_coarse=None):

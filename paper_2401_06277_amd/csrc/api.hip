@@ -42,6 +42,7 @@ struct LevelBuf {
     void* r = nullptr;
     void* W = nullptr;     // patch-operator table, MG precision (relaxed levels)
     void* dbuf = nullptr;  // boundary-patch corrections (relaxed levels)
+    void* bs = nullptr;    // Braess-Sarazin scratch: Schur rhs, dp, B^T dp (relaxed levels)
 };
 
 }  // namespace
@@ -161,7 +162,8 @@ vkmg_layout layout_of_geom(const Geom& g) {
 // With x_zero the iterate is known to be zero, so r = b and the update
 // writes every DoF of x without reading it.
 template <typename T>
-void sweep_t(vkmg_ctx* c, int l, const T* b, T* x, bool x_zero, hipStream_t s) {
+void sweep_t(vkmg_ctx* c, int l, const T* b, T* x, bool x_zero, hipStream_t s,
+             bool vanka = false) {
     LevelBuf& L = c->lev[l];
     const T* r = b;
     if (!x_zero) {
@@ -170,6 +172,14 @@ void sweep_t(vkmg_ctx* c, int l, const T* b, T* x, bool x_zero, hipStream_t s) {
         r = static_cast<const T*>(L.r);
     }
     Timed t(c, VKMG_KERNEL_VANKA, s, l);
+    if (!vanka && c->opt.relaxation == VKMG_RELAX_BRAESS_SARAZIN) {
+        const int64_t np = L.g.nq1 * c->nb();
+        T* prhs = static_cast<T*>(L.bs);
+        launch_bs_relax<T>(L.g, r, x_zero ? nullptr : x, x, prhs, prhs + np, prhs + 2 * np,
+                           c->opt.bs_t, c->opt.bs_omega, c->opt.bs_jacobi_weight,
+                           c->opt.bs_jacobi_sweeps, s, c->nb());
+        return;
+    }
     launch_vanka_update<T>(L.g, r, x_zero ? nullptr : x, x, static_cast<const T*>(L.W),
                            static_cast<const T*>(c->mtab), static_cast<T*>(L.dbuf), c->opt.omega,
                            c->opt.interior_apply == VKMG_APPLY_MATRIX, s, c->nb());
@@ -584,6 +594,11 @@ vkmg_options vkmg_default_options(void) {
     o.interior_apply = VKMG_APPLY_VECTOR;
     o.use_graphs = 1;
     o.batch = 1;
+    o.relaxation = VKMG_RELAX_VANKA;
+    o.bs_t = 1.0;
+    o.bs_omega = 1.0;
+    o.bs_jacobi_weight = 1.0;
+    o.bs_jacobi_sweeps = 2;
     return o;
 }
 
@@ -652,6 +667,14 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         return fail(VKMG_ERR_INVALID_ARG, "setup: use_graphs must be 0 or 1");
     if (o.batch < 1 || o.batch > 64)
         return fail(VKMG_ERR_INVALID_ARG, "setup: batch must be in [1, 64]");
+    if (o.relaxation != VKMG_RELAX_VANKA && o.relaxation != VKMG_RELAX_BRAESS_SARAZIN)
+        return fail(VKMG_ERR_INVALID_ARG, "setup: bad relaxation");
+    if (!(o.bs_t > 0.0) || !std::isfinite(o.bs_t) || !(o.bs_omega > 0.0 && o.bs_omega <= 2.0) ||
+        !(o.bs_jacobi_weight > 0.0 && o.bs_jacobi_weight <= 2.0) || o.bs_jacobi_sweeps < 1 ||
+        o.bs_jacobi_sweeps > 16)
+        return fail(VKMG_ERR_INVALID_ARG,
+                    "setup: Braess-Sarazin parameters out of range (t > 0, omega and Jacobi "
+                    "weight in (0, 2], 1..16 Jacobi sweeps)");
 
     // host work first (no GPU needed to detect singular patches)
     double B1[651];
@@ -709,6 +732,8 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         if (st == VKMG_OK) st = alloc(c.get(), &L.r, es * L.g.n * nbt);
         if (st == VKMG_OK && l >= 1)
             st = alloc(c.get(), &L.dbuf, es * size_t(vanka_boundary_scratch(L.g.N)) * nbt);
+        if (st == VKMG_OK && l >= 1 && o.relaxation == VKMG_RELAX_BRAESS_SARAZIN)
+            st = alloc(c.get(), &L.bs, es * size_t(2 * L.g.nq1 + 2 * L.g.nq2) * nbt);
         if (st == VKMG_OK && l >= 1) {
             const size_t nw = size_t(kLevelTable);
             st = alloc(c.get(), &L.W, es * nw);
@@ -826,6 +851,22 @@ vkmg_status vkmg_vanka_sweep(vkmg_ctx* ctx, int32_t level, void* x, const void* 
     if (!x || !b || !check_level(ctx, level, true))
         return fail(VKMG_ERR_INVALID_ARG, "vanka_sweep: NULL argument or level not in [1, levels)");
     if (x == b) return fail(VKMG_ERR_INVALID_ARG, "vanka_sweep: b must not alias x");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    if (ctx->opt.mg_precision == VKMG_FP64)
+        sweep_t<double>(ctx, level, static_cast<const double*>(b), static_cast<double*>(x), false, s,
+                        true);
+    else
+        sweep_t<float>(ctx, level, static_cast<const float*>(b), static_cast<float*>(x), false, s,
+                       true);
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_relax(vkmg_ctx* ctx, int32_t level, void* x, const void* b, void* stream) {
+    if (!x || !b || !check_level(ctx, level, true))
+        return fail(VKMG_ERR_INVALID_ARG, "relax: NULL argument or level not in [1, levels)");
+    if (x == b) return fail(VKMG_ERR_INVALID_ARG, "relax: b must not alias x");
     VKMG_HIP(hipSetDevice(ctx->device));
     hipStream_t s = as_stream(stream);
     if (ctx->opt.mg_precision == VKMG_FP64)

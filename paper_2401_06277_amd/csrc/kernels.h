@@ -41,6 +41,17 @@ void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const
                          int nb = 1);
 int64_t vanka_boundary_scratch(int N);
 
+// One Braess-Sarazin relaxation (inexact form) given the residual r of x_in
+// (x_in == nullptr: x_in = 0, r = b): rhs = r_p - (1/t) B D^{-1} r_u into
+// prhs, `jacobi_sweeps` weighted-Jacobi sweeps on S dp = rhs from dp = 0
+// (S = -(1/t) B D^{-1} B^T, scratch vtmp of 2 (2N+1)^2 values), then
+// x_out = x_in + omega [ (1/t) D^{-1} (r_u - B^T dp); dp ].  prhs and dp hold
+// (N+1)^2 values per right-hand side.
+template <typename T>
+void launch_bs_relax(const Geom& g, const T* r, const T* xin, T* xout, T* prhs, T* dp, T* vtmp,
+                     double t, double omega, double jacobi_weight, int jacobi_sweeps,
+                     hipStream_t s, int nb = 1);
+
 // Transfers between the fine level gf and the coarse level gc (gf.N == 2 gc.N).
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, hipStream_t s,

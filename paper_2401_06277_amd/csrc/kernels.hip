@@ -293,6 +293,217 @@ __global__ __launch_bounds__(256) void rhs_kernel(Geom g, const double* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Braess-Sarazin relaxation (inexact form): with D = diag(L) and
+// S = -(1/t) B D^{-1} B^T,
+//   rhs = r_p - (1/t) B D^{-1} r_u,  dp = Jacobi sweeps on S dp = rhs,
+//   x_u += w (1/t) D^{-1} (r_u - B^T dp),  x_p += w dp.
+// Tiles of BT x BT cells, one thread per cell (its Q1 node and its Q2 nodes
+// (2ex+a, 2ey+b)); D^{-1} and diag(S) are formed in the kernels from the
+// stencil constants (free velocity DoFs: D = (nu/90) L-stencil centre;
+// Dirichlet DoFs: identity rows, no B coupling).
+// ---------------------------------------------------------------------------
+
+constexpr int BT = 16;            // cells per tile side
+constexpr int BQ2 = 2 * BT + 4;   // staged Q2 nodes per side (offset -2)
+constexpr int BQ1 = BT + 2;       // staged Q1 nodes per side (offset -1)
+constexpr int BNT = BT * BT;
+
+template <typename T>
+__device__ __forceinline__ T bs_dinv(const Geom& g, int px, int py) {
+    return T(1.0 / (g.nu / 90.0 * double(st_L(py, px, 0, 0))));
+}
+
+// diag(S) at Q1 node (I, J): -(1/t) sum over the free Q2 nodes j of the
+// patch of B_Ij^2 / D_j (both components).
+template <typename T>
+__device__ __forceinline__ T bs_schur_diag(const Geom& g, int I, int J, T inv_t) {
+    const double cb = -g.h / 36.0, cl = g.nu / 90.0;
+    double s = 0.0;
+#pragma unroll
+    for (int oy = -2; oy <= 2; ++oy)
+#pragma unroll
+        for (int ox = -2; ox <= 2; ++ox) {
+            const int cx = st_Mq(oy) * st_G(ox), cy = st_G(oy) * st_Mq(ox);
+            if (cx == 0 && cy == 0) continue;
+            const int qi = 2 * I + ox, qj = 2 * J + oy;
+            const bool free = qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
+            const double d = cl * double(st_L(oy & 1, ox & 1, 0, 0));
+            s += free ? double(cx * cx + cy * cy) / d : 0.0;
+        }
+    return T(-double(inv_t) * cb * cb * s);
+}
+
+// MODE 0: prhs = vin_p - (1/t) B D^{-1} vin_u (vin = the residual r),
+// dp = wj prhs / diag(S).
+// MODE 1: dp += wj (prhs + (1/t) B D^{-1} vin_u) / diag(S) (vin_u = B^T dp of
+// the previous Jacobi iterate, so that the bracket is prhs - S dp).
+// Batched over blockIdx.y: vin advances by g.n (MODE 0) or 2 nq2 (MODE 1),
+// prhs and dp by g.nq1.
+template <typename T, int MODE>
+__global__ __launch_bounds__(BNT) void bs_div_kernel(Geom g, const T* vin, T* prhs, T* dp,
+                                                     T inv_t, T wj) {
+    __shared__ T s_u[2][BQ2 * BQ2];
+    const int tiles = (g.N + 1 + BT - 1) / BT;
+    const int ntile = tiles * tiles;
+    const int per_xcd = (ntile + 7) / 8;
+    const int tlin = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (tlin >= ntile) return;
+    vin += int64_t(blockIdx.y) * (MODE == 0 ? g.n : 2 * g.nq2);
+    prhs += int64_t(blockIdx.y) * g.nq1;
+    dp += int64_t(blockIdx.y) * g.nq1;
+    const int E0x = (tlin % tiles) * BT, E0y = (tlin / tiles) * BT;
+    const int ox = 2 * E0x - 2, oy = 2 * E0y - 2;
+    constexpr int kIt = (BQ2 * BQ2 + BNT - 1) / BNT;
+    T v0[kIt], v1[kIt];
+    bool f2[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int t = threadIdx.x + it * BNT;
+        const int qi = ox + t % BQ2, qj = oy + t / BQ2;
+        f2[it] = t < BQ2 * BQ2 && qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
+        const int64_t q = f2[it] ? int64_t(qj) * g.s2 + qi : 0;
+        v0[it] = vin[q];
+        v1[it] = vin[g.nq2 + q];
+    }
+    const int tx = threadIdx.x % BT, ty = threadIdx.x / BT;
+    const int I = E0x + tx, J = E0y + ty;
+    const bool node = I <= g.N && J <= g.N;
+    const int64_t qp = node ? int64_t(J) * g.s1 + I : 0;
+    // MODE 0 reads the pressure residual from vin, MODE 1 the stored rhs
+    const T pin = MODE == 0 ? vin[2 * g.nq2 + qp] : prhs[qp];
+    const T dpo = MODE == 1 ? dp[qp] : T(0);
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int t = threadIdx.x + it * BNT;
+        if (t < BQ2 * BQ2) {
+            const int qi = ox + t % BQ2, qj = oy + t / BQ2;
+            const T di = bs_dinv<T>(g, qi & 1, qj & 1);
+            s_u[0][t] = f2[it] ? di * v0[it] : T(0);
+            s_u[1][t] = f2[it] ? di * v1[it] : T(0);
+        }
+    }
+    __syncthreads();
+    if (!node) return;
+    const int c = (2 * ty + 2) * BQ2 + 2 * tx + 2;
+    T sb = 0;
+#pragma unroll
+    for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+        for (int dx = -2; dx <= 2; ++dx) {
+            const int cx = st_Mq(dy) * st_G(dx), cy = st_G(dy) * st_Mq(dx);
+            if (cx == 0 && cy == 0) continue;
+            sb += T(cx) * s_u[0][c + dy * BQ2 + dx] + T(cy) * s_u[1][c + dy * BQ2 + dx];
+        }
+    const T bdu = T(-g.h / 36.0) * sb;  // (B D^{-1} vin_u) at (I, J)
+    const T ds = bs_schur_diag<T>(g, I, J, inv_t);
+    if (MODE == 0) {
+        const T rhs = pin - inv_t * bdu;
+        prhs[qp] = rhs;
+        dp[qp] = wj * rhs / ds;
+    } else {
+        dp[qp] = dpo + wj * (pin + inv_t * bdu) / ds;
+    }
+}
+
+// MODE 0: out_u = B^T dp (Dirichlet rows 0); out has 2 (2N+1)^2 values.
+// MODE 1: x_u = x_u + w (1/t) D^{-1} (r_u - B^T dp), x_p = x_p + w dp, with
+// x_in == nullptr meaning x_in = 0 (x_out may alias x_in).
+// Batched over blockIdx.y: dp advances by g.nq1, r, x by g.n, out by 2 nq2.
+template <typename T, int MODE>
+__global__ __launch_bounds__(BNT) void bs_grad_kernel(Geom g, const T* dp, const T* r,
+                                                      const T* xin, T* xout, T w_t, T w) {
+    __shared__ T s_p[BQ1 * BQ1];
+    const int tiles = (g.N + 1 + BT - 1) / BT;
+    const int ntile = tiles * tiles;
+    const int per_xcd = (ntile + 7) / 8;
+    const int tlin = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (tlin >= ntile) return;
+    dp += int64_t(blockIdx.y) * g.nq1;
+    if (MODE == 1) {
+        r += int64_t(blockIdx.y) * g.n;
+        if (xin) xin += int64_t(blockIdx.y) * g.n;
+        xout += int64_t(blockIdx.y) * g.n;
+    } else {
+        xout += int64_t(blockIdx.y) * 2 * g.nq2;
+    }
+    const int E0x = (tlin % tiles) * BT, E0y = (tlin / tiles) * BT;
+    constexpr int kIt = (BQ1 * BQ1 + BNT - 1) / BNT;
+    T vp[kIt];
+    bool f1[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int t = threadIdx.x + it * BNT;
+        const int I = E0x - 1 + t % BQ1, J = E0y - 1 + t / BQ1;
+        f1[it] = t < BQ1 * BQ1 && I >= 0 && J >= 0 && I <= g.N && J <= g.N;
+        vp[it] = dp[f1[it] ? int64_t(J) * g.s1 + I : 0];
+    }
+    const int tx = threadIdx.x % BT, ty = threadIdx.x / BT;
+    const int ex = E0x + tx, ey = E0y + ty;
+    const bool cell = ex <= g.N && ey <= g.N;
+    // this cell's Q2 nodes and the values the update reads
+    int64_t qn[2][2];
+    T ru[2][2][2], xu[2][2][2];
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) {
+            const int i = 2 * ex + aa, j = 2 * ey + bb;
+            qn[bb][aa] = (cell && i < g.s2 && j < g.s2) ? int64_t(j) * g.s2 + i : -1;
+            const int64_t q = qn[bb][aa] >= 0 ? qn[bb][aa] : 0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                ru[bb][aa][c] = MODE == 1 ? r[c * g.nq2 + q] : T(0);
+                xu[bb][aa][c] = (MODE == 1 && xin) ? xin[c * g.nq2 + q] : T(0);
+            }
+        }
+    const int64_t qp = cell ? int64_t(ey) * g.s1 + ex : 0;
+    const T xp = (MODE == 1 && xin) ? xin[2 * g.nq2 + qp] : T(0);
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int t = threadIdx.x + it * BNT;
+        if (t < BQ1 * BQ1) s_p[t] = f1[it] ? vp[it] : T(0);
+    }
+    __syncthreads();
+    if (!cell) return;
+    const int c1 = (ty + 1) * BQ1 + tx + 1;
+    const T cb = T(-g.h / 36.0);
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) {
+            const int64_t q = qn[bb][aa];
+            if (q < 0) continue;
+            const int i = 2 * ex + aa, j = 2 * ey + bb;
+            const bool free = i > 0 && j > 0 && i < g.s2 - 1 && j < g.s2 - 1;
+            T bx = 0, by = 0;
+#pragma unroll
+            for (int oy = -2; oy <= 2; ++oy) {
+                if (((oy - bb) & 1) != 0) continue;
+#pragma unroll
+                for (int oxx = -2; oxx <= 2; ++oxx) {
+                    if (((oxx - aa) & 1) != 0) continue;
+                    const int cx = st_Mq(oy) * st_G(oxx);
+                    const int cy = st_G(oy) * st_Mq(oxx);
+                    if (cx == 0 && cy == 0) continue;
+                    const T pv = s_p[c1 + ((bb - oy) / 2) * BQ1 + (aa - oxx) / 2];
+                    bx += T(cx) * pv;
+                    by += T(cy) * pv;
+                }
+            }
+            const T gx = free ? cb * bx : T(0), gy = free ? cb * by : T(0);
+            if (MODE == 0) {
+                xout[q] = gx;
+                xout[g.nq2 + q] = gy;
+            } else {
+                const T di = free ? bs_dinv<T>(g, aa, bb) : T(1);
+                xout[q] = xu[bb][aa][0] + w_t * di * (ru[bb][aa][0] - gx);
+                xout[g.nq2 + q] = xu[bb][aa][1] + w_t * di * (ru[bb][aa][1] - gy);
+            }
+        }
+    if (MODE == 1) xout[2 * g.nq2 + qp] = xp + w * s_p[c1];
+}
+
+// ---------------------------------------------------------------------------
 // Vanka update (owner computes).  A workgroup owns the elements
 // [E0, E0+VT) in each direction: the Q2 nodes [2E0, 2E0+2VT) and the Q1
 // nodes [E0, E0+VT).  It solves every patch that touches an owned DoF --
@@ -1418,6 +1629,27 @@ void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hip
     const dim3 grid((g.N + 1 + 15) / 16, (g.N + 1 + 15) / 16, nb);
     rhs_kernel<<<grid, 256, 0, s>>>(g, f, gd, b);
 }
+
+template <typename T>
+void launch_bs_relax(const Geom& g, const T* r, const T* xin, T* xout, T* prhs, T* dp, T* vtmp,
+                     double t, double omega, double jacobi_weight, int jacobi_sweeps,
+                     hipStream_t s, int nb) {
+    const int tiles = (g.N + 1 + BT - 1) / BT;
+    const dim3 grid(8 * ((tiles * tiles + 7) / 8), nb);
+    const T inv_t = T(1.0 / t), wj = T(jacobi_weight);
+    bs_div_kernel<T, 0><<<grid, BNT, 0, s>>>(g, r, prhs, dp, inv_t, wj);
+    for (int k = 1; k < jacobi_sweeps; ++k) {
+        bs_grad_kernel<T, 0><<<grid, BNT, 0, s>>>(g, dp, nullptr, nullptr, vtmp, T(0), T(0));
+        bs_div_kernel<T, 1><<<grid, BNT, 0, s>>>(g, vtmp, prhs, dp, inv_t, wj);
+    }
+    bs_grad_kernel<T, 1><<<grid, BNT, 0, s>>>(g, dp, r, xin, xout, T(omega / t), T(omega));
+}
+template void launch_bs_relax<double>(const Geom&, const double*, const double*, double*, double*,
+                                      double*, double*, double, double, double, int, hipStream_t,
+                                      int);
+template void launch_bs_relax<float>(const Geom&, const float*, const float*, float*, float*,
+                                     float*, float*, double, double, double, int, hipStream_t,
+                                     int);
 
 int64_t vanka_boundary_scratch(int N) { return int64_t(n_boundary_patches(N)) * 64; }
 

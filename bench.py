@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--skip-c4", action="store_true",
                     help="skip the 512x512 batched (32 right-hand sides) solves")
     ap.add_argument("--c4-batch", type=int, default=32)
+    ap.add_argument("--skip-bs", action="store_true",
+                    help="skip the Braess-Sarazin comparison solves")
     ap.add_argument("--interior-apply", choices=["vector", "matrix"], default="vector",
                     help="interior Vanka apply: vector ALUs (default) or matrix cores")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -302,6 +304,66 @@ def bench_c4(a, vk, torch, np):
     return res
 
 
+def bench_bs(a, vk, torch, fd, N, L, vanka_ms):
+    """Braess-Sarazin relaxation (t = 1, omega_bs = 1, Jacobi weight 1, two
+    Jacobi sweeps) in the same V(2,2)-preconditioned FGMRES on the headline
+    workload, FP64 and FP32 multigrid, against the Vanka solves timed above;
+    relaxation time per finest-level sweep from HIP events."""
+    res = {"config": "inexact Braess-Sarazin, t=1, omega_bs=1, Jacobi weight 1, 2 Jacobi sweeps "
+                     "on S; same V(2,2) cycle, FGMRES(30), rtol 1e-8, workload as above"}
+    for prec in ("fp64", "fp32"):
+        log(f"[bench] braess-sarazin {prec}")
+        s = vk.VkmgSolver(N, L, precision=prec, relaxation="braess_sarazin")
+        b = s.assemble_rhs(fd)
+        x = torch.zeros_like(b)
+        s.fgmres_solve(b, x, rtol=a.rtol)  # warm (captures graphs)
+        ts, its, infos = [], [], []
+        for _ in range(max(a.steps, 2)):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.fgmres_solve(b, x, rtol=a.rtol, restart=30, max_iters=500)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            its.append(info["iterations"])
+            infos.append(info)
+        s.set_timing(1 << vk.KERNEL_VANKA)
+        x.zero_()
+        s.fgmres_solve(b, x, rtol=a.rtol, restart=30, max_iters=500)
+        nl, ms = s.kernel_timing(vk.KERNEL_VANKA, L - 1)
+        s.set_timing(0)
+        ts.sort()
+        t_med = ts[len(ts) // 2]
+        res[prec] = {"time_to_1e8_s": t_med, "fgmres_iterations": its[0],
+                     "true_rel_res": infos[-1]["true_rel_res"],
+                     "converged": all(i["status_name"] == "VKMG_OK" for i in infos),
+                     "relaxation_us_per_finest_sweep": ms / max(nl, 1) * 1e3}
+        if prec in vanka_ms:
+            res[prec]["vanka_time_to_1e8_s"] = vanka_ms[prec]
+            res[prec]["vanka_over_bs_time"] = vanka_ms[prec] / t_med
+        s.close()
+        # Vanka with the damping that minimises its iteration count in the
+        # oracle's study (0.7-0.8), for a comparison of tuned schemes
+        log(f"[bench] vanka omega=0.75 {prec}")
+        s = vk.VkmgSolver(N, L, precision=prec, omega=0.75, interior_apply=a.interior_apply)
+        b = s.assemble_rhs(fd)
+        x = torch.zeros_like(b)
+        s.fgmres_solve(b, x, rtol=a.rtol)
+        ts = []
+        for _ in range(max(a.steps, 2)):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.fgmres_solve(b, x, rtol=a.rtol, restart=30, max_iters=500)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        res[prec]["vanka_omega075_time_to_1e8_s"] = ts[len(ts) // 2]
+        res[prec]["vanka_omega075_iterations"] = info["iterations"]
+        s.close()
+    return res
+
+
 def main():
     a = parse()
     if a.copy_calibration_mib:
@@ -466,6 +528,12 @@ def main():
         log("[bench] 256x256 sweeps and solves")
         c2 = bench_c2(a, vk, torch, np)
         out["c2_256"] = {k: v for k, v in c2.items() if not k.startswith("_")}
+
+    if not a.skip_bs:
+        vms = {"fp64": out["time_to_1e8_s"]}
+        if "fp32_mg" in out:
+            vms["fp32"] = out["fp32_mg"]["time_to_1e8_s"]
+        out["braess_sarazin"] = bench_bs(a, vk, torch, fd, N, L, vms)
 
     if not a.skip_c4:
         out["c4_512_batched"] = bench_c4(a, vk, torch, np)

@@ -121,6 +121,26 @@ def test_vanka_sweep_every_level(N, levels):
         assert rel(host(xg), lev.smoother.sweep(xo, b)) < 1e-12
 
 
+@pytest.mark.parametrize("omega", [0.3, 0.75, 1.0])
+def test_vanka_sweep_other_damping(omega):
+    """The damping enters both the boundary-class tables and the scaled
+    interior constants; a sweep on every level with omega != 0.5 and the
+    V-cycle against the oracle built with the same omega."""
+    N, levels = 24, 3
+    s = vk.VkmgSolver(N, levels, omega=omega)
+    H = multigrid.Hierarchy(N, levels, omega=omega)
+    for l in range(1, levels):
+        lev = H.levels[l]
+        x, b = dirichlet_consistent_pair(lev.N, 60 + l, 70 + l)
+        xg = dev(x)
+        s.vanka_sweep(l, xg, dev(b))
+        assert rel(host(xg), lev.smoother.sweep(x, b)) < 1e-12
+    r = uniform_vector(H.A.shape[0], 77)
+    r[velocity_dirichlet_mask(N)] = 0.0
+    assert rel(host(s.vcycle(dev(r))), H.vcycle(r)) < 1e-11
+    s.close()
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_interior_apply_variants_agree(precision, tol):
     """The matrix-instruction and vector-ALU interior applies against the

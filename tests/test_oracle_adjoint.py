@@ -1,0 +1,40 @@
+"""Pin of the oracle's force gradient (chain rule through the symmetric
+solve) against central differences of the oracle's own solve.  The loss is
+quadratic in f, so central differences are exact up to rounding."""
+
+import numpy as np
+
+from oracle import adjoint
+from stokes_inputs import gaussian_random_field, grid_sizes, uniform_vector
+
+
+def test_force_gradient_matches_central_differences():
+    N = 6
+    gs = grid_sizes(N)
+    f = gaussian_random_field(N, 3, length=0.3)
+    xt = uniform_vector(gs.n, 4)
+
+    def loss(ff):
+        x = adjoint.solve(N, ff)
+        return 0.5 * float(np.sum((x - xt) ** 2))
+
+    x = adjoint.solve(N, f)
+    grad = adjoint.force_gradient(N, x - xt)
+    rng = np.random.default_rng(8)
+    for _ in range(5):
+        d = rng.standard_normal(f.shape)
+        fd = (loss(f + d) - loss(f - d)) / 2.0
+        assert abs(fd - float(np.sum(grad * d))) <= 1e-9 * abs(fd)
+
+
+def test_pressure_projection_removes_the_null_space_component():
+    N = 4
+    gs = grid_sizes(N)
+    f = gaussian_random_field(N, 5, length=0.3)
+    x = adjoint.solve(N, f)
+    assert abs(x[gs.off_p:].mean()) < 1e-14
+    # the gradient ignores a constant pressure shift in dL/dx
+    g = uniform_vector(gs.n, 6)
+    g2 = g.copy()
+    g2[gs.off_p:] += 3.0
+    assert np.allclose(adjoint.force_gradient(N, g), adjoint.force_gradient(N, g2), atol=1e-12)

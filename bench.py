@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--c4-batch", type=int, default=32)
     ap.add_argument("--skip-bs", action="store_true",
                     help="skip the Braess-Sarazin comparison solves")
+    ap.add_argument("--skip-adjoint", action="store_true",
+                    help="skip the forward + adjoint (gradient) timing")
     ap.add_argument("--interior-apply", choices=["vector", "matrix"], default="vector",
                     help="interior Vanka apply: vector ALUs (default) or matrix cores")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -364,6 +366,39 @@ def bench_bs(a, vk, torch, fd, N, L, vanka_ms):
     return res
 
 
+def bench_adjoint(a, vk, torch, fd, N, L):
+    """Gradient of L = |x - x_t|^2 / 2 with respect to the body force on the
+    headline workload: forward solve + adjoint solve + transposed load map
+    (paper_2401_06277_amd.autograd), FP64 multigrid, rtol 1e-8 both ways."""
+    import numpy as np
+
+    from paper_2401_06277_amd.autograd import stokes_solve
+    from stokes_inputs import gaussian_random_field
+
+    log("[bench] adjoint (force gradient)")
+    s = vk.VkmgSolver(N, L)
+    xt = torch.from_numpy(np.ascontiguousarray(
+        np.concatenate([gaussian_random_field(N, 6).ravel(),
+                        np.zeros((N + 1) ** 2)]))).cuda() * 0.01
+    ts = []
+    for k in range(max(a.steps, 2) + 1):
+        f = fd.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = stokes_solve(f, s, rtol=a.rtol)
+        loss = 0.5 * torch.sum((x - xt) ** 2)
+        loss.backward()
+        torch.cuda.synchronize()
+        if k > 0:  # the first pass captures the graphs
+            ts.append(time.perf_counter() - t0)
+    ts.sort()
+    s.close()
+    return {"config": "L = |x - x_t|^2/2, x_t = 0.01 GRF (seed 6) on the velocity, rtol 1e-8; "
+                      "forward + backward wall time",
+            "time_s": ts[len(ts) // 2],
+            "grad_norm": float(torch.linalg.norm(f.grad))}
+
+
 def main():
     a = parse()
     if a.copy_calibration_mib:
@@ -534,6 +569,11 @@ def main():
         if "fp32_mg" in out:
             vms["fp32"] = out["fp32_mg"]["time_to_1e8_s"]
         out["braess_sarazin"] = bench_bs(a, vk, torch, fd, N, L, vms)
+
+    if not a.skip_adjoint:
+        out["adjoint_force_gradient"] = bench_adjoint(a, vk, torch, fd, N, L)
+        out["adjoint_force_gradient"]["over_forward_solve"] = (
+            out["adjoint_force_gradient"]["time_s"] / out["time_to_1e8_s"])
 
     if not a.skip_c4:
         out["c4_512_batched"] = bench_c4(a, vk, torch, np)

@@ -187,6 +187,24 @@ vkmg_status vkmg_assemble_rhs(vkmg_ctx* ctx, const double* f, const double* g, d
                               void* stream);
 
 /*
+ * Transpose of the force-to-load map of vkmg_assemble_rhs (the part
+ * f -> (M f)_F of b; for the adjoint of a solve with respect to the body
+ * force): grad_f = M^T R_F^T lam, i.e. grad_f(k) = sum over the free
+ * velocity DoFs i of M_ik lam_u(i), per component.  lam: n doubles (only its
+ * velocity block on free nodes is read); grad_f: 2 (2N+1)^2 doubles, FP64,
+ * finest level.  Asynchronous.
+ */
+vkmg_status vkmg_assemble_rhs_adjoint(vkmg_ctx* ctx, const double* lam, double* grad_f,
+                                      void* stream);
+
+/*
+ * x_p -= mean(x_p): removes the constant-pressure null-space component of an
+ * FP64 finest-level vector (plain mean over the (N+1)^2 pressure DoFs; an
+ * orthogonal projection, so it is its own adjoint).  Asynchronous.
+ */
+vkmg_status vkmg_remove_pressure_mean(vkmg_ctx* ctx, double* x, void* stream);
+
+/*
  * One additive Vanka sweep on `level` (1 <= level <= levels-1), in the
  * context's multigrid precision (x, b are double for VKMG_FP64 contexts and
  * float for VKMG_FP32 contexts): r = b - A_l x, then

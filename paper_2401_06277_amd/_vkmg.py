@@ -35,7 +35,7 @@ STATUS = {
 EXPORTED = [
     "vkmg_default_options", "vkmg_setup", "vkmg_destroy", "vkmg_layout_of", "vkmg_level_layout",
     "vkmg_num_levels", "vkmg_residual", "vkmg_apply", "vkmg_assemble_rhs", "vkmg_vanka_sweep",
-    "vkmg_vanka_update", "vkmg_relax",
+    "vkmg_vanka_update", "vkmg_relax", "vkmg_assemble_rhs_adjoint", "vkmg_remove_pressure_mean",
     "vkmg_restrict", "vkmg_prolong_add", "vkmg_coarse_solve", "vkmg_vcycle",
     "vkmg_fgmres_solve", "vkmg_set_timing", "vkmg_kernel_timing", "vkmg_host_patch_matrix",
     "vkmg_status_string", "vkmg_last_error",
@@ -106,6 +106,8 @@ def load_library(path: str = LIB_PATH):
         "vkmg_vanka_sweep": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_vanka_update": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_relax": (c_int32, [P, c_int32, P, P, P]),
+        "vkmg_assemble_rhs_adjoint": (c_int32, [P, P, P, P]),
+        "vkmg_remove_pressure_mean": (c_int32, [P, P, P]),
         "vkmg_restrict": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_prolong_add": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_coarse_solve": (c_int32, [P, P, P, P]),
@@ -266,6 +268,39 @@ class VkmgSolver:
                                     self._stream())
         _check(st, "vkmg_assemble_rhs")
         return b
+
+    def dirichlet_mask(self):
+        """Boolean tensor (n * batch) marking the Dirichlet velocity DoFs
+        (boundary Q2 nodes, both components): where vkmg_fgmres_solve's
+        initial guess must carry the boundary values of b."""
+        if getattr(self, "_dmask", None) is None:
+            lay = self.layout
+            s2 = lay["q2_side"]
+            node = self._torch.zeros((s2, s2), dtype=self._torch.bool)
+            node[0, :] = node[-1, :] = node[:, 0] = node[:, -1] = True
+            m = self._torch.zeros(lay["n"], dtype=self._torch.bool)
+            m[:2 * s2 * s2] = node.reshape(-1).repeat(2)
+            self._dmask = m.repeat(self.batch).to(self.device)
+        return self._dmask
+
+    def assemble_rhs_adjoint(self, lam, grad_f=None):
+        """Transpose of the force-to-load map of assemble_rhs applied to lam."""
+        lay = self.layout
+        nb = self.batch
+        grad_f = self._empty(lay["n_vel"] * nb, self._torch.float64) if grad_f is None else grad_f
+        st = _lib.vkmg_assemble_rhs_adjoint(
+            self._ctx, self._ptr(lam, self._torch.float64, lay["n"] * nb, "lam"),
+            self._ptr(grad_f, self._torch.float64, lay["n_vel"] * nb, "grad_f"), self._stream())
+        _check(st, "vkmg_assemble_rhs_adjoint")
+        return grad_f
+
+    def remove_pressure_mean(self, x):
+        """In place: subtract the mean of the pressure block (per right-hand side)."""
+        st = _lib.vkmg_remove_pressure_mean(
+            self._ctx, self._ptr(x, self._torch.float64, self.layout["n"] * self.batch, "x"),
+            self._stream())
+        _check(st, "vkmg_remove_pressure_mean")
+        return x
 
     def vanka_sweep(self, level: int, x, b):
         n = self.level_layout(level)["n"] * self.batch

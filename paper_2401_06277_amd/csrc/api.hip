@@ -847,6 +847,28 @@ vkmg_status vkmg_assemble_rhs(vkmg_ctx* ctx, const double* f, const double* g, d
     return VKMG_OK;
 }
 
+vkmg_status vkmg_assemble_rhs_adjoint(vkmg_ctx* ctx, const double* lam, double* grad_f,
+                                      void* stream) {
+    if (!ctx || !lam || !grad_f)
+        return fail(VKMG_ERR_INVALID_ARG, "assemble_rhs_adjoint: NULL argument");
+    if (static_cast<const void*>(lam) == static_cast<const void*>(grad_f))
+        return fail(VKMG_ERR_INVALID_ARG, "assemble_rhs_adjoint: grad_f must not alias lam");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    launch_rhs_adjoint(ctx->top(), lam, grad_f, as_stream(stream), ctx->nb());
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_remove_pressure_mean(vkmg_ctx* ctx, double* x, void* stream) {
+    if (!ctx || !x) return fail(VKMG_ERR_INVALID_ARG, "remove_pressure_mean: NULL argument");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    // scratch: the dot partials and slot 1000 of each coefficient area
+    launch_pressure_mean_zero(ctx->top(), x, ctx->part, ctx->hdev + 1000, kHostScratch,
+                              as_stream(stream), ctx->nb());
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
 vkmg_status vkmg_vanka_sweep(vkmg_ctx* ctx, int32_t level, void* x, const void* b, void* stream) {
     if (!x || !b || !check_level(ctx, level, true))
         return fail(VKMG_ERR_INVALID_ARG, "vanka_sweep: NULL argument or level not in [1, levels)");

@@ -25,6 +25,15 @@ void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hip
 void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hipStream_t s,
                 int nb = 1);
 
+// grad_f = transpose of f -> (M f)_F (the force part of launch_rhs) applied
+// to lam (n values per right-hand side; its velocity block is read on free
+// nodes); grad_f: 2 (2N+1)^2 values per right-hand side.
+void launch_rhs_adjoint(const Geom& g, const double* lam, double* grad, hipStream_t s, int nb = 1);
+// x_p -= mean(x_p) on every right-hand side (FP64): partial sums in part
+// (256 per entry), the sums at sums[entry * so].
+void launch_pressure_mean_zero(const Geom& g, double* x, double* part, double* sums, int64_t so,
+                               hipStream_t s, int nb = 1);
+
 // One Vanka update given the residual r of x_in:
 // x_out = x_in + sum_i V_i^T W_i A_i^{-1} V_i r (x_out == x_in allowed;
 // x_in == nullptr means x_in = 0, so r = b).  `table` is the level's

@@ -1229,6 +1229,76 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Transpose of f -> b_F = (M f)_F (the force-dependent part of rhs_kernel):
+// grad_f(k) = h^2/900 sum over the free Q2 nodes i within two of k of
+// M_ik lambda_u(i), with the interior row stencil of i (every free row is an
+// interior row).  One thread per Q2 node, both components; batched over
+// blockIdx.y (lambda advances by g.n, grad by 2 nq2).
+__global__ __launch_bounds__(256) void rhs_adjoint_kernel(Geom g, const double* __restrict__ lam,
+                                                          double* __restrict__ grad) {
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.z * 4 + (threadIdx.x >> 6);
+    if (i >= g.s2 || j >= g.s2) return;
+    lam += int64_t(blockIdx.y) * g.n;
+    grad += int64_t(blockIdx.y) * 2 * g.nq2;
+    double vx[5][5], vy[5][5];
+    bool ok[5][5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            const int qi = i - (a - 2), qj = j - (b - 2);
+            ok[b][a] = qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
+            const int64_t q = ok[b][a] ? int64_t(qj) * g.s2 + qi : 0;
+            vx[b][a] = lam[q];
+            vy[b][a] = lam[g.nq2 + q];
+        }
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            // row node (i - ox, j - oy) with offset (ox, oy) = (a - 2, b - 2)
+            const int ox = a - 2, oy = b - 2;
+            const int c = st_M((j - oy) & 1, oy) * st_M((i - ox) & 1, ox);
+            const double w = ok[b][a] ? double(c) : 0.0;
+            sx += w * vx[b][a];
+            sy += w * vy[b][a];
+        }
+    const double cm = g.h * g.h / 900.0;
+    const int64_t q = int64_t(j) * g.s2 + i;
+    grad[q] = cm * sx;
+    grad[g.nq2 + q] = cm * sy;
+}
+
+// Sum of the pressure block of every batch entry: partial sums per block
+// (part[entry * G + blk], G = gridDim.x).
+__global__ __launch_bounds__(256) void pressure_sum_kernel(Geom g, const double* __restrict__ x,
+                                                           double* __restrict__ part) {
+    const double* p = x + int64_t(blockIdx.y) * g.n + 2 * g.nq2;
+    double s = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < g.nq1;
+         i += int64_t(gridDim.x) * 256)
+        s += p[i];
+    __shared__ double red[4];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// x_p -= sum / nq1 with the sum of entry blockIdx.y at sums[entry * so]
+__global__ __launch_bounds__(256) void pressure_shift_kernel(Geom g, double* __restrict__ x,
+                                                             const double* __restrict__ sums,
+                                                             int64_t so) {
+    double* p = x + int64_t(blockIdx.y) * g.n + 2 * g.nq2;
+    const double m = sums[int64_t(blockIdx.y) * so] / double(g.nq1);
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < g.nq1;
+         i += int64_t(gridDim.x) * 256)
+        p[i] -= m;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void coarse_gemv_kernel(int64_t n, const double* __restrict__ C,
                                                           const T* __restrict__ r,
@@ -1650,6 +1720,19 @@ template void launch_bs_relax<double>(const Geom&, const double*, const double*,
 template void launch_bs_relax<float>(const Geom&, const float*, const float*, float*, float*,
                                      float*, float*, double, double, double, int, hipStream_t,
                                      int);
+
+void launch_rhs_adjoint(const Geom& g, const double* lam, double* grad, hipStream_t s, int nb) {
+    const dim3 grid((g.s2 + 63) / 64, nb, (g.s2 + 3) / 4);
+    rhs_adjoint_kernel<<<grid, 256, 0, s>>>(g, lam, grad);
+}
+
+void launch_pressure_mean_zero(const Geom& g, double* x, double* part, double* sums, int64_t so,
+                               hipStream_t s, int nb) {
+    constexpr int kBlocks = 256;
+    pressure_sum_kernel<<<dim3(kBlocks, nb), 256, 0, s>>>(g, x, part);
+    reduce_partials_kernel<<<dim3(1, nb), 256, 0, s>>>(part, kBlocks, sums, so);
+    pressure_shift_kernel<<<dim3(kBlocks, nb), 256, 0, s>>>(g, x, sums, so);
+}
 
 int64_t vanka_boundary_scratch(int N) { return int64_t(n_boundary_patches(N)) * 64; }
 

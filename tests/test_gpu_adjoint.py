@@ -1,0 +1,136 @@
+"""GPU: differentiable solve with respect to the body force
+(paper_2401_06277_amd.autograd.stokes_solve).  The transpose of the
+force-to-load map against the inner-product identity and the oracle's mass
+matrix (1e-13); the gradient of L = |x_hat - x_t|^2 / 2 against the oracle's
+chain-rule gradient and against central differences of the GPU solve on 20
+seeded directions (1e-6 relative, the solves at rtol 1e-12)."""
+
+import numpy as np
+import pytest
+
+from oracle import adjoint
+from oracle.fem import assemble_q2_mass
+from stokes_inputs import gaussian_random_field, grid_sizes, uniform_vector, velocity_dirichlet_mask
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2401_06277_amd as vk  # noqa: E402
+from paper_2401_06277_amd.autograd import stokes_solve  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+
+
+@pytest.mark.parametrize("N,levels", [(8, 2), (24, 3)])
+def test_rhs_adjoint_is_the_transpose(N, levels):
+    s = vk.VkmgSolver(N, levels)
+    gs = grid_sizes(N)
+    f = uniform_vector(2 * gs.n_q2, 1)
+    lam = uniform_vector(gs.n, 2)
+    b = host(s.assemble_rhs(dev(f)))
+    gf = host(s.assemble_rhs_adjoint(dev(lam)))
+    lhs, rhs = float(b @ lam), float(f @ gf)
+    assert abs(lhs - rhs) <= 1e-13 * (np.abs(b).max() * np.abs(lam).sum())
+    free = ~velocity_dirichlet_mask(N)[:gs.off_p]
+    lu = np.where(free, lam[:gs.off_p], 0.0).reshape(2, -1)
+    M = assemble_q2_mass(N)
+    ref = np.concatenate([M @ lu[0], M @ lu[1]])
+    assert np.abs(gf - ref).max() <= 1e-13 * np.abs(ref).max()
+    s.close()
+
+
+def test_remove_pressure_mean():
+    N, levels = 16, 3
+    s = vk.VkmgSolver(N, levels, batch=2)
+    gs = grid_sizes(N)
+    x = np.concatenate([uniform_vector(gs.n, 3), uniform_vector(gs.n, 4) + 5.0])
+    xd = dev(x)
+    s.remove_pressure_mean(xd)
+    got = host(xd).reshape(2, -1)
+    for k in range(2):
+        ref = x.reshape(2, -1)[k].copy()
+        ref[gs.off_p:] -= ref[gs.off_p:].mean()
+        assert np.abs(got[k] - ref).max() < 1e-14 * np.abs(ref).max() + 1e-15
+    s.close()
+
+
+def _problem(N):
+    gs = grid_sizes(N)
+    f = gaussian_random_field(N, 6, length=0.2)
+    xt = uniform_vector(gs.n, 7) * 0.01
+    xt[gs.off_p:] -= xt[gs.off_p:].mean()
+    return f, xt
+
+
+def test_force_gradient_matches_oracle():
+    N, levels = 16, 3
+    s = vk.VkmgSolver(N, levels)
+    f, xt = _problem(N)
+    fd = dev(f.ravel()).requires_grad_(True)
+    x = stokes_solve(fd, s, rtol=1e-12)
+    loss = 0.5 * torch.sum((x - dev(xt)) ** 2)
+    loss.backward()
+    g_gpu = host(fd.grad)
+    xo = adjoint.solve(N, f)
+    assert np.linalg.norm(host(x) - xo) <= 1e-9 * np.linalg.norm(xo)
+    g_or = adjoint.force_gradient(N, xo - xt).ravel()
+    assert np.linalg.norm(g_gpu - g_or) <= 1e-6 * np.linalg.norm(g_or)
+    s.close()
+
+
+def test_force_gradient_matches_central_differences():
+    N, levels = 16, 3
+    s = vk.VkmgSolver(N, levels)
+    f, xt = _problem(N)
+    xt_d = dev(xt)
+    fd = dev(f.ravel()).requires_grad_(True)
+    loss = 0.5 * torch.sum((stokes_solve(fd, s, rtol=1e-12) - xt_d) ** 2)
+    loss.backward()
+    grad = fd.grad.detach()
+
+    def L(ff):
+        with torch.no_grad():
+            return float(0.5 * torch.sum((stokes_solve(ff, s, rtol=1e-12) - xt_d) ** 2))
+
+    rng = np.random.default_rng(8)
+    f0 = fd.detach()
+    for _ in range(20):
+        d = dev(rng.standard_normal(f.size))
+        eps = 0.1
+        fdiff = (L(f0 + eps * d) - L(f0 - eps * d)) / (2 * eps)
+        an = float(torch.dot(grad, d))
+        assert abs(fdiff - an) <= 1e-6 * max(abs(an), 1e-12 * float(loss.detach())), (fdiff, an)
+    s.close()
+
+
+def test_batched_force_gradient_equals_single():
+    N, levels = 16, 3
+    f, xt = _problem(N)
+    f2 = gaussian_random_field(N, 9, length=0.2)
+    sb = vk.VkmgSolver(N, levels, batch=2)
+    s1 = vk.VkmgSolver(N, levels)
+    fb = dev(np.concatenate([f.ravel(), f2.ravel()])).requires_grad_(True)
+    xb = stokes_solve(fb, sb, rtol=1e-12)
+    (0.5 * torch.sum((xb.view(2, -1) - dev(xt)) ** 2)).backward()
+    for k, ff in enumerate((f, f2)):
+        fs = dev(ff.ravel()).requires_grad_(True)
+        (0.5 * torch.sum((stokes_solve(fs, s1, rtol=1e-12) - dev(xt)) ** 2)).backward()
+        gb = host(fb.grad).reshape(2, -1)[k]
+        assert np.linalg.norm(gb - host(fs.grad)) <= 1e-8 * np.linalg.norm(host(fs.grad))
+    sb.close()
+    s1.close()

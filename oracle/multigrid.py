@@ -7,6 +7,9 @@ from a zero initial guess.
 
 Readings: the coarse operators are rediscretised on each level (equal to
 the Galerkin product P^T A P for constant viscosity, which a test checks);
+a per-element viscosity (array of N^2 values, index ey*N + ex) is coarsened
+by the arithmetic mean of the four children, and its Vanka patches are then
+all distinct ("simple" Vanka: one stored inverse per patch);
 the relaxation is the additive Vanka sweep (or, with relaxation="bs", the
 inexact Braess-Sarazin step of braess_sarazin.py), nu_pre sweeps before and
 nu_post after the coarse correction; the level-0 solve is exact, with the
@@ -38,6 +41,8 @@ class Level:
         elif relaxation == "bs":
             self.smoother = BraessSarazinSmoother(self.A, N, **(bs or {}))
         else:
+            if np.ndim(nu) > 0:
+                shared = False  # per-element viscosity: every patch differs
             self.smoother = VankaSmoother(self.A, N, self.dmask, omega, shared)
 
 
@@ -53,10 +58,19 @@ class Hierarchy:
             raise ValueError("N must be divisible by 2^(levels-1)")
         self.L = levels
         self.nu_pre, self.nu_post = nu_pre, nu_post
+        nus = [nu]
+        if np.ndim(nu) > 0:
+            for l in range(levels - 1):
+                Nl = N >> l
+                v = np.asarray(nus[-1], dtype=np.float64).reshape(Nl, Nl)
+                nus.append(0.25 * (v[0::2, 0::2] + v[0::2, 1::2] + v[1::2, 0::2] + v[1::2, 1::2]).ravel())
+        else:
+            nus = [nu] * levels
+        self.nu_levels = nus[::-1]  # index l = level (0 coarsest)
         self.levels = []
         for l in range(levels):
             Nl = N >> (levels - 1 - l)
-            self.levels.append(Level(Nl, nu, omega, shared, relax=(l > 0),
+            self.levels.append(Level(Nl, self.nu_levels[l], omega, shared, relax=(l > 0),
                                      relaxation=relaxation, bs=bs))
         self.P = [None] + [prolongation(self.levels[l - 1].N) for l in range(1, levels)]
         # bordered coarse matrix

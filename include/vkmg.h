@@ -156,6 +156,21 @@ vkmg_options vkmg_default_options(void);
 vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu,
                        const vkmg_options* opts, void* hip_stream, vkmg_ctx** out);
 
+/*
+ * As vkmg_setup for a per-element viscosity (paper, bilinear form a(u,v) =
+ * nu (grad u, grad v) with nu constant on each element; the extension to
+ * variable coefficients for which the paper notes that the shared-inverse
+ * Vanka does not apply): nu_elem holds nx*nx positive values on the host,
+ * element (ex, ey) at index ey*nx + ex.  Coarser levels take the
+ * arithmetic mean of the four children.  Every Vanka patch then has its own
+ * inverse ("simple" Vanka: (N_l+1)^2 x 51 x 51 stored weighted inverses per
+ * relaxed level, formed on the host threads); the residual sums the element
+ * matrices scaled by nu_e.  Requires Vanka relaxation (VKMG_ERR_UNSUPPORTED
+ * otherwise); interior_apply is ignored.  Errors as vkmg_setup.
+ */
+vkmg_status vkmg_setup_viscosity(const vkmg_grid* grid, int32_t levels, const double* nu_elem,
+                                 const vkmg_options* opts, void* hip_stream, vkmg_ctx** out);
+
 /* Destroy a context (NULL-safe).  Waits for the device to finish its work. */
 void vkmg_destroy(vkmg_ctx* ctx);
 
@@ -182,6 +197,8 @@ vkmg_status vkmg_apply(vkmg_ctx* ctx, const double* x, double* y, void* stream);
  * Q2 interpolant has nodal values f) and g holds the Dirichlet data.
  * f, g: 2*(2N+1)^2 doubles each ([f_x | f_y], only the boundary entries of
  * g are read; g may be NULL for homogeneous data); b: n doubles, FP64.
+ * Contexts with a per-element viscosity take g == NULL only
+ * (VKMG_ERR_UNSUPPORTED otherwise).
  */
 vkmg_status vkmg_assemble_rhs(vkmg_ctx* ctx, const double* f, const double* g, double* b,
                               void* stream);

@@ -33,7 +33,7 @@ STATUS = {
 }
 
 EXPORTED = [
-    "vkmg_default_options", "vkmg_setup", "vkmg_destroy", "vkmg_layout_of", "vkmg_level_layout",
+    "vkmg_default_options", "vkmg_setup", "vkmg_setup_viscosity", "vkmg_destroy", "vkmg_layout_of", "vkmg_level_layout",
     "vkmg_num_levels", "vkmg_residual", "vkmg_apply", "vkmg_assemble_rhs", "vkmg_vanka_sweep",
     "vkmg_vanka_update", "vkmg_relax", "vkmg_assemble_rhs_adjoint", "vkmg_remove_pressure_mean",
     "vkmg_restrict", "vkmg_prolong_add", "vkmg_coarse_solve", "vkmg_vcycle",
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "vkmg_default_options": (Options, []),
         "vkmg_setup": (c_int32, [POINTER(Grid), c_int32, c_double, POINTER(Options), P, POINTER(P)]),
+        "vkmg_setup_viscosity": (c_int32, [POINTER(Grid), c_int32, P, POINTER(Options), P, POINTER(P)]),
         "vkmg_destroy": (None, [P]),
         "vkmg_layout_of": (c_int32, [P, POINTER(Layout)]),
         "vkmg_level_layout": (c_int32, [P, c_int32, POINTER(Layout)]),
@@ -162,7 +163,7 @@ class VkmgSolver:
                  omega: float = 0.5, precision: str = "fp64", interior_apply: str = "vector",
                  graphs: bool = True, batch: int = 1, relaxation: str = "vanka",
                  bs_t: float = 1.0, bs_omega: float = 1.0, bs_jacobi_weight: float = 1.0,
-                 bs_jacobi_sweeps: int = 2):
+                 bs_jacobi_sweeps: int = 2, nu_elem=None):
         import torch
         lib = load_library()
         self._torch = torch
@@ -176,9 +177,19 @@ class VkmgSolver:
                        APPLY[interior_apply], 1 if graphs else 0, batch, RELAX[relaxation],
                        bs_t, bs_omega, bs_jacobi_weight, bs_jacobi_sweeps)
         ctx = c_void_p()
-        st = lib.vkmg_setup(byref(Grid(N, N)), levels, nu, byref(opts), self._stream(),
-                            byref(ctx))
-        _check(st, "vkmg_setup")
+        if nu_elem is None:
+            st = lib.vkmg_setup(byref(Grid(N, N)), levels, nu, byref(opts), self._stream(),
+                                byref(ctx))
+            _check(st, "vkmg_setup")
+        else:
+            # per-element viscosity (host array of N*N values, index ey*N + ex)
+            arr = np.ascontiguousarray(np.asarray(nu_elem, dtype=np.float64).ravel())
+            if arr.size != N * N:
+                raise ValueError(f"nu_elem must have {N * N} values")
+            st = lib.vkmg_setup_viscosity(byref(Grid(N, N)), levels,
+                                          arr.ctypes.data_as(c_void_p), byref(opts),
+                                          self._stream(), byref(ctx))
+            _check(st, "vkmg_setup_viscosity")
         self._ctx = ctx
         self.N, self.levels, self.nu, self.batch = N, levels, nu, batch
         self.device = torch.device("cuda", torch.cuda.current_device())

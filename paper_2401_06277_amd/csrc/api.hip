@@ -43,6 +43,7 @@ struct LevelBuf {
     void* W = nullptr;     // patch-operator table, MG precision (relaxed levels)
     void* dbuf = nullptr;  // boundary-patch corrections (relaxed levels)
     void* bs = nullptr;    // Braess-Sarazin scratch: Schur rhs, dp, B^T dp (relaxed levels)
+    void* nu = nullptr;    // per-element viscosity, MG precision (variable-viscosity contexts)
 };
 
 }  // namespace
@@ -80,6 +81,10 @@ struct vkmg_ctx {
 
     size_t esize() const { return opt.mg_precision == VKMG_FP32 ? 4 : 8; }
     int nb() const { return opt.batch; }
+    bool variable = false;     // per-element viscosity ("simple" Vanka, per-patch inverses)
+    double* nu64 = nullptr;    // finest-level per-element viscosity, FP64 (FGMRES residuals)
+    template <typename T>
+    const T* nu_of(int l) const { return static_cast<const T*>(lev[l].nu); }
     const Geom& top() const { return lev.back().g; }
 };
 
@@ -168,10 +173,15 @@ void sweep_t(vkmg_ctx* c, int l, const T* b, T* x, bool x_zero, hipStream_t s,
     const T* r = b;
     if (!x_zero) {
         Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
-        launch_residual<T, T>(L.g, b, x, static_cast<T*>(L.r), 0, s, c->nb());
+        launch_residual<T, T>(L.g, b, x, static_cast<T*>(L.r), 0, s, c->nb(), c->nu_of<T>(l));
         r = static_cast<const T*>(L.r);
     }
     Timed t(c, VKMG_KERNEL_VANKA, s, l);
+    if (c->variable) {
+        launch_vanka_simple<T>(L.g, r, x_zero ? nullptr : x, x, static_cast<const T*>(L.W),
+                               static_cast<T*>(L.dbuf), s, c->nb());
+        return;
+    }
     if (!vanka && c->opt.relaxation == VKMG_RELAX_BRAESS_SARAZIN) {
         const int64_t np = L.g.nq1 * c->nb();
         T* prhs = static_cast<T*>(L.bs);
@@ -201,7 +211,7 @@ void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
         launch_fill_zero<T>(x, L.g.n * c->nb(), s);
     } else {
         Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
-        launch_residual<T, T>(L.g, b, x, r, 0, s, c->nb());
+        launch_residual<T, T>(L.g, b, x, r, 0, s, c->nb(), c->nu_of<T>(l));
         rr = r;
     }
     T* bc = static_cast<T*>(Lc.b);
@@ -355,7 +365,7 @@ vkmg_status fgmres_batched(vkmg_ctx* ctx, const double* b, double* x, double rto
     };
     auto residual = [&]() {
         Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
-        launch_residual<double, double>(g, b, x, r, 0, s, B);
+        launch_residual<double, double>(g, b, x, r, 0, s, B, ctx->nu64);
     };
     struct Sys {
         std::vector<double> Hu, R, cs, sn, gbase, gv, y;
@@ -417,7 +427,7 @@ vkmg_status fgmres_batched(vkmg_ctx* ctx, const double* b, double* x, double rto
         vcycle_impl(ctx, vj, zj, ss);
         {
             Timed t(ctx, VKMG_KERNEL_RESIDUAL, ss);
-            launch_residual<double, double>(g, nullptr, zj, w, 1, ss, B);
+            launch_residual<double, double>(g, nullptr, zj, w, 1, ss, B, ctx->nu64);
         }
         Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);
         launch_dcgs_dots(V, S, j, vj, w, n, ctx->part, ss, B, n);
@@ -637,8 +647,9 @@ vkmg_status vkmg_host_patch_matrix(int32_t N, double nu, double omega, int32_t c
     return VKMG_OK;
 }
 
-vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const vkmg_options* opts,
-                       void* hip_stream, vkmg_ctx** out) {
+static vkmg_status setup_impl(const vkmg_grid* grid, int32_t levels, double nu,
+                              const double* nu_elem, const vkmg_options* opts, void* hip_stream,
+                              vkmg_ctx** out) {
     if (!grid || !out) return fail(VKMG_ERR_INVALID_ARG, "setup: NULL grid or out");
     *out = nullptr;
     if (grid->nx != grid->ny) return fail(VKMG_ERR_INVALID_ARG, "setup: nx must equal ny");
@@ -675,6 +686,29 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         return fail(VKMG_ERR_INVALID_ARG,
                     "setup: Braess-Sarazin parameters out of range (t > 0, omega and Jacobi "
                     "weight in (0, 2], 1..16 Jacobi sweeps)");
+    // per-element viscosity: finest level as given, coarser levels by the
+    // arithmetic mean of the four children
+    std::vector<std::vector<double>> nul(levels);
+    if (nu_elem) {
+        if (o.relaxation != VKMG_RELAX_VANKA)
+            return fail(VKMG_ERR_UNSUPPORTED,
+                        "setup: a per-element viscosity needs Vanka relaxation");
+        nul[levels - 1].assign(nu_elem, nu_elem + size_t(N) * N);
+        for (double v : nul[levels - 1])
+            if (!(v > 0.0) || !std::isfinite(v))
+                return fail(VKMG_ERR_INVALID_ARG, "setup: viscosities must be positive and finite");
+        for (int l = levels - 2; l >= 0; --l) {
+            const int Nc = N >> (levels - 1 - l), Nf = 2 * Nc;
+            const std::vector<double>& f = nul[l + 1];
+            nul[l].resize(size_t(Nc) * Nc);
+            for (int ey = 0; ey < Nc; ++ey)
+                for (int ex = 0; ex < Nc; ++ex)
+                    nul[l][size_t(ey) * Nc + ex] =
+                        0.25 * ((f[size_t(2 * ey) * Nf + 2 * ex] + f[size_t(2 * ey) * Nf + 2 * ex + 1]) +
+                                (f[size_t(2 * ey + 1) * Nf + 2 * ex] +
+                                 f[size_t(2 * ey + 1) * Nf + 2 * ex + 1]));
+        }
+    }
 
     // host work first (no GPU needed to detect singular patches)
     double B1[651];
@@ -682,6 +716,13 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         return fail(VKMG_ERR_SINGULAR_PATCH, "setup: universal interior operator failed");
     std::vector<std::vector<double>> Wh(levels);
     for (int l = 1; l < levels; ++l) {
+        if (nu_elem) {  // one weighted inverse per patch
+            const int Nl = N >> (levels - 1 - l);
+            Wh[l].resize(size_t(Nl + 1) * (Nl + 1) * kSlots * kSlots);
+            if (!simple_vanka_tables(Nl, nul[l].data(), o.omega, Wh[l].data()))
+                return fail(VKMG_ERR_SINGULAR_PATCH, "setup: singular Vanka patch matrix");
+            continue;
+        }
         const int Nl = N >> (levels - 1 - l);
         Wh[l].assign(size_t(kLevelTable), 0.0);
         for (int c = 0; c < kClasses; ++c) {
@@ -712,12 +753,13 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
     mfma_interior_table(B1, o.mg_precision == VKMG_FP64, Mh.data());
     std::vector<float> Mf(Mh.begin(), Mh.end());
     std::vector<double> Ch;
-    if (!coarse_bordered_inverse(N0, nu, Ch))
+    if (!coarse_bordered_inverse(N0, nu, Ch, nu_elem ? nul[0].data() : nullptr))
         return fail(VKMG_ERR_SINGULAR_PATCH, "setup: singular coarse matrix");
 
     std::unique_ptr<vkmg_ctx> c(new vkmg_ctx);
     c->L = levels;
     c->opt = o;
+    c->variable = nu_elem != nullptr;
     VKMG_HIP(hipGetDevice(&c->device));
     hipStream_t s = as_stream(hip_stream);
     c->lev.resize(levels);
@@ -730,12 +772,29 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
         st = alloc(c.get(), &L.x, es * L.g.n * nbt);
         if (st == VKMG_OK) st = alloc(c.get(), &L.b, es * L.g.n * nbt);
         if (st == VKMG_OK) st = alloc(c.get(), &L.r, es * L.g.n * nbt);
+        const size_t npatch = size_t(L.g.N + 1) * (L.g.N + 1);
         if (st == VKMG_OK && l >= 1)
-            st = alloc(c.get(), &L.dbuf, es * size_t(vanka_boundary_scratch(L.g.N)) * nbt);
+            st = alloc(c.get(), &L.dbuf,
+                       es * (nu_elem ? npatch * 64 : size_t(vanka_boundary_scratch(L.g.N))) * nbt);
+        if (st == VKMG_OK && l >= 1 && nu_elem) {
+            const size_t ne = size_t(L.g.N) * L.g.N;
+            st = alloc(c.get(), &L.nu, es * ne);
+            if (st == VKMG_OK) {
+                hipError_t e;
+                if (o.mg_precision == VKMG_FP64) {
+                    e = hipMemcpyAsync(L.nu, nul[l].data(), 8 * ne, hipMemcpyHostToDevice, s);
+                } else {
+                    std::vector<float> vf(nul[l].begin(), nul[l].end());
+                    e = hipMemcpyAsync(L.nu, vf.data(), 4 * ne, hipMemcpyHostToDevice, s);
+                    if (e == hipSuccess) e = hipStreamSynchronize(s);
+                }
+                if (e != hipSuccess) st = fail(VKMG_ERR_HIP, "setup: upload of viscosities");
+            }
+        }
         if (st == VKMG_OK && l >= 1 && o.relaxation == VKMG_RELAX_BRAESS_SARAZIN)
             st = alloc(c.get(), &L.bs, es * size_t(2 * L.g.nq1 + 2 * L.g.nq2) * nbt);
         if (st == VKMG_OK && l >= 1) {
-            const size_t nw = size_t(kLevelTable);
+            const size_t nw = nu_elem ? Wh[l].size() : size_t(kLevelTable);
             st = alloc(c.get(), &L.W, es * nw);
             if (st == VKMG_OK) {
                 if (o.mg_precision == VKMG_FP64) {
@@ -764,6 +823,14 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
     }
     const int64_t n = c->top().n;
     const size_t nbt = size_t(o.batch);
+    if (st == VKMG_OK && nu_elem) {
+        st = alloc(c.get(), reinterpret_cast<void**>(&c->nu64), 8 * size_t(N) * N);
+        if (st == VKMG_OK) {
+            hipError_t e = hipMemcpyAsync(c->nu64, nul[levels - 1].data(), 8 * size_t(N) * N,
+                                          hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) st = fail(VKMG_ERR_HIP, "setup: upload of viscosities");
+        }
+    }
     if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->r64), 8 * n * nbt);
     if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->w64), 8 * n * nbt);
     // partials: 264 rows of kDotBlocks, or 65 rows of dot_blocks(B) per batch entry
@@ -786,6 +853,18 @@ vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const v
     }
     *out = c.release();
     return VKMG_OK;
+}
+
+vkmg_status vkmg_setup(const vkmg_grid* grid, int32_t levels, double nu, const vkmg_options* opts,
+                       void* hip_stream, vkmg_ctx** out) {
+    return setup_impl(grid, levels, nu, nullptr, opts, hip_stream, out);
+}
+
+vkmg_status vkmg_setup_viscosity(const vkmg_grid* grid, int32_t levels, const double* nu_elem,
+                                 const vkmg_options* opts, void* hip_stream, vkmg_ctx** out) {
+    if (out) *out = nullptr;
+    if (!nu_elem) return fail(VKMG_ERR_INVALID_ARG, "setup_viscosity: NULL viscosity field");
+    return setup_impl(grid, levels, 1.0, nu_elem, opts, hip_stream, out);
 }
 
 void vkmg_destroy(vkmg_ctx* ctx) {
@@ -821,7 +900,7 @@ vkmg_status vkmg_residual(vkmg_ctx* ctx, const double* b, const double* x, doubl
     VKMG_HIP(hipSetDevice(ctx->device));
     hipStream_t s = as_stream(stream);
     Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
-    launch_residual<double, double>(ctx->top(), b, x, r, 0, s, ctx->nb());
+    launch_residual<double, double>(ctx->top(), b, x, r, 0, s, ctx->nb(), ctx->nu64);
     VKMG_HIP(hipGetLastError());
     return VKMG_OK;
 }
@@ -832,7 +911,7 @@ vkmg_status vkmg_apply(vkmg_ctx* ctx, const double* x, double* y, void* stream) 
     VKMG_HIP(hipSetDevice(ctx->device));
     hipStream_t s = as_stream(stream);
     Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
-    launch_residual<double, double>(ctx->top(), nullptr, x, y, 1, s, ctx->nb());
+    launch_residual<double, double>(ctx->top(), nullptr, x, y, 1, s, ctx->nb(), ctx->nu64);
     VKMG_HIP(hipGetLastError());
     return VKMG_OK;
 }
@@ -841,6 +920,9 @@ vkmg_status vkmg_assemble_rhs(vkmg_ctx* ctx, const double* f, const double* g, d
                               void* stream) {
     if (!ctx || !f || !b) return fail(VKMG_ERR_INVALID_ARG, "assemble_rhs: NULL f or b");
     if (b == f || b == g) return fail(VKMG_ERR_INVALID_ARG, "assemble_rhs: b must not alias f or g");
+    if (ctx->variable && g)
+        return fail(VKMG_ERR_UNSUPPORTED,
+                    "assemble_rhs: Dirichlet data with a per-element viscosity (lift it by hand)");
     VKMG_HIP(hipSetDevice(ctx->device));
     launch_rhs(ctx->top(), f, g, b, as_stream(stream), ctx->nb());
     VKMG_HIP(hipGetLastError());
@@ -908,6 +990,18 @@ vkmg_status vkmg_vanka_update(vkmg_ctx* ctx, int32_t level, void* x, const void*
     LevelBuf& L = ctx->lev[level];
     const bool mfma = ctx->opt.interior_apply == VKMG_APPLY_MATRIX;
     Timed t(ctx, VKMG_KERNEL_VANKA, s, level);
+    if (ctx->variable) {
+        if (ctx->opt.mg_precision == VKMG_FP64)
+            launch_vanka_simple<double>(L.g, static_cast<const double*>(r), static_cast<double*>(x),
+                                        static_cast<double*>(x), static_cast<const double*>(L.W),
+                                        static_cast<double*>(L.dbuf), s, ctx->nb());
+        else
+            launch_vanka_simple<float>(L.g, static_cast<const float*>(r), static_cast<float*>(x),
+                                       static_cast<float*>(x), static_cast<const float*>(L.W),
+                                       static_cast<float*>(L.dbuf), s, ctx->nb());
+        VKMG_HIP(hipGetLastError());
+        return VKMG_OK;
+    }
     if (ctx->opt.mg_precision == VKMG_FP64)
         launch_vanka_update<double>(L.g, static_cast<const double*>(r), static_cast<double*>(x),
                                     static_cast<double*>(x), static_cast<const double*>(L.W),
@@ -1017,7 +1111,7 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
 
     auto residual = [&](void) {
         Timed t(ctx, VKMG_KERNEL_RESIDUAL, s);
-        launch_residual<double, double>(g, b, x, r, 0, s);
+        launch_residual<double, double>(g, b, x, r, 0, s, 1, ctx->nu64);
     };
     residual();
     double beta0 = 0.0;
@@ -1098,7 +1192,7 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
         vcycle_impl(ctx, vj, zj, ss);
         {
             Timed t(ctx, VKMG_KERNEL_RESIDUAL, ss);
-            launch_residual<double, double>(g, nullptr, zj, w, 1, ss);
+            launch_residual<double, double>(g, nullptr, zj, w, 1, ss, 1, ctx->nu64);
         }
         if (delayed) {
             Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);

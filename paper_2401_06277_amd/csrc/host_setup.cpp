@@ -22,6 +22,9 @@
 
 #include "symmetry.h"
 #include "mfma_patch.h"
+#include <atomic>
+#include <thread>
+
 #include "vkmg_internal.h"
 
 namespace vkmg {
@@ -81,8 +84,13 @@ int class_representative(int c, int N) {
 
 bool patch_matrix(int N, double nu, int cls, double* A, uint8_t* present) {
     if (N < 4 || cls < 0 || cls >= kClasses) return false;
-    const int I = class_representative(cls % 5, N);
-    const int J = class_representative(cls / 5, N);
+    patch_matrix_at(N, nullptr, nu, class_representative(cls % 5, N),
+                    class_representative(cls / 5, N), A, present);
+    return true;
+}
+
+void patch_matrix_at(int N, const double* nu_elem, double nu, int I, int J, double* A,
+                     uint8_t* present) {
     const double h = 1.0 / N;
     const int s2 = 2 * N + 1;
     std::fill(A, A + kSlots * kSlots, 0.0);
@@ -114,12 +122,13 @@ bool patch_matrix(int N, double nu, int cls, double* A, uint8_t* present) {
             for (int d = 0; d < 2; ++d)
                 for (int c = 0; c < 2; ++c)
                     if (ex + c == I && ey + d == J) pl = 2 * d + c;
+            const double nue = nu_elem ? nu_elem[int64_t(ey) * N + ex] : nu;
             for (int k = 0; k < 9; ++k) {
                 if (sl[k] < 0) continue;
                 const int a = k % 3, b = k / 3;
                 for (int m = 0; m < 9; ++m) {
                     if (sl[m] < 0) continue;
-                    const double v = nu * elem_L(a, b, m % 3, m / 3);
+                    const double v = nue * elem_L(a, b, m % 3, m / 3);
                     A[sl[k] * kSlots + sl[m]] += v;
                     A[(25 + sl[k]) * kSlots + 25 + sl[m]] += v;
                 }
@@ -144,7 +153,6 @@ bool patch_matrix(int N, double nu, int cls, double* A, uint8_t* present) {
         A[s * kSlots + s] = 1.0;
     }
     if (present) std::memcpy(present, pres, kSlots);
-    return true;
 }
 
 bool invert_dense(int n, std::vector<double>& A, std::vector<double>& Ainv) {
@@ -194,8 +202,12 @@ bool invert_dense(int n, std::vector<double>& A, std::vector<double>& Ainv) {
 
 void weighted_inverse(int N, int cls, double omega, const double* Ainv, const uint8_t* present,
                       double* W) {
-    const int I = class_representative(cls % 5, N);
-    const int J = class_representative(cls / 5, N);
+    weighted_inverse_at(N, class_representative(cls % 5, N), class_representative(cls / 5, N),
+                        omega, Ainv, present, W);
+}
+
+void weighted_inverse_at(int N, int I, int J, double omega, const double* Ainv,
+                         const uint8_t* present, double* W) {
     const int s2 = 2 * N + 1;
     for (int s = 0; s < kSlots; ++s) {
         double w = 0.0;
@@ -217,7 +229,7 @@ void weighted_inverse(int N, int cls, double omega, const double* Ainv, const ui
     }
 }
 
-void assemble_dense_level(int N, double nu, std::vector<double>& A) {
+void assemble_dense_level(int N, double nu, std::vector<double>& A, const double* nu_elem) {
     const Geom g = make_geom(N, nu);
     const int64_t n = g.n;
     A.assign(size_t(n) * n, 0.0);
@@ -229,9 +241,10 @@ void assemble_dense_level(int N, double nu, std::vector<double>& A) {
             for (int k = 0; k < 9; ++k) {
                 const int a = k % 3, b = k / 3;
                 const int qi = 2 * ex + a, qj = 2 * ey + b;
+                const double nue = nu_elem ? nu_elem[int64_t(ey) * N + ex] : nu;
                 for (int m = 0; m < 9; ++m) {
                     const int c = m % 3, d = m / 3;
-                    const double v = nu * elem_L(a, b, c, d);
+                    const double v = nue * elem_L(a, b, c, d);
                     A[ux(qi, qj) * n + ux(2 * ex + c, 2 * ey + d)] += v;
                     A[uy(qi, qj) * n + uy(2 * ex + c, 2 * ey + d)] += v;
                 }
@@ -258,11 +271,11 @@ void assemble_dense_level(int N, double nu, std::vector<double>& A) {
         }
 }
 
-bool coarse_bordered_inverse(int N, double nu, std::vector<double>& C) {
+bool coarse_bordered_inverse(int N, double nu, std::vector<double>& C, const double* nu_elem) {
     const Geom g = make_geom(N, nu);
     const int64_t n = g.n, nb = n + 1;
     std::vector<double> A;
-    assemble_dense_level(N, nu, A);
+    assemble_dense_level(N, nu, A, nu_elem);
     std::vector<double> Ab(size_t(nb) * nb, 0.0);
     for (int64_t r = 0; r < n; ++r)
         for (int64_t c = 0; c < n; ++c) Ab[r * nb + c] = A[r * n + c];
@@ -451,6 +464,39 @@ double universal_mismatch(const double* Blevel, const double* B1, double omega, 
             }
     }
     return err / ref;
+}
+
+// Weighted inverses of every patch of an N x N level with per-element
+// viscosity nu_elem (N^2 values, index ey*N + ex), each stored transposed
+// (51 x 51, column s of W_i at [s*51, s*51+51)) at out + k*51*51 for patch
+// k = J*(N+1) + I; patches are split over the host threads.  Returns false
+// if a patch matrix is singular.
+bool simple_vanka_tables(int N, const double* nu_elem, double omega, double* out) {
+    const int P = (N + 1) * (N + 1);
+    unsigned nt = std::thread::hardware_concurrency();
+    if (nt < 1) nt = 1;
+    if (nt > 64) nt = 64;
+    std::atomic<bool> ok{true};
+    auto work = [&](int t) {
+        std::vector<double> A(kSlots * kSlots), inv, W(kSlots * kSlots);
+        uint8_t pres[kSlots];
+        for (int k = t; k < P && ok.load(); k += int(nt)) {
+            const int I = k % (N + 1), J = k / (N + 1);
+            patch_matrix_at(N, nu_elem, 1.0, I, J, A.data(), pres);
+            if (!invert_dense(kSlots, A, inv)) {
+                ok = false;
+                return;
+            }
+            weighted_inverse_at(N, I, J, omega, inv.data(), pres, W.data());
+            double* o = out + int64_t(k) * kSlots * kSlots;
+            for (int i = 0; i < kSlots; ++i)
+                for (int j = 0; j < kSlots; ++j) o[j * kSlots + i] = W[i * kSlots + j];
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) th.emplace_back(work, int(t));
+    for (auto& x : th) x.join();
+    return ok.load();
 }
 
 }  // namespace vkmg

@@ -16,9 +16,11 @@ namespace vkmg {
 
 // r = b - A x (mode 0) or r = A x (mode 1, b unused); Ti: type of x,
 // To: type of b and r, arithmetic in To.
+// nue: per-element viscosity (N^2 values, index ey*N + ex) or nullptr for
+// the constant g.nu.
 template <typename Tx, typename T>
 void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hipStream_t s,
-                     int nb = 1);
+                     int nb = 1, const T* nue = nullptr);
 
 // b = M f - A_FD g on free rows, g on Dirichlet rows, -B_pD g on pressure
 // rows (f, g: 2 (2N+1)^2 values per right-hand side).
@@ -49,6 +51,13 @@ void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const
                          const T* mtab, T* dbuf, double omega, bool mfma, hipStream_t s,
                          int nb = 1);
 int64_t vanka_boundary_scratch(int N);
+// Vanka update with one stored weighted inverse per patch ("simple" Vanka,
+// for a per-element viscosity): `tables` holds (N+1)^2 transposed 51 x 51
+// inverses (simple_vanka_tables), `dbuf` (N+1)^2 * 64 values per
+// right-hand side.
+template <typename T>
+void launch_vanka_simple(const Geom& g, const T* r, const T* xin, T* xout, const T* tables,
+                         T* dbuf, hipStream_t s, int nb = 1);
 
 // One Braess-Sarazin relaxation (inexact form) given the residual r of x_in
 // (x_in == nullptr: x_in = 0, r = b): rhs = r_p - (1/t) B D^{-1} r_u into

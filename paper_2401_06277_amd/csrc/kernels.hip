@@ -98,12 +98,23 @@ constexpr int RQ2 = 2 * RT + 4;     // staged Q2 nodes per side
 constexpr int RQ1 = RT + 2;         // staged Q1 nodes per side
 constexpr int RNT = 2 * RT * RT;    // threads: one per cell and Q2 row parity
 
-template <int MODE, typename Tx, typename T>
+// 1D Q2 stiffness (x 1/(3h)) and mass (x h/30) of one element, local nodes
+// 0, 1 (midpoint), 2: the element Laplacian per unit viscosity between
+// local nodes (a,b) and (c,d) is (M[b][d] K[a][c] + K[b][d] M[a][c]) / 90.
+__device__ constexpr int kEK[3][3] = {{7, -8, 1}, {-8, 16, -8}, {1, -8, 7}};
+__device__ constexpr int kEM[3][3] = {{4, 2, -1}, {2, 16, 2}, {-1, 2, 4}};
+
+// VAR: per-element viscosity nue (N^2 values, index ey*N + ex); the L rows
+// are then summed element by element (each Q2 node lies in 1, 2 or 4
+// elements) instead of by the constant-coefficient stencil.
+template <int MODE, typename Tx, typename T, bool VAR = false>
 __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void residual_kernel(Geom g, const T* __restrict__ b,
                                                        const Tx* __restrict__ x,
-                                                       T* __restrict__ r) {
+                                                       T* __restrict__ r,
+                                                       const T* __restrict__ nue = nullptr) {
     __shared__ T s_u[2][RQ2 * RQ2];
     __shared__ T s_p[RQ1 * RQ1];
+    __shared__ T s_nu[VAR ? RQ1 * RQ1 : 1];
     const int tiles = (g.N + 1 + RT - 1) / RT;
     const int ntile = tiles * tiles;
     const int per_xcd = (ntile + 7) / 8;
@@ -152,6 +163,13 @@ __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void r
         const int t = threadIdx.x + it * RNT;
         if (t < RQ1 * RQ1) s_p[t] = f1[it] ? T(vp[it]) : T(0);
     }
+    if (VAR) {  // viscosities of the elements [E0-1, E0+RT] per direction
+        for (int t = threadIdx.x; t < RQ1 * RQ1; t += RNT) {
+            const int ex = E0x - 1 + t % RQ1, ey = E0y - 1 + t / RQ1;
+            const bool in = ex >= 0 && ey >= 0 && ex < g.N && ey < g.N;
+            s_nu[t] = in ? nue[int64_t(ey) * g.N + ex] : T(0);
+        }
+    }
     __syncthreads();
     // this thread: the two Q2 nodes of row parity bb of cell (tx, ty) (and
     // for bb = 0 the cell's Q1 node); waves 0-3 take bb = 0, waves 4-7 bb = 1
@@ -179,9 +197,42 @@ __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void r
     const int c2 = (2 * ty + 2) * RQ2 + 2 * tx + 2, c1 = (ty + 1) * RQ1 + tx + 1;
     const T cl = T(g.nu / 90.0), cb = T(-g.h / 36.0);
     if (bb == 0)
-        cell_row_pair<RQ2, RQ1, 0>(s_u[0], s_u[1], s_p, c2, c1, cl, cb, ax, ay, ap);
+        cell_row_pair<RQ2, RQ1, 0>(s_u[0], s_u[1], s_p, c2, c1, VAR ? T(0) : cl, cb, ax, ay, ap);
     else
-        cell_row_pair<RQ2, RQ1, 1>(s_u[0], s_u[1], s_p, c2, c1, cl, cb, ax, ay, ap);
+        cell_row_pair<RQ2, RQ1, 1>(s_u[0], s_u[1], s_p, c2, c1, VAR ? T(0) : cl, cb, ax, ay, ap);
+    if (VAR) {
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) {
+            T lx = 0, ly = 0;
+            // elements containing node (2ex+aa, 2ey+bb): ex-1 and ex for a
+            // vertex column (aa = 0), ex for a midpoint column; same in y
+#pragma unroll
+            for (int ey_ = -1; ey_ <= 0; ++ey_) {
+                if (bb == 1 && ey_ == -1) continue;
+#pragma unroll
+                for (int ex_ = -1; ex_ <= 0; ++ex_) {
+                    if (aa == 1 && ex_ == -1) continue;
+                    const int la = aa - 2 * ex_, lb = bb - 2 * ey_;  // local node
+                    const T nv = s_nu[(ty + 1 + ey_) * RQ1 + tx + 1 + ex_];
+                    T ex0 = 0, ey0 = 0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const int co = kEM[lb][d] * kEK[la][c] + kEK[lb][d] * kEM[la][c];
+                            if (co == 0) continue;
+                            const int cc = c2 + (2 * ey_ + d) * RQ2 + 2 * ex_ + c;
+                            ex0 += T(co) * s_u[0][cc];
+                            ey0 += T(co) * s_u[1][cc];
+                        }
+                    lx += nv * ex0;
+                    ly += nv * ey0;
+                }
+            }
+            ax[aa] += T(1.0 / 90.0) * lx;
+            ay[aa] += T(1.0 / 90.0) * ly;
+        }
+    }
 #pragma unroll
     for (int aa = 0; aa < 2; ++aa) {
         const int64_t q = qn[aa];
@@ -666,6 +717,43 @@ __global__ __launch_bounds__(256) void vanka_boundary_kernel(Geom g, const T* __
     }
 }
 
+// "Simple" Vanka for a per-element viscosity: every patch has its own
+// stored weighted inverse (transposed, 51 x 51 per patch, patch k =
+// J*(N+1) + I); one wavefront per patch, lane s computing correction slot s
+// (column reads coalesced over the lanes) into dbuf[k*64 + s].  Batched over
+// blockIdx.y (rb by g.n, dbuf by (N+1)^2 * 64); the tables are shared.
+template <typename T>
+__global__ __launch_bounds__(256) void vanka_patch_kernel(Geom g, const T* __restrict__ rb,
+                                                          const T* __restrict__ tables,
+                                                          T* __restrict__ dbuf) {
+    __shared__ T s_r[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int np = (g.N + 1) * (g.N + 1);
+    rb += int64_t(blockIdx.y) * g.n;
+    dbuf += int64_t(blockIdx.y) * np * 64;
+    const int k = blockIdx.x * 4 + w;
+    const bool active = k < np;
+    const int kk = active ? k : 0;
+    const int I = kk % (g.N + 1), J = kk / (g.N + 1);
+    const int s = lane < kSlots ? lane : 0;
+    const int64_t q = slot_index(g, I, J, s);
+    const T rv = rb[q >= 0 ? q : 0];
+    const T* tb = tables + int64_t(kk) * kSlots * kSlots;
+    T m[kSlots];
+#pragma unroll
+    for (int t = 0; t < kSlots; ++t) m[t] = tb[t * kSlots + s];
+    s_r[w][lane] = (active && lane < kSlots && q >= 0) ? rv : T(0);
+    __syncthreads();
+    T a0 = 0, a1 = 0;
+#pragma unroll
+    for (int t = 0; t + 1 < kSlots; t += 2) {
+        a0 += m[t] * s_r[w][t];
+        a1 += m[t + 1] * s_r[w][t + 1];
+    }
+    a0 += m[kSlots - 1] * s_r[w][kSlots - 1];
+    if (active && lane < kSlots) dbuf[int64_t(k) * 64 + lane] = a0 + a1;
+}
+
 // Tile grid and the XCD-aware tile order: consecutive workgroup ids are
 // dealt round-robin to the 8 XCDs, so id L takes tile (L mod 8) ceil(T/8) +
 // L/8 in row-major order, giving every XCD a contiguous band of tiles whose
@@ -762,7 +850,9 @@ __device__ __forceinline__ void owner_update_velocity(const Geom& g, const T* __
 // x_in == nullptr meaning x_in = 0.  Every DoF a tile owns is written
 // (Dirichlet DoFs keep x_in).  The interior operator is applied to the
 // residual scaled by omega/nu (pressure also by t = nu/h), see sym_apply.
-template <typename T>
+// SIMPLE: every patch correction comes from dbuf (vanka_patch_kernel, patch
+// k = J*(N+1) + I) instead of the interior operator and the boundary kernel.
+template <typename T, bool SIMPLE = false>
 __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __restrict__ rb,
                                                              const T* xin, T* xout,
                                                              const T* __restrict__ dbuf, T scale,
@@ -781,34 +871,39 @@ __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __
         rb += bo;
         if (xin) xin += bo;
         xout += bo;
-        dbuf += int64_t(blockIdx.y) * n_boundary_patches(g.N) * 64;
+        dbuf += int64_t(blockIdx.y) * (SIMPLE ? (g.N + 1) * (g.N + 1) : n_boundary_patches(g.N)) * 64;
     }
     const int E0x = (tlin % tiles) * VT, E0y = (tlin / tiles) * VT;
     const int tx = threadIdx.x % VP, ty = threadIdx.x / VP;
     const int I = E0x - 1 + tx, J = E0y - 1 + ty;
     const bool valid = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
 
-    stage_residual_region(g, rb, E0x, E0y, scale, t, sr0, sr1, srp);
-    __syncthreads();
-
     T rv[kSlots];
+    if (SIMPLE) {
+        const int64_t bi = valid ? int64_t(J) * (g.N + 1) + I : 0;
 #pragma unroll
-    for (int b = 0; b < 5; ++b)
+        for (int s = 0; s < kSlots; ++s) rv[s] = valid ? dbuf[bi * 64 + s] : T(0);
+    } else {
+        stage_residual_region(g, rb, E0x, E0y, scale, t, sr0, sr1, srp);
+        __syncthreads();
 #pragma unroll
-        for (int a = 0; a < 5; ++a) {
-            const int l = (2 * ty + b) * VR + 2 * tx + a;
-            rv[5 * b + a] = sr0[l];
-            rv[25 + 5 * b + a] = sr1[l];
-        }
-    rv[50] = srp[ty * VR1 + tx];
+        for (int b = 0; b < 5; ++b)
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                const int l = (2 * ty + b) * VR + 2 * tx + a;
+                rv[5 * b + a] = sr0[l];
+                rv[25 + 5 * b + a] = sr1[l];
+            }
+        rv[50] = srp[ty * VR1 + tx];
 
-    sym_apply(rv, t);  // interior operator, every lane
-    const bool interior = valid && I >= 2 && J >= 2 && I <= g.N - 2 && J <= g.N - 2;
-    if (!interior) {
-        // boundary patch: corrections precomputed; outside the domain: none
-        const int bi = valid ? boundary_index(I, J, g.N) : 0;
+        sym_apply(rv, t);  // interior operator, every lane
+        const bool interior = valid && I >= 2 && J >= 2 && I <= g.N - 2 && J <= g.N - 2;
+        if (!interior) {
+            // boundary patch: corrections precomputed; outside the domain: none
+            const int bi = valid ? boundary_index(I, J, g.N) : 0;
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) rv[s] = valid ? dbuf[int64_t(bi) * 64 + s] : T(0);
+            for (int s = 0; s < kSlots; ++s) rv[s] = valid ? dbuf[int64_t(bi) * 64 + s] : T(0);
+        }
     }
     __syncthreads();  // the staging buffers are reused for the exchange below
 
@@ -1681,18 +1776,24 @@ int elementwise_blocks(int64_t n) {
 
 template <typename Tx, typename T>
 void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hipStream_t s,
-                     int nb) {
+                     int nb, const T* nue) {
     const int tiles = (g.N + 1 + RT - 1) / RT;
     const dim3 grid(8 * ((tiles * tiles + 7) / 8), nb);
-    if (mode == 0)
+    if (nue) {
+        if (mode == 0)
+            residual_kernel<0, Tx, T, true><<<grid, RNT, 0, s>>>(g, b, x, r, nue);
+        else
+            residual_kernel<1, Tx, T, true><<<grid, RNT, 0, s>>>(g, b, x, r, nue);
+    } else if (mode == 0) {
         residual_kernel<0, Tx, T><<<grid, RNT, 0, s>>>(g, b, x, r);
-    else
+    } else {
         residual_kernel<1, Tx, T><<<grid, RNT, 0, s>>>(g, b, x, r);
+    }
 }
 template void launch_residual<double, double>(const Geom&, const double*, const double*, double*,
-                                              int, hipStream_t, int);
+                                              int, hipStream_t, int, const double*);
 template void launch_residual<float, float>(const Geom&, const float*, const float*, float*, int,
-                                            hipStream_t, int);
+                                            hipStream_t, int, const float*);
 
 void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hipStream_t s,
                 int nb) {
@@ -1733,6 +1834,20 @@ void launch_pressure_mean_zero(const Geom& g, double* x, double* part, double* s
     reduce_partials_kernel<<<dim3(1, nb), 256, 0, s>>>(part, kBlocks, sums, so);
     pressure_shift_kernel<<<dim3(kBlocks, nb), 256, 0, s>>>(g, x, sums, so);
 }
+
+template <typename T>
+void launch_vanka_simple(const Geom& g, const T* r, const T* xin, T* xout, const T* tables,
+                         T* dbuf, hipStream_t s, int nb) {
+    const int np = (g.N + 1) * (g.N + 1);
+    vanka_patch_kernel<T><<<dim3((np + 3) / 4, nb), 256, 0, s>>>(g, r, tables, dbuf);
+    const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
+    const dim3 grid(8 * ((ntile + 7) / 8), nb);
+    vanka_sweep_kernel<T, true><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf, T(0), T(0));
+}
+template void launch_vanka_simple<double>(const Geom&, const double*, const double*, double*,
+                                          const double*, double*, hipStream_t, int);
+template void launch_vanka_simple<float>(const Geom&, const float*, const float*, float*,
+                                         const float*, float*, hipStream_t, int);
 
 int64_t vanka_boundary_scratch(int N) { return int64_t(n_boundary_patches(N)) * 64; }
 

@@ -37,6 +37,10 @@ int class_representative(int c, int N);
 // Patch matrix of class `cls` (51x51 row-major, absent slots identity).
 // Returns false if the arguments are out of range.
 bool patch_matrix(int N, double nu, int cls, double* A, uint8_t* present);
+// Patch matrix of the patch at Q1 node (I, J); per-element viscosity
+// nu_elem (N^2 values, index ey*N + ex) or, if NULL, the constant nu.
+void patch_matrix_at(int N, const double* nu_elem, double nu, int I, int J, double* A,
+                     uint8_t* present);
 
 // In-place Gauss-Jordan inversion with partial pivoting; false if singular.
 bool invert_dense(int n, std::vector<double>& A, std::vector<double>& Ainv);
@@ -45,13 +49,21 @@ bool invert_dense(int n, std::vector<double>& A, std::vector<double>& Ainv);
 // slots, zero for Dirichlet and absent slots.
 void weighted_inverse(int N, int cls, double omega, const double* Ainv, const uint8_t* present,
                       double* W);
+void weighted_inverse_at(int N, int I, int J, double omega, const double* Ainv,
+                         const uint8_t* present, double* W);
+// Transposed weighted inverses of all (N+1)^2 patches for a per-element
+// viscosity (51*51 values per patch, patch k = J*(N+1) + I); false if a
+// patch matrix is singular.
+bool simple_vanka_tables(int N, const double* nu_elem, double omega, double* out);
 
 // Dense constrained operator of the whole level (n x n, row-major).
-void assemble_dense_level(int N, double nu, std::vector<double>& A);
+void assemble_dense_level(int N, double nu, std::vector<double>& A,
+                          const double* nu_elem = nullptr);
 
 // Top-left n x n block of the inverse of the matrix bordered by the
 // constant-pressure vector; false if singular.
-bool coarse_bordered_inverse(int N, double nu, std::vector<double>& C);
+bool coarse_bordered_inverse(int N, double nu, std::vector<double>& C,
+                             const double* nu_elem = nullptr);
 
 // Block-diagonal form of the interior weighted inverse W in the reflection-
 // adapted coordinates of symmetry.h (651 values, blocks concatenated

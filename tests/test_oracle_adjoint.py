@@ -5,7 +5,7 @@ quadratic in f, so central differences are exact up to rounding."""
 import numpy as np
 
 from oracle import adjoint
-from stokes_inputs import gaussian_random_field, grid_sizes, uniform_vector
+from stokes_inputs import gaussian_random_field, grid_sizes, log_viscosity_field, uniform_vector
 
 
 def test_force_gradient_matches_central_differences():
@@ -38,3 +38,26 @@ def test_pressure_projection_removes_the_null_space_component():
     g2 = g.copy()
     g2[gs.off_p:] += 3.0
     assert np.allclose(adjoint.force_gradient(N, g), adjoint.force_gradient(N, g2), atol=1e-12)
+
+
+def test_viscosity_gradient_matches_central_differences():
+    """The loss is not quadratic in nu: central differences with a small
+    relative step (error O(eps^2))."""
+    N = 6
+    gs = grid_sizes(N)
+    f = gaussian_random_field(N, 3, length=0.3)
+    nu = np.exp(log_viscosity_field(N, 7))
+    xt = uniform_vector(gs.n, 4)
+
+    def loss(v):
+        x = adjoint.solve(N, f, nu=v)
+        return 0.5 * float(np.sum((x - xt) ** 2))
+
+    x = adjoint.solve(N, f, nu=nu)
+    grad = adjoint.viscosity_gradient(N, x - xt, x, nu)
+    rng = np.random.default_rng(8)
+    for _ in range(5):
+        d = rng.standard_normal(nu.shape) * nu
+        eps = 1e-4
+        fd = (loss(nu + eps * d) - loss(nu - eps * d)) / (2 * eps)
+        assert abs(fd - float(grad @ d)) <= 1e-6 * abs(fd)

@@ -215,6 +215,17 @@ vkmg_status vkmg_assemble_rhs_adjoint(vkmg_ctx* ctx, const double* lam, double* 
                                       void* stream);
 
 /*
+ * Gradient of a loss with respect to a per-element viscosity, from the
+ * adjoint state lam (A lam = P dL/dx) and the solution x: grad_nu[e] =
+ * -sum over both velocity components of lam_e^T L_e x_e on the free nodes
+ * of element e (L_e the Q2 element Laplacian per unit viscosity; the
+ * derivative of A with respect to nu_e).  lam, x: n doubles; grad_nu: nx*nx
+ * doubles (index ey*nx + ex); FP64, finest level.  Asynchronous.
+ */
+vkmg_status vkmg_viscosity_gradient(vkmg_ctx* ctx, const double* lam, const double* x,
+                                    double* grad_nu, void* stream);
+
+/*
  * x_p -= mean(x_p): removes the constant-pressure null-space component of an
  * FP64 finest-level vector (plain mean over the (N+1)^2 pressure DoFs; an
  * orthogonal projection, so it is its own adjoint).  Asynchronous.

@@ -36,6 +36,7 @@ EXPORTED = [
     "vkmg_default_options", "vkmg_setup", "vkmg_setup_viscosity", "vkmg_destroy", "vkmg_layout_of", "vkmg_level_layout",
     "vkmg_num_levels", "vkmg_residual", "vkmg_apply", "vkmg_assemble_rhs", "vkmg_vanka_sweep",
     "vkmg_vanka_update", "vkmg_relax", "vkmg_assemble_rhs_adjoint", "vkmg_remove_pressure_mean",
+    "vkmg_viscosity_gradient",
     "vkmg_restrict", "vkmg_prolong_add", "vkmg_coarse_solve", "vkmg_vcycle",
     "vkmg_fgmres_solve", "vkmg_set_timing", "vkmg_kernel_timing", "vkmg_host_patch_matrix",
     "vkmg_status_string", "vkmg_last_error",
@@ -109,6 +110,7 @@ def load_library(path: str = LIB_PATH):
         "vkmg_relax": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_assemble_rhs_adjoint": (c_int32, [P, P, P, P]),
         "vkmg_remove_pressure_mean": (c_int32, [P, P, P]),
+        "vkmg_viscosity_gradient": (c_int32, [P, P, P, P, P]),
         "vkmg_restrict": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_prolong_add": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_coarse_solve": (c_int32, [P, P, P, P]),
@@ -190,6 +192,7 @@ class VkmgSolver:
                                           arr.ctypes.data_as(c_void_p), byref(opts),
                                           self._stream(), byref(ctx))
             _check(st, "vkmg_setup_viscosity")
+        self.nu_elem = None if nu_elem is None else arr
         self._ctx = ctx
         self.N, self.levels, self.nu, self.batch = N, levels, nu, batch
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -304,6 +307,18 @@ class VkmgSolver:
             self._ptr(grad_f, self._torch.float64, lay["n_vel"] * nb, "grad_f"), self._stream())
         _check(st, "vkmg_assemble_rhs_adjoint")
         return grad_f
+
+    def viscosity_gradient(self, lam, x, grad_nu=None):
+        """-lam_e^T L_e x_e per element (N*N values per right-hand side)."""
+        n = self.layout["n"] * self.batch
+        ne = self.N * self.N * self.batch
+        grad_nu = self._empty(ne, self._torch.float64) if grad_nu is None else grad_nu
+        st = _lib.vkmg_viscosity_gradient(
+            self._ctx, self._ptr(lam, self._torch.float64, n, "lam"),
+            self._ptr(x, self._torch.float64, n, "x"),
+            self._ptr(grad_nu, self._torch.float64, ne, "grad_nu"), self._stream())
+        _check(st, "vkmg_viscosity_gradient")
+        return grad_nu
 
     def remove_pressure_mean(self, x):
         """In place: subtract the mean of the pressure block (per right-hand side)."""

@@ -941,6 +941,16 @@ vkmg_status vkmg_assemble_rhs_adjoint(vkmg_ctx* ctx, const double* lam, double* 
     return VKMG_OK;
 }
 
+vkmg_status vkmg_viscosity_gradient(vkmg_ctx* ctx, const double* lam, const double* x,
+                                    double* grad_nu, void* stream) {
+    if (!ctx || !lam || !x || !grad_nu)
+        return fail(VKMG_ERR_INVALID_ARG, "viscosity_gradient: NULL argument");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    launch_visc_grad(ctx->top(), lam, x, grad_nu, as_stream(stream), ctx->nb());
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
 vkmg_status vkmg_remove_pressure_mean(vkmg_ctx* ctx, double* x, void* stream) {
     if (!ctx || !x) return fail(VKMG_ERR_INVALID_ARG, "remove_pressure_mean: NULL argument");
     VKMG_HIP(hipSetDevice(ctx->device));

@@ -31,6 +31,10 @@ void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hip
 // to lam (n values per right-hand side; its velocity block is read on free
 // nodes); grad_f: 2 (2N+1)^2 values per right-hand side.
 void launch_rhs_adjoint(const Geom& g, const double* lam, double* grad, hipStream_t s, int nb = 1);
+// grad[e] = -sum_c lam_{c,e}^T L_e x_{c,e} over the free Q2 nodes of element e
+// (N^2 values per right-hand side, index ey*N + ex).
+void launch_visc_grad(const Geom& g, const double* lam, const double* x, double* grad,
+                      hipStream_t s, int nb = 1);
 // x_p -= mean(x_p) on every right-hand side (FP64): partial sums in part
 // (256 per entry), the sums at sums[entry * so].
 void launch_pressure_mean_zero(const Geom& g, double* x, double* part, double* sums, int64_t so,

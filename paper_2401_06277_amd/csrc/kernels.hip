@@ -1366,6 +1366,45 @@ __global__ __launch_bounds__(256) void rhs_adjoint_kernel(Geom g, const double* 
     grad[g.nq2 + q] = cm * sy;
 }
 
+// Gradient with respect to a per-element viscosity:
+// grad(e) = -sum over both components of lam_e^T L_e x_e on the free Q2
+// nodes of element e (L_e the element Laplacian per unit viscosity, 9 x 9).
+// One thread per element; batched over blockIdx.y (lam, x by g.n, grad by
+// N^2).
+__global__ __launch_bounds__(256) void visc_grad_kernel(Geom g, const double* __restrict__ lam,
+                                                        const double* __restrict__ x,
+                                                        double* __restrict__ grad) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= g.N * g.N) return;
+    lam += int64_t(blockIdx.y) * g.n;
+    x += int64_t(blockIdx.y) * g.n;
+    grad += int64_t(blockIdx.y) * g.N * g.N;
+    const int ex = e % g.N, ey = e / g.N;
+    double lv[2][9], xv[2][9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int qi = 2 * ex + k % 3, qj = 2 * ey + k / 3;
+        const bool free = qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
+        const int64_t q = int64_t(qj) * g.s2 + qi;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            lv[c][k] = free ? lam[c * g.nq2 + q] : 0.0;
+            xv[c][k] = free ? x[c * g.nq2 + q] : 0.0;
+        }
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+            const int a = k % 3, b = k / 3, c = m % 3, d = m / 3;
+            const int co = kEM[b][d] * kEK[a][c] + kEK[b][d] * kEM[a][c];
+            if (co == 0) continue;
+            sum += double(co) * (lv[0][k] * xv[0][m] + lv[1][k] * xv[1][m]);
+        }
+    grad[e] = -sum / 90.0;
+}
+
 // Sum of the pressure block of every batch entry: partial sums per block
 // (part[entry * G + blk], G = gridDim.x).
 __global__ __launch_bounds__(256) void pressure_sum_kernel(Geom g, const double* __restrict__ x,
@@ -1825,6 +1864,12 @@ template void launch_bs_relax<float>(const Geom&, const float*, const float*, fl
 void launch_rhs_adjoint(const Geom& g, const double* lam, double* grad, hipStream_t s, int nb) {
     const dim3 grid((g.s2 + 63) / 64, nb, (g.s2 + 3) / 4);
     rhs_adjoint_kernel<<<grid, 256, 0, s>>>(g, lam, grad);
+}
+
+void launch_visc_grad(const Geom& g, const double* lam, const double* x, double* grad,
+                      hipStream_t s, int nb) {
+    const int ne = g.N * g.N;
+    visc_grad_kernel<<<dim3((ne + 255) / 256, nb), 256, 0, s>>>(g, lam, x, grad);
 }
 
 void launch_pressure_mean_zero(const Geom& g, double* x, double* part, double* sums, int64_t so,

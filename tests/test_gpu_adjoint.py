@@ -134,3 +134,41 @@ def test_batched_force_gradient_equals_single():
         assert np.linalg.norm(gb - host(fs.grad)) <= 1e-8 * np.linalg.norm(host(fs.grad))
     sb.close()
     s1.close()
+
+
+def test_viscosity_gradient_matches_oracle_and_central_differences():
+    from stokes_inputs import log_viscosity_field
+    N, levels = 16, 3
+    nu = np.exp(log_viscosity_field(N, 7))
+    f, xt = _problem(N)
+    s = vk.VkmgSolver(N, levels, nu_elem=nu)
+    fd = dev(f.ravel()).requires_grad_(True)
+    nud = dev(nu).requires_grad_(True)
+    x = stokes_solve(fd, s, nu=nud, rtol=1e-12)
+    loss = 0.5 * torch.sum((x - dev(xt)) ** 2)
+    loss.backward()
+    gnu = host(nud.grad)
+    xo = adjoint.solve(N, f, nu=nu)
+    assert np.linalg.norm(host(x) - xo) <= 1e-9 * np.linalg.norm(xo)
+    g_or = adjoint.viscosity_gradient(N, xo - xt, xo, nu)
+    assert np.linalg.norm(gnu - g_or) <= 1e-6 * np.linalg.norm(g_or)
+    gf_or = adjoint.force_gradient(N, xo - xt, nu=nu).ravel()
+    assert np.linalg.norm(host(fd.grad) - gf_or) <= 1e-6 * np.linalg.norm(gf_or)
+    s.close()
+    # central differences in log-viscosity directions (new setups per point)
+    rng = np.random.default_rng(8)
+    xt_d = dev(xt)
+
+    def L(v):
+        sv = vk.VkmgSolver(N, levels, nu_elem=v)
+        with torch.no_grad():
+            val = float(0.5 * torch.sum((stokes_solve(dev(f.ravel()), sv, rtol=1e-12) - xt_d) ** 2))
+        sv.close()
+        return val
+
+    for _ in range(20):
+        d = rng.standard_normal(nu.shape) * nu
+        eps = 1e-4
+        fdiff = (L(nu + eps * d) - L(nu - eps * d)) / (2 * eps)
+        an = float(gnu @ d)
+        assert abs(fdiff - an) <= 1e-6 * abs(an), (fdiff, an)

@@ -82,6 +82,8 @@ def parse():
                     help="skip the Braess-Sarazin comparison solves")
     ap.add_argument("--skip-adjoint", action="store_true",
                     help="skip the forward + adjoint (gradient) timing")
+    ap.add_argument("--skip-c5", action="store_true",
+                    help="skip the 256x256 per-element viscosity solves and gradients")
     ap.add_argument("--interior-apply", choices=["vector", "matrix"], default="vector",
                     help="interior Vanka apply: vector ALUs (default) or matrix cores")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -399,6 +401,61 @@ def bench_adjoint(a, vk, torch, fd, N, L):
             "grad_norm": float(torch.linalg.norm(f.grad))}
 
 
+def bench_c5(a, vk, torch, np):
+    """256 x 256, 6 levels, per-element viscosity log nu_e ~ U[-1,1] (seed 7):
+    setup (per-patch inverses on the host threads), FGMRES solve to 1e-8
+    with "simple" Vanka (one stored inverse per patch), and the gradient of
+    L = |x - x_t|^2 / 2 (x_t: GRF seed 6 on the velocity) with respect to the
+    force and the viscosity (forward + adjoint); the constant-viscosity
+    solve of the same problem for comparison."""
+    from paper_2401_06277_amd.autograd import stokes_solve
+    from stokes_inputs import gaussian_random_field, log_viscosity_field
+
+    N5, L5 = 256, 6
+    nu = np.exp(log_viscosity_field(N5, 7))
+    f = torch.from_numpy(np.ascontiguousarray(gaussian_random_field(N5, 5).ravel())).cuda()
+    xt = torch.from_numpy(np.ascontiguousarray(np.concatenate(
+        [gaussian_random_field(N5, 6).ravel(), np.zeros((N5 + 1) ** 2)]))).cuda() * 0.01
+    res = {"config": "256x256 elements, 6 levels, log nu_e ~ U[-1,1] (seed 7), GRF force (seed 5), "
+                     "FGMRES(30) + V(2,2) simple Vanka omega=0.5, rtol 1e-8; loss |x - x_t|^2/2"}
+    for label, kw in (("variable_nu", {"nu_elem": nu}), ("constant_nu", {})):
+        log(f"[bench] 256x256 {label}")
+        t0 = time.perf_counter()
+        s = vk.VkmgSolver(N5, L5, **kw)
+        setup = time.perf_counter() - t0
+        b = s.assemble_rhs(f)
+        x = torch.zeros_like(b)
+        s.fgmres_solve(b, x, rtol=1e-8)
+        ts = []
+        for _ in range(max(a.steps, 2)):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.fgmres_solve(b, x, rtol=1e-8)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        res[label] = {"setup_s": setup, "time_to_1e8_s": ts[len(ts) // 2],
+                      "iterations": info["iterations"], "true_rel_res": info["true_rel_res"]}
+        if label == "variable_nu":
+            nud = torch.from_numpy(nu).cuda()
+            tg = []
+            for k in range(3):
+                fd = f.clone().requires_grad_(True)
+                nv = nud.clone().requires_grad_(True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                xs = stokes_solve(fd, s, nu=nv, rtol=1e-8)
+                (0.5 * torch.sum((xs - xt) ** 2)).backward()
+                torch.cuda.synchronize()
+                if k > 0:
+                    tg.append(time.perf_counter() - t0)
+            res[label]["forward_backward_s"] = min(tg)
+            res[label]["grad_nu_norm"] = float(torch.linalg.norm(nv.grad))
+        s.close()
+    return res
+
+
 def main():
     a = parse()
     if a.copy_calibration_mib:
@@ -574,6 +631,9 @@ def main():
         out["adjoint_force_gradient"] = bench_adjoint(a, vk, torch, fd, N, L)
         out["adjoint_force_gradient"]["over_forward_solve"] = (
             out["adjoint_force_gradient"]["time_s"] / out["time_to_1e8_s"])
+
+    if not a.skip_c5:
+        out["c5_256_variable_viscosity"] = bench_c5(a, vk, torch, np)
 
     if not a.skip_c4:
         out["c4_512_batched"] = bench_c4(a, vk, torch, np)

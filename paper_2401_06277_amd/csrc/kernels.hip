@@ -565,11 +565,12 @@ __global__ __launch_bounds__(BNT) void bs_grad_kernel(Geom g, const T* dp, const
 // reproducible.
 //
 // Interior patches (distance >= 2 from the boundary) share one inverse,
-// applied in the reflection-adapted block form (symmetry.h: 651
-// multiply-adds instead of 2601) with coefficients read through the scalar
-// cache.  The O(N) boundary patches (24 other classes) are solved first by
-// vanka_boundary_kernel, one wavefront per patch, into a side buffer that
-// the tile kernel reads.
+// applied in the coordinates of the symmetry group of the square
+// (d4_apply.h: 495 multiply-adds on compile-time constants instead of
+// 2601).  The O(N) boundary patches (24 other classes) are solved first by
+// vanka_boundary_kernel into a side buffer that the tile kernel reads; with
+// a per-element viscosity every patch is solved that way
+// (vanka_patch_kernel, one stored inverse per patch).
 //
 // Summation of the corrections: a patch with its lower-left window corner
 // at Q2 column 2tx-4 (tile coordinates) sends slot a to column 2tx-4+a, so

@@ -144,3 +144,16 @@ def test_bs_batched_vcycle_equals_single_bitwise():
         assert np.array_equal(zb[k], host(s1.vcycle(dev(rs[k]))))
     sb.close()
     s1.close()
+
+
+def test_bs_fp32_multigrid_fgmres_reaches_fp64_tolerance():
+    N, levels = 32, 4
+    s = _solver(N, levels, PARAMS[0], precision="fp32")
+    gd = manufactured_boundary_values(N, "trig")
+    A, b, _, xl = fem.stokes_system(N, 1.0, f_nodal=manufactured_nodal_force(N, "trig"),
+                                    g_nodal=gd)
+    x = dev(xl)
+    info = s.fgmres_solve(dev(b), x, rtol=1e-8, restart=30, max_iters=200)
+    assert info["status_name"] == "VKMG_OK"
+    assert np.linalg.norm(b - A @ host(x)) <= 1.01e-8 * np.linalg.norm(b - A @ xl)
+    s.close()

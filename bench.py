@@ -131,6 +131,18 @@ def cpu_baseline(N, levels, nvc, c2=None):
     ups = H.patch_updates_per_cycle() * nvc / dt
     blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     extra = {}
+    # the same V-cycles on one thread (the paper's CPU runs are serial)
+    from threadpoolctl import threadpool_limits
+    n1 = max(nvc // 6, 3)
+    with threadpool_limits(limits=1):
+        H.vcycle(b)
+        t0 = time.perf_counter()
+        for _ in range(n1):
+            H.vcycle(b)
+        dt1 = time.perf_counter() - t0
+    extra["single_thread"] = {"value": H.patch_updates_per_cycle() * n1 / dt1,
+                              "unit": "patch-updates/s", "cores": 1,
+                              "sample": f"{n1} V(2,2) cycles at {N}x{N}, BLAS limited to 1 thread"}
     if c2 is not None and N == 256:
         from oracle import fgmres
         from stokes_inputs import manufactured_boundary_values, manufactured_nodal_force

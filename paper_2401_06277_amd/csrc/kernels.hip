@@ -846,6 +846,66 @@ __device__ __forceinline__ void owner_update_velocity(const Geom& g, const T* __
         }
 }
 
+// The same update with its loads issued early: owner_prefetch at the start
+// of the kernel (the loads are in flight during the patch solves; DoFs are
+// owned by one workgroup, so reading x_in first is safe in place too), then
+// owner_commit after the exchange.
+template <typename T>
+struct OwnerBase {
+    T v[2][2][2];
+    T p;
+};
+
+template <typename T>
+__device__ __forceinline__ void owner_prefetch(const Geom& g, int E0x, int E0y, const T* xin,
+                                               OwnerBase<T>& ob) {
+    const int tx = threadIdx.x % VP, ty = threadIdx.x / VP;
+    const bool own = tx < VT && ty < VT;
+    const int gi0 = 2 * E0x + 2 * tx, gj0 = 2 * E0y + 2 * ty;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int px = 0; px < 2; ++px)
+#pragma unroll
+            for (int py = 0; py < 2; ++py) {
+                const int gi = gi0 + px, gj = gj0 + py;
+                const bool in = own && gi < g.s2 && gj < g.s2;
+                const int64_t q = in ? int64_t(c) * g.nq2 + int64_t(gj) * g.s2 + gi : 0;
+                ob.v[c][px][py] = xin ? xin[q] : T(0);
+            }
+    // owned pressure: Q1 node (E0 - 1 + tx, E0 - 1 + ty) for 1 <= tx, ty <= VT
+    const int I = E0x - 1 + tx, J = E0y - 1 + ty;
+    const bool pin = tx >= 1 && ty >= 1 && tx <= VT && ty <= VT && I <= g.N && J <= g.N;
+    ob.p = xin ? xin[2 * g.nq2 + (pin ? int64_t(J) * g.s1 + I : 0)] : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ void owner_commit(const Geom& g, const T* __restrict__ xs, int E0x,
+                                             int E0y, const OwnerBase<T>& ob, T* xout) {
+    const int tx = threadIdx.x % VP, ty = threadIdx.x / VP;
+    if (tx >= VT || ty >= VT) return;
+    const int gi0 = 2 * E0x + 2 * tx, gj0 = 2 * E0y + 2 * ty;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int px = 0; px < 2; ++px) {
+            auto at = [&](int b, int dty) {
+                return xs[((b * 2 + c) * 2 + px) * VNT + threadIdx.x + dty * VP];
+            };
+            const T even_row = at(4, 0) + at(2, 1) + at(0, 2);
+            const T odd_row = at(3, 1) + at(1, 2);
+            const int gi = gi0 + px;
+#pragma unroll
+            for (int py = 0; py < 2; ++py) {
+                const int gj = gj0 + py;
+                if (gi >= g.s2 || gj >= g.s2) continue;
+                const int64_t q = int64_t(c) * g.nq2 + int64_t(gj) * g.s2 + gi;
+                const bool free = gi > 0 && gj > 0 && gi < g.s2 - 1 && gj < g.s2 - 1;
+                xout[q] = free ? ob.v[c][px][py] + (py ? odd_row : even_row) : ob.v[c][px][py];
+            }
+        }
+}
+
 // One additive Vanka sweep on a tile given the residual r (`rb`) of x_in:
 // x_out = x_in + corrections, with x_in == x_out allowed (in place) and
 // x_in == nullptr meaning x_in = 0.  Every DoF a tile owns is written
@@ -875,6 +935,8 @@ __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __
         dbuf += int64_t(blockIdx.y) * (SIMPLE ? (g.N + 1) * (g.N + 1) : n_boundary_patches(g.N)) * 64;
     }
     const int E0x = (tlin % tiles) * VT, E0y = (tlin / tiles) * VT;
+    OwnerBase<T> ob;
+    owner_prefetch(g, E0x, E0y, xin, ob);
     const int tx = threadIdx.x % VP, ty = threadIdx.x / VP;
     const int I = E0x - 1 + tx, J = E0y - 1 + ty;
     const bool valid = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
@@ -923,10 +985,10 @@ __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __
             xs[base + VNT + threadIdx.x] = od;
         }
     __syncthreads();
-    owner_update_velocity(g, xs, E0x, E0y, xin, xout);
+    owner_commit(g, xs, E0x, E0y, ob, xout);
     if (valid && tx >= 1 && tx <= VT && ty >= 1 && ty <= VT) {
         const int64_t q = 2 * g.nq2 + int64_t(J) * g.s1 + I;
-        xout[q] = (xin ? xin[q] : T(0)) + rv[50];
+        xout[q] = ob.p + rv[50];
     }
 }
 

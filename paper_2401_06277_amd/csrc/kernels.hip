@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <type_traits>
 
 #include "kernels.h"
 #include "stencil.h"
@@ -598,6 +599,144 @@ __device__ __forceinline__ void sym_apply(T (&v)[kSlots], T t) {
     d4_apply(v, t, InteriorD4{});
 }
 
+// Keeps the compiler from carrying a value across an LDS round trip in
+// registers, and the scheduler from moving any instruction across this point.
+__device__ __forceinline__ void lds_order() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+// Makes the value exist in a register at this point of the instruction
+// stream (so its computation cannot sink below a following lds_order).
+template <typename T>
+__device__ __forceinline__ void pin(T& a) {
+    asm volatile("" : "+v"(a));
+}
+
+// sym_apply with the same arithmetic in the same order, but with at most 26
+// of the 51 patch values in registers at a time: the inputs of blocks 0 and 3
+// wait in LDS while blocks 1 and 2 are formed, and the outputs of blocks 1
+// and 2 while blocks 0 and 3 are.  `park` is this lane's column of a
+// [26][VNT] LDS area that no other lane touches.
+constexpr int kPark = 26;
+// FP64 tile kernel with parking (160 VGPRs, three waves per SIMD, 52 KiB of
+// LDS) on levels with at least this many elements per side; below, where a
+// launch is one or two waves per SIMD, the extra LDS round trips and barrier
+// lengthen each wave and the two-wave form (229 VGPRs) is faster.
+constexpr int kParkMinN = 512;
+template <typename T>
+__device__ __forceinline__ void sym_apply_parked(T (&v)[kSlots], T t, T* park) {
+    const D4Table& d = kD4Table;
+    const InteriorD4 coef{};
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+#pragma unroll
+        for (int b = 0; b < 5; ++b) d4_bfly(v, 25 * f + 5 * b, 1);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) d4_bfly(v, 25 * f + q, 5);
+    }
+    // inputs of blocks 0 (pressure, pairs a0/b0) and 3 (pairs a3/b3)
+    park[0] = v[50];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        park[(1 + k) * VNT] = v[d.a0[k]];
+        park[(7 + k) * VNT] = v[d.b0[k]];
+        park[(13 + k) * VNT] = v[d.a3[k]];
+        park[(19 + k) * VNT] = v[d.b3[k]];
+    }
+    lds_order();
+    // blocks 1 and 2: one set of constants, each used twice
+    T y1[13], y2[13];
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        T a1 = 0, a2 = 0;
+#pragma unroll
+        for (int k = 0; k < 13; ++k) {
+            const T c = T(coef(kD4Off1 + i * 13 + k));
+            a1 += c * v[d.m1[k]];
+            a2 += c * v[d.m2[k]];
+        }
+        y1[i] = a1;
+        y2[i] = a2;
+    }
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        pin(y1[i]);
+        pin(y2[i]);
+    }
+    lds_order();
+    v[50] = park[0];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        v[d.a0[k]] = park[(1 + k) * VNT];
+        v[d.b0[k]] = park[(7 + k) * VNT];
+        v[d.a3[k]] = park[(13 + k) * VNT];
+        v[d.b3[k]] = park[(19 + k) * VNT];
+    }
+    lds_order();
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        park[i * VNT] = y1[i];
+        park[(13 + i) * VNT] = y2[i];
+    }
+    lds_order();
+    // block 0: even (p and pair sums) and odd (pair differences) parts
+    {
+        T e[7], o[6], ye[7], yo[6];
+        e[0] = v[50];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            e[k + 1] = v[d.a0[k]] + v[d.b0[k]];
+            o[k] = v[d.a0[k]] - v[d.b0[k]];
+        }
+        d4_block(e, ye, kD4Off0e, coef);
+        d4_block(o, yo, kD4Off0o, coef);
+        v[50] = ye[0];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            v[d.a0[k]] = ye[k + 1] + yo[k];
+            v[d.b0[k]] = ye[k + 1] - yo[k];
+        }
+    }
+    // block 3: pair sums and differences
+    {
+        T e[6], o[6], ye[6], yo[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            e[k] = v[d.a3[k]] + v[d.b3[k]];
+            o[k] = v[d.a3[k]] - v[d.b3[k]];
+        }
+        d4_block(e, ye, kD4Off3e, coef);
+        d4_block(o, yo, kD4Off3o, coef);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            v[d.a3[k]] = ye[k] + yo[k];
+            v[d.b3[k]] = ye[k] - yo[k];
+        }
+    }
+    v[50] *= t;
+    pin(v[50]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        pin(v[d.a0[k]]);
+        pin(v[d.b0[k]]);
+        pin(v[d.a3[k]]);
+        pin(v[d.b3[k]]);
+    }
+    lds_order();
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        v[d.m1[i]] = park[i * VNT];
+        v[d.m2[i]] = park[(13 + i) * VNT];
+    }
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) d4_bfly_t(v, 25 * f + q, 5);
+#pragma unroll
+        for (int b = 0; b < 5; ++b) d4_bfly_t(v, 25 * f + 5 * b, 1);
+    }
+}
+
 // Value of lane (l + S) of the same 16-lane row, 0 past the row end
 // (DPP row_shl; the 64-bit value moves as two 32-bit halves).
 template <int S>
@@ -767,6 +906,7 @@ constexpr int VR1 = VT + 2;
 constexpr int kRRegion = 2 * VR * VR + VR1 * VR1;
 constexpr int kExchange = 20 * VNT;
 constexpr int kSweepLds = (kRRegion > kExchange) ? kRRegion : kExchange;
+constexpr int kSweepLdsPark = (kSweepLds > kPark * VNT) ? kSweepLds : kPark * VNT;
 
 // Stage the scaled residual of a tile's r region in LDS (velocity scaled
 // by `scale`, pressure by `scale * t`, nodes outside the mesh zero).  All
@@ -913,12 +1053,14 @@ __device__ __forceinline__ void owner_commit(const Geom& g, const T* __restrict_
 // residual scaled by omega/nu (pressure also by t = nu/h), see sym_apply.
 // SIMPLE: every patch correction comes from dbuf (vanka_patch_kernel, patch
 // k = J*(N+1) + I) instead of the interior operator and the boundary kernel.
-template <typename T, bool SIMPLE = false>
-__global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __restrict__ rb,
+// PARK: the interior operator through sym_apply_parked (same results), for
+// three waves per SIMD instead of two.
+template <typename T, bool SIMPLE = false, bool PARK = false>
+__global__ __launch_bounds__(VNT, PARK ? 3 : 2) void vanka_sweep_kernel(Geom g, const T* __restrict__ rb,
                                                              const T* xin, T* xout,
                                                              const T* __restrict__ dbuf, T scale,
                                                              T t) {
-    __shared__ T s_buf[kSweepLds];
+    __shared__ T s_buf[PARK ? kSweepLdsPark : kSweepLds];
     T* const sr0 = s_buf;
     T* const sr1 = sr0 + VR * VR;
     T* const srp = sr1 + VR * VR;
@@ -935,8 +1077,10 @@ __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __
         dbuf += int64_t(blockIdx.y) * (SIMPLE ? (g.N + 1) * (g.N + 1) : n_boundary_patches(g.N)) * 64;
     }
     const int E0x = (tlin % tiles) * VT, E0y = (tlin / tiles) * VT;
+    // the owners' x loads are issued here and land while the patches are
+    // solved (with parking: after the solves, where registers are free)
     OwnerBase<T> ob;
-    owner_prefetch(g, E0x, E0y, xin, ob);
+    if (!PARK) owner_prefetch(g, E0x, E0y, xin, ob);
     const int tx = threadIdx.x % VP, ty = threadIdx.x / VP;
     const int I = E0x - 1 + tx, J = E0y - 1 + ty;
     const bool valid = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
@@ -959,7 +1103,12 @@ __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __
             }
         rv[50] = srp[ty * VR1 + tx];
 
-        sym_apply(rv, t);  // interior operator, every lane
+        if (PARK) {
+            __syncthreads();  // the park area overlaps the staged residual
+            sym_apply_parked(rv, t, s_buf + threadIdx.x);
+        } else {
+            sym_apply(rv, t);  // interior operator, every lane
+        }
         const bool interior = valid && I >= 2 && J >= 2 && I <= g.N - 2 && J <= g.N - 2;
         if (!interior) {
             // boundary patch: corrections precomputed; outside the domain: none
@@ -968,6 +1117,7 @@ __global__ __launch_bounds__(VNT, 2) void vanka_sweep_kernel(Geom g, const T* __
             for (int s = 0; s < kSlots; ++s) rv[s] = valid ? dbuf[int64_t(bi) * 64 + s] : T(0);
         }
     }
+    if (PARK) owner_prefetch(g, E0x, E0y, xin, ob);
     __syncthreads();  // the staging buffers are reused for the exchange below
 
     // x-sums within the 16-lane rows: column 2tx (even) and 2tx+1 (odd) of
@@ -1979,6 +2129,9 @@ void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const
     if (mfma)
         vanka_mfma_kernel<T><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf, mtab, T(omega / g.nu),
                                                   T(g.nu / g.h));
+    else if (std::is_same<T, double>::value && g.N >= kParkMinN)
+        vanka_sweep_kernel<T, false, true><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf,
+                                                                T(omega / g.nu), T(g.nu / g.h));
     else
         vanka_sweep_kernel<T><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf, T(omega / g.nu),
                                                    T(g.nu / g.h));

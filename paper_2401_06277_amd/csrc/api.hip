@@ -40,6 +40,7 @@ struct LevelBuf {
     void* x = nullptr;  // MG precision
     void* b = nullptr;
     void* r = nullptr;
+    void* x2 = nullptr;    // x + prolonged coarse correction (levels above the coarsest)
     void* W = nullptr;     // patch-operator table, MG precision (relaxed levels)
     void* dbuf = nullptr;  // boundary-patch corrections (relaxed levels)
     void* bs = nullptr;    // Braess-Sarazin scratch: Schur rhs, dp, B^T dp (relaxed levels)
@@ -165,35 +166,45 @@ vkmg_layout layout_of_geom(const Geom& g) {
 
 // One sweep on level l: r = b - A x, then x += corrections (in place).
 // With x_zero the iterate is known to be zero, so r = b and the update
-// writes every DoF of x without reading it.
+// writes every DoF of x without reading it.  With xin given, L.r already
+// holds b - A xin and the update writes xin + corrections to x.
 template <typename T>
 void sweep_t(vkmg_ctx* c, int l, const T* b, T* x, bool x_zero, hipStream_t s,
-             bool vanka = false) {
+             bool vanka = false, const T* xin = nullptr) {
     LevelBuf& L = c->lev[l];
     const T* r = b;
-    if (!x_zero) {
+    if (xin) {
+        r = static_cast<const T*>(L.r);
+    } else if (!x_zero) {
         Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
         launch_residual<T, T>(L.g, b, x, static_cast<T*>(L.r), 0, s, c->nb(), c->nu_of<T>(l));
         r = static_cast<const T*>(L.r);
+        xin = x;
     }
     Timed t(c, VKMG_KERNEL_VANKA, s, l);
     if (c->variable) {
-        launch_vanka_simple<T>(L.g, r, x_zero ? nullptr : x, x, static_cast<const T*>(L.W),
+        launch_vanka_simple<T>(L.g, r, xin, x, static_cast<const T*>(L.W),
                                static_cast<T*>(L.dbuf), s, c->nb());
         return;
     }
     if (!vanka && c->opt.relaxation == VKMG_RELAX_BRAESS_SARAZIN) {
         const int64_t np = L.g.nq1 * c->nb();
         T* prhs = static_cast<T*>(L.bs);
-        launch_bs_relax<T>(L.g, r, x_zero ? nullptr : x, x, prhs, prhs + np, prhs + 2 * np,
-                           c->opt.bs_t, c->opt.bs_omega, c->opt.bs_jacobi_weight,
-                           c->opt.bs_jacobi_sweeps, s, c->nb());
+        launch_bs_relax<T>(L.g, r, xin, x, prhs, prhs + np, prhs + 2 * np, c->opt.bs_t,
+                           c->opt.bs_omega, c->opt.bs_jacobi_weight, c->opt.bs_jacobi_sweeps, s,
+                           c->nb());
         return;
     }
-    launch_vanka_update<T>(L.g, r, x_zero ? nullptr : x, x, static_cast<const T*>(L.W),
+    launch_vanka_update<T>(L.g, r, xin, x, static_cast<const T*>(L.W),
                            static_cast<const T*>(c->mtab), static_cast<T*>(L.dbuf), c->opt.omega,
                            c->opt.interior_apply == VKMG_APPLY_MATRIX, s, c->nb());
 }
+
+// Largest FP64 level on which the coarse-grid correction is added by the
+// residual of the first post-smoothing sweep (launch_residual_prolong):
+// there it saves a launch; on larger FP64 levels the separate kernels are
+// faster (measured at 512x512 and 1024x1024).
+constexpr int kFusedProlongMaxN = 256;
 
 // MG(l, b) of Algorithm 1 with zero initial guess, result in x.
 template <typename T>
@@ -226,11 +237,26 @@ void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
     } else {
         mg_t<T>(c, l - 1, bc, xc, s);
     }
-    {
+    // FP64 levels above kFusedProlongMaxN: the separate prolongation and
+    // residual kernels are faster (the fused one is not bandwidth-bound there)
+    const bool fused = sizeof(T) == 4 || L.g.N <= kFusedProlongMaxN;
+    if (c->opt.nu_post == 0 || !fused) {
         Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
         launch_prolong_add<T>(L.g, Lc.g, xc, x, s, c->nb());
     }
-    for (int i = 0; i < c->opt.nu_post; ++i) sweep_t<T>(c, l, b, x, false, s);
+    if (c->opt.nu_post == 0) return;
+    if (!fused) {
+        for (int i = 0; i < c->opt.nu_post; ++i) sweep_t<T>(c, l, b, x, false, s);
+        return;
+    }
+    {  // x + P xc into x2 and its residual in one pass; the first sweep
+       // then updates x2 into x
+        Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
+        launch_residual_prolong<T>(L.g, Lc.g, b, x, xc, static_cast<T*>(L.x2),
+                                   static_cast<T*>(L.r), s, c->nb(), c->nu_of<T>(l));
+    }
+    sweep_t<T>(c, l, b, x, false, s, false, static_cast<const T*>(L.x2));
+    for (int i = 1; i < c->opt.nu_post; ++i) sweep_t<T>(c, l, b, x, false, s);
 }
 
 void vcycle_impl(vkmg_ctx* c, const double* r, double* z, hipStream_t s) {
@@ -772,6 +798,7 @@ static vkmg_status setup_impl(const vkmg_grid* grid, int32_t levels, double nu,
         st = alloc(c.get(), &L.x, es * L.g.n * nbt);
         if (st == VKMG_OK) st = alloc(c.get(), &L.b, es * L.g.n * nbt);
         if (st == VKMG_OK) st = alloc(c.get(), &L.r, es * L.g.n * nbt);
+        if (st == VKMG_OK && l >= 1) st = alloc(c.get(), &L.x2, es * L.g.n * nbt);
         const size_t npatch = size_t(L.g.N + 1) * (L.g.N + 1);
         if (st == VKMG_OK && l >= 1)
             st = alloc(c.get(), &L.dbuf,

@@ -22,6 +22,13 @@ template <typename Tx, typename T>
 void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hipStream_t s,
                      int nb = 1, const T* nue = nullptr);
 
+// x2 = x + P ec (the prolongation of the coarse correction ec, as
+// launch_prolong_add) and r = b - A x2 in one pass over the fine level g
+// (coarse level gc); x is not modified.  nue as for launch_residual.
+template <typename T>
+void launch_residual_prolong(const Geom& g, const Geom& gc, const T* b, const T* x, const T* ec,
+                             T* x2, T* r, hipStream_t s, int nb = 1, const T* nue = nullptr);
+
 // b = M f - A_FD g on free rows, g on Dirichlet rows, -B_pD g on pressure
 // rows (f, g: 2 (2N+1)^2 values per right-hand side).
 void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hipStream_t s,

@@ -86,6 +86,24 @@ __device__ __forceinline__ void cell_row_pair(const T* __restrict__ su0, const T
     }
 }
 
+// 1D interpolation taps of fine Q2 node i from coarse Q2 nodes, padded to
+// three (a fine node on a coarse node has one tap of weight 1).
+__device__ __forceinline__ void q2_prolong_taps(int i, int (&c)[3], double (&w)[3]) {
+    if ((i & 1) == 0) {
+        c[0] = i / 2; w[0] = 1.0;
+        c[1] = i / 2; w[1] = 0.0;
+        c[2] = i / 2; w[2] = 0.0;
+        return;
+    }
+    const int e = i / 4;  // coarse element
+    c[0] = 2 * e; c[1] = 2 * e + 1; c[2] = 2 * e + 2;
+    if ((i & 3) == 1) {
+        w[0] = 0.375; w[1] = 0.75; w[2] = -0.125;
+    } else {
+        w[0] = -0.125; w[1] = 0.75; w[2] = 0.375;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Residual r = b - A x (MODE 0) / apply r = A x (MODE 1)
 // A workgroup computes the rows of a tile of RT x RT cells, one thread per
@@ -105,14 +123,107 @@ constexpr int RNT = 2 * RT * RT;    // threads: one per cell and Q2 row parity
 __device__ constexpr int kEK[3][3] = {{7, -8, 1}, {-8, 16, -8}, {1, -8, 7}};
 __device__ constexpr int kEM[3][3] = {{4, 2, -1}, {2, 16, 2}, {-1, 2, 4}};
 
+// Stage x + P ec for a residual tile (Q2 nodes [2E0 - 2, 2E0 + RQ2 - 2) and
+// Q1 nodes [E0 - 1, E0 + RQ1 - 1) per direction; Dirichlet and outside
+// nodes zero, as the residual staging).  Q2: one item per staged column
+// and coarse element row, interpolating along x and then y with the
+// expressions of prolong_kernel; Q1: bilinear per node, likewise.  A
+// thread takes at most one item and one Q1 node and issues all their loads
+// before the first is used.
+constexpr int kProRows = RQ2 / 4 + 1;  // coarse element rows meeting the staged rows
+static_assert(RQ2 * kProRows <= RNT && RQ1 * RQ1 <= RNT, "one staging item per thread");
+
+template <typename T>
+__device__ __forceinline__ void stage_prolonged(const Geom& g, const Geom& gc, const T* x,
+                                                const T* ec, int E0x, int E0y, T* su0, T* su1,
+                                                T* sp) {
+    const int ox = 2 * E0x - 2, oy = 2 * E0y - 2;
+    const int jg0 = (oy + 4) / 4 - 1;  // floor(oy / 4), oy >= -2
+    const int item = threadIdx.x;
+    const bool q2item = item < RQ2 * kProRows;
+    const int ci = item % RQ2, jg = jg0 + item / RQ2;
+    const int i = ox + ci;
+    const bool col = q2item && i >= 0 && i < g.s2 && jg >= 0 && jg < gc.N;
+    int cx[3];
+    double wx[3];
+    q2_prolong_taps(col ? i : 0, cx, wx);
+    T f0[4], f1[4], vx[3][3], vy[3][3];
+    bool fr[4], ok[3][3];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int fj = 4 * jg + p;
+        fr[p] = col && i > 0 && i < g.s2 - 1 && fj > 0 && fj < g.s2 - 1;
+        const int64_t q = fr[p] ? int64_t(fj) * g.s2 + i : 0;
+        f0[p] = x[q];
+        f1[p] = x[g.nq2 + q];
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ok[b][a] = col && !q2_boundary(cx[a], 2 * jg + b, gc.s2);
+            const int64_t qc = ok[b][a] ? int64_t(2 * jg + b) * gc.s2 + cx[a] : 0;
+            vx[b][a] = ec[qc];
+            vy[b][a] = ec[gc.nq2 + qc];
+        }
+    // Q1 node t = threadIdx.x
+    const int t = threadIdx.x;
+    const int I = E0x - 1 + t % RQ1, J = E0y - 1 + t / RQ1;
+    const bool pin = t < RQ1 * RQ1 && I >= 0 && J >= 0 && I <= g.N && J <= g.N;
+    const int Ic = pin ? I : 0, Jc = pin ? J : 0;
+    const int i0 = Ic / 2, i1 = (Ic + 1) / 2, j0 = Jc / 2, j1 = (Jc + 1) / 2;
+    const T* pc = ec + 2 * gc.nq2;
+    const T fp = x[2 * g.nq2 + int64_t(Jc) * g.s1 + Ic];
+    const T p00 = pc[int64_t(j0) * gc.s1 + i0], p01 = pc[int64_t(j0) * gc.s1 + i1];
+    const T p10 = pc[int64_t(j1) * gc.s1 + i0], p11 = pc[int64_t(j1) * gc.s1 + i1];
+
+    T tx[3], ty[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        tx[b] = 0;
+        ty[b] = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T wa = ok[b][a] ? T(wx[a]) : T(0);
+            tx[b] += wa * vx[b][a];
+            ty[b] += wa * vy[b][a];
+        }
+    }
+    const T sx[4] = {tx[0], T(0.375) * tx[0] + T(0.75) * tx[1] + T(-0.125) * tx[2], tx[1],
+                     T(-0.125) * tx[0] + T(0.75) * tx[1] + T(0.375) * tx[2]};
+    const T sy[4] = {ty[0], T(0.375) * ty[0] + T(0.75) * ty[1] + T(-0.125) * ty[2], ty[1],
+                     T(-0.125) * ty[0] + T(0.75) * ty[1] + T(0.375) * ty[2]};
+    if (q2item) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int lr = 4 * jg + p - oy;
+            if (lr < 0 || lr >= RQ2) continue;
+            su0[lr * RQ2 + ci] = fr[p] ? f0[p] + sx[p] : T(0);
+            su1[lr * RQ2 + ci] = fr[p] ? f1[p] + sy[p] : T(0);
+        }
+    }
+    if (t < RQ1 * RQ1) {
+        const T r0 = (Ic & 1) ? T(0.5) * (p00 + p01) : p00;
+        const T r1 = (Ic & 1) ? T(0.5) * (p10 + p11) : p10;
+        sp[t] = pin ? fp + ((Jc & 1) ? T(0.5) * (r0 + r1) : r0) : T(0);
+    }
+}
+
 // VAR: per-element viscosity nue (N^2 values, index ey*N + ex); the L rows
 // are then summed element by element (each Q2 node lies in 1, 2 or 4
 // elements) instead of by the constant-coefficient stencil.
-template <int MODE, typename Tx, typename T, bool VAR = false>
+// PRO (MODE 0, Tx = T): the coarse-grid correction is added first: the tile
+// stages x + P ec (ec on the coarse level gc, the arithmetic of
+// prolong_kernel, so the sums are the same), writes it to x2 for the nodes
+// whose rows it computes, and forms r = b - A (x + P ec).
+template <int MODE, typename Tx, typename T, bool VAR = false, bool PRO = false>
 __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void residual_kernel(Geom g, const T* __restrict__ b,
                                                        const Tx* __restrict__ x,
                                                        T* __restrict__ r,
-                                                       const T* __restrict__ nue = nullptr) {
+                                                       const T* __restrict__ nue = nullptr,
+                                                       Geom gc = Geom{},
+                                                       const T* __restrict__ ec = nullptr,
+                                                       T* __restrict__ x2 = nullptr) {
     __shared__ T s_u[2][RQ2 * RQ2];
     __shared__ T s_p[RQ1 * RQ1];
     __shared__ T s_nu[VAR ? RQ1 * RQ1 : 1];
@@ -126,9 +237,16 @@ __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void r
         if (MODE == 0) b += bo;
         x += bo;
         r += bo;
+        if (PRO) {
+            x2 += bo;
+            ec += int64_t(blockIdx.y) * gc.n;
+        }
     }
     const int E0x = (tlin % tiles) * RT, E0y = (tlin / tiles) * RT;
     const int ox = 2 * E0x - 2, oy = 2 * E0y - 2;
+    if (PRO) {
+        stage_prolonged(g, gc, x, ec, E0x, E0y, s_u[0], s_u[1], s_p);
+    } else {
     // every load of the tile is issued before the first is used: addresses
     // of nodes outside the staged set are clamped to node 0 and the values
     // replaced by zero afterwards
@@ -163,6 +281,7 @@ __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void r
     for (int it = 0; it < kIt1; ++it) {
         const int t = threadIdx.x + it * RNT;
         if (t < RQ1 * RQ1) s_p[t] = f1[it] ? T(vp[it]) : T(0);
+    }
     }
     if (VAR) {  // viscosities of the elements [E0-1, E0+RT] per direction
         for (int t = threadIdx.x; t < RQ1 * RQ1; t += RNT) {
@@ -240,9 +359,14 @@ __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void r
         if (q < 0) continue;
         const int i = 2 * ex + aa, j = 2 * ey + bb;
         T vx = ax[aa], vy = ay[aa];
-        if (i == 0 || j == 0 || i == g.s2 - 1 || j == g.s2 - 1) {
+        const bool dir = i == 0 || j == 0 || i == g.s2 - 1 || j == g.s2 - 1;
+        if (dir) {
             vx = T(x[q]);  // Dirichlet row: identity (edge tiles only)
             vy = T(x[g.nq2 + q]);
+        }
+        if (PRO) {  // x + P ec: unchanged on Dirichlet nodes
+            x2[q] = dir ? vx : s_u[0][c2 + bb * RQ2 + aa];
+            x2[g.nq2 + q] = dir ? vy : s_u[1][c2 + bb * RQ2 + aa];
         }
         if (MODE == 0) {
             r[q] = bx[aa] - vx;
@@ -253,6 +377,7 @@ __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void r
         }
     }
     if (bb == 0) r[qp] = (MODE == 0) ? bp - ap : ap;
+    if (PRO && bb == 0) x2[qp] = s_p[c1];
 }
 
 // ---------------------------------------------------------------------------
@@ -1426,24 +1551,6 @@ __global__ __launch_bounds__(256) void restrict_kernel(Geom gf, Geom gc, const T
     }
 }
 
-// 1D interpolation taps of fine Q2 node i from coarse Q2 nodes, padded to
-// three (a fine node on a coarse node has one tap of weight 1).
-__device__ __forceinline__ void q2_prolong_taps(int i, int (&c)[3], double (&w)[3]) {
-    if ((i & 1) == 0) {
-        c[0] = i / 2; w[0] = 1.0;
-        c[1] = i / 2; w[1] = 0.0;
-        c[2] = i / 2; w[2] = 0.0;
-        return;
-    }
-    const int e = i / 4;  // coarse element
-    c[0] = 2 * e; c[1] = 2 * e + 1; c[2] = 2 * e + 2;
-    if ((i & 3) == 1) {
-        w[0] = 0.375; w[1] = 0.75; w[2] = -0.125;
-    } else {
-        w[0] = -0.125; w[1] = 0.75; w[2] = 0.375;
-    }
-}
-
 // Prolongation (x_f += P e_c), one thread per fine Q2 column i and coarse
 // element row jg: the fine rows 4jg..4jg+3 interpolate the coarse rows
 // 2jg..2jg+2 (each first interpolated along x at column i) with the 1D
@@ -2044,6 +2151,23 @@ void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hip
 }
 template void launch_residual<double, double>(const Geom&, const double*, const double*, double*,
                                               int, hipStream_t, int, const double*);
+
+template <typename T>
+void launch_residual_prolong(const Geom& g, const Geom& gc, const T* b, const T* x, const T* ec,
+                             T* x2, T* r, hipStream_t s, int nb, const T* nue) {
+    const int tiles = (g.N + 1 + RT - 1) / RT;
+    const dim3 grid(8 * ((tiles * tiles + 7) / 8), nb);
+    if (nue)
+        residual_kernel<0, T, T, true, true><<<grid, RNT, 0, s>>>(g, b, x, r, nue, gc, ec, x2);
+    else
+        residual_kernel<0, T, T, false, true><<<grid, RNT, 0, s>>>(g, b, x, r, nullptr, gc, ec, x2);
+}
+template void launch_residual_prolong<double>(const Geom&, const Geom&, const double*,
+                                              const double*, const double*, double*, double*,
+                                              hipStream_t, int, const double*);
+template void launch_residual_prolong<float>(const Geom&, const Geom&, const float*, const float*,
+                                             const float*, float*, float*, hipStream_t, int,
+                                             const float*);
 template void launch_residual<float, float>(const Geom&, const float*, const float*, float*, int,
                                             hipStream_t, int, const float*);
 

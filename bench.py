@@ -39,6 +39,7 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, published
 ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -106,6 +107,59 @@ def copy_calibration(mib):
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Usable HBM bandwidth: read + write bytes per second of a plain device
+    copy of `mib` MiB (larger than the 256 MB last-level cache)."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2 * n * 8 / t
+
+
+def vcycle_roofline(N, L, bw):
+    """Time bound of one FP64 V(2,2) cycle: the sum over its kernels of the
+    larger of algorithmic bytes / bw and algorithmic flops / the FP64 vector
+    peak.  Per relaxed level (n_l DoFs, N_l^2 elements, (N_l+1)^2 patches):
+    four Vanka updates (read r and x, write x; the first, from x = 0, does
+    not read x; 2*495 + 297 + 51 flops per interior patch in the symmetry
+    form, 2*51*51 per boundary patch), four residuals (read x and b, write
+    r; about 345 flops per element), the restriction (read n_l, write
+    n_{l-1}) and the prolongation (read n_{l-1} and n_l, write n_l); the
+    coarse solve reads its n_0 x n_0 inverse."""
+    def n_of(Nl):
+        return 2 * (2 * Nl + 1) ** 2 + (Nl + 1) ** 2
+
+    peak = FP64_VECTOR_PEAK_TFLOPS * 1e12
+    terms = []
+    for l in range(1, L):
+        Nl = N >> (L - 1 - l)
+        n, nc = n_of(Nl), n_of(Nl // 2)
+        pb = 8 * Nl - 8
+        pint = (Nl + 1) ** 2 - pb
+        fv = pint * (2 * 495 + 297 + 51) + pb * 2 * 51 * 51
+        for k in range(4):
+            terms.append((("vanka", Nl), (16 if k == 0 else 24) * n, fv))
+            terms.append((("residual", Nl), 24 * n, 345 * Nl * Nl))
+        terms.append((("restrict", Nl), 8 * (n + nc), 20 * Nl * Nl))
+        terms.append((("prolong", Nl), 8 * (nc + 2 * n), 20 * Nl * Nl))
+    n0 = n_of(N >> (L - 1)) + 1
+    terms.append((("coarse", N >> (L - 1)), 8 * n0 * n0, 2 * n0 * n0))
+    t_roof = sum(max(b / bw, f / peak) for _, b, f in terms)
+    nbytes = sum(b for _, b, _ in terms)
+    flops = sum(f for _, _, f in terms)
+    return t_roof, nbytes, flops
 
 
 def cpu_baseline(N, levels, nvc, c2=None):
@@ -555,6 +609,9 @@ def main():
         ts.append(e0.elapsed_time(e1) / 1e3)
     ts.sort()
     vcycle_s = ts[len(ts) // 2]
+    del r, z
+    bw = copy_bandwidth(torch)
+    t_roof, vc_bytes, vc_flops = vcycle_roofline(N, L, bw)
 
     out = {
         "metric": "Vanka V-cycle patch-updates/s + FGMRES time-to-1e-8, FP64 vs FP32-MG, 1024²",
@@ -583,6 +640,18 @@ def main():
         "true_rel_res": inf64[-1]["true_rel_res"],
         "vcycle_s": vcycle_s,
         "vcycle_patch_updates_per_s": ups_per_cycle / vcycle_s,
+        "vcycle_roofline": {
+            "t_roof_s": t_roof,
+            "frac": t_roof / vcycle_s,
+            "alg_bytes": vc_bytes,
+            "alg_flops": vc_flops,
+            "hbm_frac_of_copy": vc_bytes / vcycle_s / bw,
+            "hbm_frac_of_peak": vc_bytes / vcycle_s / (HBM_PEAK_GBS * 1e9),
+            "copy_bandwidth_gbs": bw / 1e9,
+            "model": "sum over the cycle's kernels of max(algorithmic bytes / measured copy "
+                     "bandwidth, algorithmic flops / FP64 vector peak); launch latency not "
+                     "modelled",
+        },
         "roofline": {
             "kernel": ("Vanka update at the finest level (boundary-patch kernel + "
                        + ("vanka_mfma_kernel" if a.interior_apply == "matrix"

@@ -62,6 +62,7 @@ struct vkmg_ctx {
     double* part = nullptr;   // dot partials
     double* hdev = nullptr;   // coefficients (device)
     double* hhost = nullptr;  // pinned host mirror
+    hipEvent_t step_done[2] = {nullptr, nullptr};  // coefficient copies of Arnoldi steps
     // FGMRES basis
     double* V = nullptr;
     double* Z = nullptr;
@@ -135,6 +136,10 @@ void free_all(vkmg_ctx* c) {
     c->allocations.clear();
     if (c->hhost) (void)hipHostFree(c->hhost);
     c->hhost = nullptr;
+    for (auto& e : c->step_done) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
 
     for (auto& v : c->events)
         for (auto& e : v) {
@@ -1220,8 +1225,9 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
     // Every pointer depends only on j, so a step can be captured once per j
     // and replayed.
     const bool delayed = m <= kDelayedMaxRestart;
-    double* dco = ctx->hdev;       // delayed: 2j+3 reduced values of pass 1
-    double* dcf = ctx->hdev + 300;  // delayed: alpha, gamma, d, sigma
+    // delayed: the 2j+3 reduced values of pass 1 of step j, followed by its
+    // alpha, gamma, d, sigma (one copy to the host per step)
+    double* dco = ctx->hdev;
     auto arnoldi_step = [&](int j, hipStream_t ss) {
         double* vj = V + int64_t(j) * ld;
         double* zj = Z + int64_t(j) * ld;
@@ -1235,7 +1241,7 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
             Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);
             launch_dcgs_dots(V, ld, j, vj, w, n, ctx->part, ss);
             launch_reduce_partials(ctx->part, 2 * j + 3, dco, ss);
-            launch_dcgs_update(V, ld, j, dco, vj, w, V + int64_t(kb) * ld, n, dcf, ss);
+            launch_dcgs_update(V, ld, j, dco, vj, w, V + int64_t(kb) * ld, n, dco + 2 * j + 3, ss);
             return;
         }
         dots_async(ctx, V, ld, kb, w, h1, ss);
@@ -1265,6 +1271,32 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
         drop_graphs(ctx);
         ctx->graphs_scheme = int(delayed);
     }
+    // Pipelined steps (delayed scheme with graphs): step j+1 needs nothing
+    // from the host, so it is enqueued before the host waits for the
+    // coefficients of step j (double-buffered pinned copies, one event per
+    // buffer), unless the residual estimate, extrapolated at its last rate,
+    // may reach the tolerance at step j; a step enqueued past convergence is
+    // left unused.
+    const bool pipe = use_graphs && delayed;
+    if (pipe)
+        for (auto& e : ctx->step_done)
+            if (!e) VKMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    double* const hbuf[2] = {ctx->hhost + 650, ctx->hhost + 800};
+    auto enqueue_step = [&](int j) -> vkmg_status {
+        if (use_graphs) {
+            vkmg_status sg = step_graph(ctx, j, arnoldi_step);
+            if (sg != VKMG_OK) return sg;
+            VKMG_HIP(hipGraphLaunch(ctx->step_graphs[j], s));
+        } else {
+            arnoldi_step(j, s);
+        }
+        if (delayed) {
+            VKMG_HIP(hipMemcpyAsync(hbuf[j & 1], dco, sizeof(double) * (2 * j + 7),
+                                    hipMemcpyDeviceToHost, s));
+            if (pipe) VKMG_HIP(hipEventRecord(ctx->step_done[j & 1], s));
+        }
+        return VKMG_OK;
+    };
     for (;;) {
         {
             Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
@@ -1275,25 +1307,33 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
         gbase[0] = beta;
         int k = 0;
         double sigma_prev = 0.0;
+        bool queued = false;              // step j already enqueued
+        double g_last = beta, g_prev = 0.0;  // |g| after the last two steps
         for (int j = 0; j < m; ++j) {
             const int kb = j + 1;  // basis vectors so far
             const bool normalized = kb <= 32;
             double hnext = 0.0;
-            if (use_graphs) {
-                st = step_graph(ctx, j, arnoldi_step);
+            if (!queued) {
+                st = enqueue_step(j);
                 if (st != VKMG_OK) return st;
-                VKMG_HIP(hipGraphLaunch(ctx->step_graphs[j], s));
-            } else {
-                arnoldi_step(j, s);
+            }
+            queued = false;
+            if (pipe && j >= 1 && j + 1 < m && total + 1 < max_iters &&
+                g_last * (g_last / g_prev) > 8.0 * target) {
+                st = enqueue_step(j + 1);
+                if (st != VKMG_OK) return st;
+                queued = true;
             }
             bool finite = true;
             if (delayed) {
-                VKMG_HIP(hipMemcpyAsync(ctx->hhost, dco, sizeof(double) * (2 * j + 3), hipMemcpyDeviceToHost, s));
-                VKMG_HIP(hipMemcpyAsync(ctx->hhost + 300, dcf, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
-                VKMG_HIP(hipStreamSynchronize(s));
-                const double* c = ctx->hhost;
-                const double alpha = ctx->hhost[300], gamma = ctx->hhost[301];
-                const double d = ctx->hhost[302], sigma = ctx->hhost[303];
+                if (pipe) {
+                    VKMG_HIP(hipEventSynchronize(ctx->step_done[j & 1]));
+                } else {
+                    VKMG_HIP(hipStreamSynchronize(s));
+                }
+                const double* c = hbuf[j & 1];
+                const double alpha = c[2 * j + 3], gamma = c[2 * j + 4];
+                const double d = c[2 * j + 5], sigma = c[2 * j + 6];
                 if (j > 0) {  // finalise column j-1
                     for (int i = 0; i < j; ++i) Hij(i, j - 1) += c[j + i] / sigma_prev;
                     Hij(j, j - 1) = alpha / sigma_prev;
@@ -1338,6 +1378,8 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
             }
             ++total;
             k = j + 1;
+            g_prev = g_last;
+            g_last = std::fabs(gv[j + 1]);
             est = std::fabs(gv[j + 1]) / beta0;
             if (std::fabs(gv[j + 1]) <= target) break;
             if (breakdown || total >= max_iters) break;

@@ -29,6 +29,10 @@ HIPCC_FLAGS = [
     "-Wno-unused-function", "-Wno-unknown-pragmas",
     # no packed FP32 VALU instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # machine scheduling that keeps memory clauses together: no spills in the
+    # residual kernel at its 128-register budget (same arithmetic, the FP64
+    # solve ~0.6 % faster than the default strategy)
+    "-mllvm", "-amdgpu-sched-strategy=max-memory-clause",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-I" + GEN_DIR,
 ]
 GXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

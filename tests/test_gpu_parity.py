@@ -326,6 +326,33 @@ def test_fgmres_restarts_match_oracle():
     assert np.linalg.norm(xa - xo) <= 1e-8 * np.linalg.norm(xo)
 
 
+def test_fgmres_long_restart_classical_path():
+    """Restarts above 32 use the classical three-pass CGS2 (unfused passes
+    beyond 32 basis vectors, the new vector scaled on host request): the
+    iteration count and solution at rtol 1e-10 match the oracle, and 36
+    steps of one cycle (rtol 0, more than 32 basis vectors) reach the
+    rounding floor with the oracle's solution."""
+    N, levels = 16, 3
+    s = solver(N, levels)
+    H = hierarchy(N, levels)
+    A, b, xl, _ = _manufactured_system(N)
+    ro = fgmres.fgmres(A, b, xl, H.vcycle, rtol=1e-10, restart=40, max_iters=200)
+    x = dev(xl)
+    info = s.fgmres_solve(dev(b), x, rtol=1e-10, restart=40, max_iters=200)
+    assert info["status_name"] == "VKMG_OK"
+    assert abs(info["iterations"] - ro.iterations) <= 1
+    xo = fem.normalise_pressure(N, ro.x)
+    assert np.linalg.norm(fem.normalise_pressure(N, host(x)) - xo) <= 1e-8 * np.linalg.norm(xo)
+    x = dev(xl)
+    info = s.fgmres_solve(dev(b), x, rtol=0.0, restart=40, max_iters=36)
+    assert info["iterations"] == 36 and info["restarts"] == 0
+    assert info["status_name"] == "VKMG_ERR_NOT_CONVERGED"
+    xh = host(x)
+    r0 = np.linalg.norm(b - A @ xl)
+    assert np.linalg.norm(b - A @ xh) <= 1e-12 * r0
+    assert np.linalg.norm(fem.normalise_pressure(N, xh) - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
 def test_fgmres_edge_cases():
     N, levels = 16, 3
     s = solver(N, levels)

@@ -264,13 +264,16 @@ void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
     for (int i = 1; i < c->opt.nu_post; ++i) sweep_t<T>(c, l, b, x, false, s);
 }
 
-void vcycle_impl(vkmg_ctx* c, const double* r, double* z, hipStream_t s) {
+// r32_ready (FP32 multigrid): the top level's b already holds r rounded to
+// FP32 (written by the Gram-Schmidt kernel that produced r).
+void vcycle_impl(vkmg_ctx* c, const double* r, double* z, hipStream_t s, bool r32_ready = false) {
     const int top = c->L - 1;
     if (c->opt.mg_precision == VKMG_FP64) {
         mg_t<double>(c, top, r, z, s);
     } else {
         LevelBuf& L = c->lev[top];
-        launch_cast<double, float>(r, static_cast<float*>(L.b), L.g.n * c->nb(), s);
+        if (!r32_ready)
+            launch_cast<double, float>(r, static_cast<float*>(L.b), L.g.n * c->nb(), s);
         mg_t<float>(c, top, static_cast<const float*>(L.b), static_cast<float*>(L.x), s);
         launch_cast<float, double>(static_cast<const float*>(L.x), z, L.g.n * c->nb(), s);
     }
@@ -1225,6 +1228,7 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
     // Every pointer depends only on j, so a step can be captured once per j
     // and replayed.
     const bool delayed = m <= kDelayedMaxRestart;
+    const bool fp32_mg = ctx->opt.mg_precision == VKMG_FP32;
     // delayed: the 2j+3 reduced values of pass 1 of step j, followed by its
     // alpha, gamma, d, sigma (one copy to the host per step)
     double* dco = ctx->hdev;
@@ -1232,7 +1236,9 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
         double* vj = V + int64_t(j) * ld;
         double* zj = Z + int64_t(j) * ld;
         const int kb = j + 1;
-        vcycle_impl(ctx, vj, zj, ss);
+        // delayed scheme, FP32 multigrid: the V-cycle input of step j >= 1
+        // was rounded to FP32 by the update kernel of step j-1
+        vcycle_impl(ctx, vj, zj, ss, delayed && fp32_mg && j >= 1);
         {
             Timed t(ctx, VKMG_KERNEL_RESIDUAL, ss);
             launch_residual<double, double>(g, nullptr, zj, w, 1, ss, 1, ctx->nu64);
@@ -1241,7 +1247,8 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
             Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);
             launch_dcgs_dots(V, ld, j, vj, w, n, ctx->part, ss);
             launch_reduce_partials(ctx->part, 2 * j + 3, dco, ss);
-            launch_dcgs_update(V, ld, j, dco, vj, w, V + int64_t(kb) * ld, n, dco + 2 * j + 3, ss);
+            launch_dcgs_update(V, ld, j, dco, vj, w, V + int64_t(kb) * ld, n, dco + 2 * j + 3, ss,
+                               1, 0, 0, fp32_mg ? static_cast<float*>(ctx->lev.back().b) : nullptr);
             return;
         }
         dots_async(ctx, V, ld, kb, w, h1, ss);

@@ -128,10 +128,11 @@ void launch_dcgs_dots(const double* V, int64_t ldv, int j, const double* u, cons
                       int64_t n, double* part, hipStream_t s, int nb = 1, int64_t sb = 0);
 // Delayed CGS2, pass 2 from the 2j+3 reduced values c: u <- v_j (final),
 // next <- normalised successor; cf = (alpha, gamma, d, 1/sqrt(d)); c and cf
-// of batch entry b at offset b * sc
+// of batch entry b at offset b * sc.  next32: if given, also next rounded
+// to FP32 (the input of an FP32 V-cycle), vectors sb apart.
 void launch_dcgs_update(const double* V, int64_t ldv, int j, const double* c, double* u,
                         const double* w, double* next, int64_t n, double* cf, hipStream_t s,
-                        int nb = 1, int64_t sb = 0, int64_t sc = 0);
+                        int nb = 1, int64_t sb = 0, int64_t sc = 0, float* next32 = nullptr);
 // x += sum_v y[v] Z_v; y of batch entry b at offset b * sy
 void launch_axpy_multi(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t n,
                        hipStream_t s, int nb = 1, int64_t sb = 0, int64_t sy = 0);

@@ -2014,13 +2014,14 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(const double* __restri
                                                           double* uv, const double* __restrict__ w,
                                                           double* __restrict__ next, int64_t n,
                                                           double* __restrict__ cf, int64_t sb,
-                                                          int64_t sc) {
+                                                          int64_t sc, float* __restrict__ next32) {
     {  // batch entry blockIdx.y: vectors sb apart, coefficients sc apart
         const int64_t bo = int64_t(blockIdx.y) * sb;
         V += bo;
         uv += bo;
         w += bo;
         next += bo;
+        if (next32) next32 += bo;
         c += int64_t(blockIdx.y) * sc;
         cf += int64_t(blockIdx.y) * sc;
     }
@@ -2061,7 +2062,9 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(const double* __restri
         }
         const double vj = (ui - ps) * ra;
         uv[i] = vj;
-        next[i] = ((wi - ph) - gamma * vj) * sigma;
+        const double nx = ((wi - ph) - gamma * vj) * sigma;
+        next[i] = nx;
+        if (next32) next32[i] = float(nx);
     }
 }
 
@@ -2384,9 +2387,9 @@ void launch_dcgs_dots(const double* V, int64_t ldv, int j, const double* u, cons
 
 void launch_dcgs_update(const double* V, int64_t ldv, int j, const double* c, double* u,
                         const double* w, double* next, int64_t n, double* cf, hipStream_t s,
-                        int nb, int64_t sb, int64_t sc) {
+                        int nb, int64_t sb, int64_t sc, float* next32) {
     const dim3 kgrid(dot_blocks(nb), nb);
-    VKMG_KDISPATCH(j, dcgs_update_kernel, V, ldv, j, c, u, w, next, n, cf, sb, sc);
+    VKMG_KDISPATCH(j, dcgs_update_kernel, V, ldv, j, c, u, w, next, n, cf, sb, sc, next32);
 }
 
 void launch_axpy_multi(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t n,

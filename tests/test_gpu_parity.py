@@ -310,6 +310,34 @@ def test_fgmres_graph_replays_match_direct_launches(precision):
     sd.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fgmres_pipelined_steps_stop_where_direct_launches_do(precision):
+    """With graphs the next Arnoldi step is enqueued before the host has
+    tested the current one (unless convergence is predicted).  Across
+    tolerances that stop the solve at different steps of a cycle, short
+    restarts, an iteration cap and a fixed iteration count, the iteration
+    counts, statuses and iterates equal those of direct launches (which never
+    run ahead)."""
+    N, levels = 32, 4
+    sg = vk.VkmgSolver(N, levels, precision=precision, graphs=True)
+    sd = vk.VkmgSolver(N, levels, precision=precision, graphs=False)
+    _, b, xl, _ = _manufactured_system(N)
+    bg = dev(b)
+    cases = [(rt, 30, 200) for rt in (1e-1, 3e-3, 1e-4, 2e-6, 1e-8, 5e-10, 1e-11)]
+    cases += [(1e-9, 3, 200), (1e-9, 5, 200), (1e-12, 30, 7), (0.0, 30, 9)]
+    for rtol, restart, iters in cases:
+        note(f"pipelined {precision} rtol={rtol} restart={restart} max_iters={iters}")
+        xg, xd = dev(xl), dev(xl)
+        ig = sg.fgmres_solve(bg, xg, rtol=rtol, restart=restart, max_iters=iters)
+        idr = sd.fgmres_solve(bg, xd, rtol=rtol, restart=restart, max_iters=iters)
+        assert (ig["iterations"], ig["restarts"], ig["status_name"]) == \
+            (idr["iterations"], idr["restarts"], idr["status_name"])
+        assert ig["true_rel_res"] == idr["true_rel_res"]
+        assert torch.equal(xg, xd)
+    sg.close()
+    sd.close()
+
+
 def test_fgmres_restarts_match_oracle():
     N, levels = 16, 3
     s = solver(N, levels)

@@ -93,6 +93,25 @@ def test_force_gradient_matches_oracle():
     s.close()
 
 
+def test_force_gradient_fp32_multigrid_matches_oracle():
+    """The same gradient with the FP32 V-cycle inside the FP64 FGMRES of both
+    the forward and the adjoint solve (rtol 1e-10; the preconditioner's
+    precision changes the iterates, not what they converge to)."""
+    N, levels = 16, 3
+    s = vk.VkmgSolver(N, levels, precision="fp32")
+    f, xt = _problem(N)
+    fd = dev(f.ravel()).requires_grad_(True)
+    x = stokes_solve(fd, s, rtol=1e-10)
+    loss = 0.5 * torch.sum((x - dev(xt)) ** 2)
+    loss.backward()
+    g_gpu = host(fd.grad)
+    xo = adjoint.solve(N, f)
+    assert np.linalg.norm(host(x) - xo) <= 1e-7 * np.linalg.norm(xo)
+    g_or = adjoint.force_gradient(N, xo - xt).ravel()
+    assert np.linalg.norm(g_gpu - g_or) <= 1e-5 * np.linalg.norm(g_or)
+    s.close()
+
+
 def test_force_gradient_matches_central_differences():
     N, levels = 16, 3
     s = vk.VkmgSolver(N, levels)

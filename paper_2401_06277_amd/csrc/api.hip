@@ -266,7 +266,10 @@ void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
 
 // r32_ready (FP32 multigrid): the top level's b already holds r rounded to
 // FP32 (written by the Gram-Schmidt kernel that produced r).
-void vcycle_impl(vkmg_ctx* c, const double* r, double* z, hipStream_t s, bool r32_ready = false) {
+// z32_only (FP32 multigrid): z is left in FP32 in the top level's x and not
+// written (launch_apply_widen writes it next to A z).
+void vcycle_impl(vkmg_ctx* c, const double* r, double* z, hipStream_t s, bool r32_ready = false,
+                 bool z32_only = false) {
     const int top = c->L - 1;
     if (c->opt.mg_precision == VKMG_FP64) {
         mg_t<double>(c, top, r, z, s);
@@ -275,7 +278,8 @@ void vcycle_impl(vkmg_ctx* c, const double* r, double* z, hipStream_t s, bool r3
         if (!r32_ready)
             launch_cast<double, float>(r, static_cast<float*>(L.b), L.g.n * c->nb(), s);
         mg_t<float>(c, top, static_cast<const float*>(L.b), static_cast<float*>(L.x), s);
-        launch_cast<float, double>(static_cast<const float*>(L.x), z, L.g.n * c->nb(), s);
+        if (!z32_only)
+            launch_cast<float, double>(static_cast<const float*>(L.x), z, L.g.n * c->nb(), s);
     }
 }
 
@@ -1238,10 +1242,16 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
         const int kb = j + 1;
         // delayed scheme, FP32 multigrid: the V-cycle input of step j >= 1
         // was rounded to FP32 by the update kernel of step j-1
-        vcycle_impl(ctx, vj, zj, ss, delayed && fp32_mg && j >= 1);
+        // FP32 multigrid: z_j stays FP32 and the apply w = A z_j writes it
+        // widened into the basis
+        vcycle_impl(ctx, vj, zj, ss, delayed && fp32_mg && j >= 1, fp32_mg);
         {
             Timed t(ctx, VKMG_KERNEL_RESIDUAL, ss);
-            launch_residual<double, double>(g, nullptr, zj, w, 1, ss, 1, ctx->nu64);
+            if (fp32_mg)
+                launch_apply_widen(g, static_cast<const float*>(ctx->lev.back().x), w, zj, ss,
+                                   ctx->nu64);
+            else
+                launch_residual<double, double>(g, nullptr, zj, w, 1, ss, 1, ctx->nu64);
         }
         if (delayed) {
             Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);

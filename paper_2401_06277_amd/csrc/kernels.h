@@ -22,6 +22,11 @@ template <typename Tx, typename T>
 void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hipStream_t s,
                      int nb = 1, const T* nue = nullptr);
 
+// y = A x (FP64 operator, as launch_residual mode 1) for an FP32 x, which is
+// also written widened to FP64 into x64 (one right-hand side).
+void launch_apply_widen(const Geom& g, const float* x, double* y, double* x64, hipStream_t s,
+                        const double* nue = nullptr);
+
 // x2 = x + P ec (the prolongation of the coarse correction ec, as
 // launch_prolong_add) and r = b - A x2 in one pass over the fine level g
 // (coarse level gc); x is not modified.  nue as for launch_residual.

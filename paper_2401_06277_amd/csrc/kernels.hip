@@ -216,7 +216,9 @@ __device__ __forceinline__ void stage_prolonged(const Geom& g, const Geom& gc, c
 // stages x + P ec (ec on the coarse level gc, the arithmetic of
 // prolong_kernel, so the sums are the same), writes it to x2 for the nodes
 // whose rows it computes, and forms r = b - A (x + P ec).
-template <int MODE, typename Tx, typename T, bool VAR = false, bool PRO = false>
+// COPY: x converted to T is also written to x2 for those nodes (an FP32 x
+// widened to FP64 next to its FP64 operator apply).
+template <int MODE, typename Tx, typename T, bool VAR = false, bool PRO = false, bool COPY = false>
 __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void residual_kernel(Geom g, const T* __restrict__ b,
                                                        const Tx* __restrict__ x,
                                                        T* __restrict__ r,
@@ -237,14 +239,12 @@ __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void r
         if (MODE == 0) b += bo;
         x += bo;
         r += bo;
-        if (PRO) {
-            x2 += bo;
-            ec += int64_t(blockIdx.y) * gc.n;
-        }
+        if (PRO || COPY) x2 += bo;
+        if (PRO) ec += int64_t(blockIdx.y) * gc.n;
     }
     const int E0x = (tlin % tiles) * RT, E0y = (tlin / tiles) * RT;
     const int ox = 2 * E0x - 2, oy = 2 * E0y - 2;
-    if (PRO) {
+    if constexpr (PRO) {
         stage_prolonged(g, gc, x, ec, E0x, E0y, s_u[0], s_u[1], s_p);
     } else {
     // every load of the tile is issued before the first is used: addresses
@@ -364,9 +364,9 @@ __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void r
             vx = T(x[q]);  // Dirichlet row: identity (edge tiles only)
             vy = T(x[g.nq2 + q]);
         }
-        if (PRO) {  // x + P ec: unchanged on Dirichlet nodes
-            x2[q] = dir ? vx : s_u[0][c2 + bb * RQ2 + aa];
-            x2[g.nq2 + q] = dir ? vy : s_u[1][c2 + bb * RQ2 + aa];
+        if (PRO || COPY) {  // x + P ec (PRO) or x (COPY); Dirichlet: x
+            x2[q] = dir ? T(x[q]) : s_u[0][c2 + bb * RQ2 + aa];
+            x2[g.nq2 + q] = dir ? T(x[g.nq2 + q]) : s_u[1][c2 + bb * RQ2 + aa];
         }
         if (MODE == 0) {
             r[q] = bx[aa] - vx;
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void r
         }
     }
     if (bb == 0) r[qp] = (MODE == 0) ? bp - ap : ap;
-    if (PRO && bb == 0) x2[qp] = s_p[c1];
+    if ((PRO || COPY) && bb == 0) x2[qp] = s_p[c1];
 }
 
 // ---------------------------------------------------------------------------
@@ -2154,6 +2154,18 @@ void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hip
 }
 template void launch_residual<double, double>(const Geom&, const double*, const double*, double*,
                                               int, hipStream_t, int, const double*);
+
+void launch_apply_widen(const Geom& g, const float* x, double* y, double* x64, hipStream_t s,
+                        const double* nue) {
+    const int tiles = (g.N + 1 + RT - 1) / RT;
+    const dim3 grid(8 * ((tiles * tiles + 7) / 8), 1);
+    if (nue)
+        residual_kernel<1, float, double, true, false, true><<<grid, RNT, 0, s>>>(
+            g, nullptr, x, y, nue, Geom{}, nullptr, x64);
+    else
+        residual_kernel<1, float, double, false, false, true><<<grid, RNT, 0, s>>>(
+            g, nullptr, x, y, nullptr, Geom{}, nullptr, x64);
+}
 
 template <typename T>
 void launch_residual_prolong(const Geom& g, const Geom& gc, const T* b, const T* x, const T* ec,

@@ -459,18 +459,26 @@ vkmg_status fgmres_batched(vkmg_ctx* ctx, const double* b, double* x, double rto
             q.est = q.true_rel = 0.0;
         }
     }
+    // FP32 multigrid: as in the single solve, the update kernel rounds the
+    // next V-cycle inputs and the apply widens the V-cycle outputs
+    const bool fp32_mg = ctx->opt.mg_precision == VKMG_FP32;
     auto step = [&](int j, hipStream_t ss) {
         double* vj = V + int64_t(j) * S;
         double* zj = Z + int64_t(j) * S;
-        vcycle_impl(ctx, vj, zj, ss);
+        vcycle_impl(ctx, vj, zj, ss, fp32_mg && j >= 1, fp32_mg);
         {
             Timed t(ctx, VKMG_KERNEL_RESIDUAL, ss);
-            launch_residual<double, double>(g, nullptr, zj, w, 1, ss, B, ctx->nu64);
+            if (fp32_mg)
+                launch_apply_widen(g, static_cast<const float*>(ctx->lev.back().x), w, zj, ss,
+                                   ctx->nu64, B);
+            else
+                launch_residual<double, double>(g, nullptr, zj, w, 1, ss, B, ctx->nu64);
         }
         Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);
         launch_dcgs_dots(V, S, j, vj, w, n, ctx->part, ss, B, n);
         launch_reduce_partials(ctx->part, 2 * j + 3, dco, ss, B, HS);
-        launch_dcgs_update(V, S, j, dco, vj, w, V + int64_t(j + 1) * S, n, dcf, ss, B, n, HS);
+        launch_dcgs_update(V, S, j, dco, vj, w, V + int64_t(j + 1) * S, n, dcf, ss, B, n, HS,
+                           fp32_mg ? static_cast<float*>(ctx->lev.back().b) : nullptr);
     };
     const bool use_graphs = ctx->opt.use_graphs != 0 && ctx->timing_mask == 0;
     if (use_graphs && ctx->graphs_scheme != 2) {

@@ -23,9 +23,9 @@ void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hip
                      int nb = 1, const T* nue = nullptr);
 
 // y = A x (FP64 operator, as launch_residual mode 1) for an FP32 x, which is
-// also written widened to FP64 into x64 (one right-hand side).
+// also written widened to FP64 into x64.
 void launch_apply_widen(const Geom& g, const float* x, double* y, double* x64, hipStream_t s,
-                        const double* nue = nullptr);
+                        const double* nue = nullptr, int nb = 1);
 
 // x2 = x + P ec (the prolongation of the coarse correction ec, as
 // launch_prolong_add) and r = b - A x2 in one pass over the fine level g

@@ -2156,9 +2156,9 @@ template void launch_residual<double, double>(const Geom&, const double*, const 
                                               int, hipStream_t, int, const double*);
 
 void launch_apply_widen(const Geom& g, const float* x, double* y, double* x64, hipStream_t s,
-                        const double* nue) {
+                        const double* nue, int nb) {
     const int tiles = (g.N + 1 + RT - 1) / RT;
-    const dim3 grid(8 * ((tiles * tiles + 7) / 8), 1);
+    const dim3 grid(8 * ((tiles * tiles + 7) / 8), nb);
     if (nue)
         residual_kernel<1, float, double, true, false, true><<<grid, RNT, 0, s>>>(
             g, nullptr, x, y, nue, Geom{}, nullptr, x64);

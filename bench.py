@@ -87,6 +87,9 @@ def parse():
                     help="skip the 256x256 per-element viscosity solves and gradients")
     ap.add_argument("--interior-apply", choices=["vector", "matrix"], default="vector",
                     help="interior Vanka apply: vector ALUs (default) or matrix cores")
+    ap.add_argument("--vcycle-only", action="store_true",
+                    help="only set up the FP64 (and FP32) contexts and time V-cycles: the "
+                         "median cycle and the per-level kernel table (for profiling)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB "
                          "(3 times) and exit: the reference kernel for scaling HBM "
@@ -160,6 +163,72 @@ def vcycle_roofline(N, L, bw):
     nbytes = sum(b for _, b, _ in terms)
     flops = sum(f for _, _, f in terms)
     return t_roof, nbytes, flops
+
+
+def vcycle_level_table(s, vk, torch, r, z, N, L, reps=20):
+    """Kernel time per V-cycle by level and kernel class, from HIP events
+    around every launch on the cycle's stream (launch by launch, no graph)."""
+    classes = {"vanka": vk.KERNEL_VANKA, "residual": vk.KERNEL_RESIDUAL,
+               "transfer": vk.KERNEL_TRANSFER, "coarse": vk.KERNEL_COARSE}
+    s.set_timing(sum(1 << c for c in classes.values()))
+    for _ in range(reps):
+        s.vcycle(r, z)
+    torch.cuda.synchronize()
+    rows = []
+    for l in range(L - 1, -1, -1):
+        row = {"level": l, "N": N >> (L - 1 - l)}
+        tot = 0.0
+        for k, c in classes.items():
+            n, ms = s.kernel_timing(c, l)
+            if n:
+                row[f"{k}_us"] = round(ms * 1e3 / reps, 2)
+                row[f"{k}_launches"] = n // reps
+                tot += ms * 1e3 / reps
+        row["total_us"] = round(tot, 2)
+        rows.append(row)
+    s.set_timing(0)
+    return rows
+
+
+def timed_vcycles(s, torch, r, z, reps=20, warm=5):
+    """Median of `reps` V-cycles (HIP events around each on the current stream)."""
+    for _ in range(warm):
+        s.vcycle(r, z)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.vcycle(r, z)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def vcycle_only(a):
+    """Set up the benchmark's contexts and time V-cycles only (for
+    profiling): median cycle in both precisions and the per-level table."""
+    import torch
+
+    import paper_2401_06277_amd as vk
+    from stokes_inputs import uniform_vector, velocity_dirichlet_mask
+
+    torch.cuda.set_device(0)
+    N, L = a.N, a.levels
+    out = {"N": N, "levels": L}
+    for prec in ("fp64", "fp32"):
+        log(f"[bench] V-cycles {prec}")
+        s = vk.VkmgSolver(N, L, precision=prec, interior_apply=a.interior_apply)
+        n = s.layout["n"]
+        rh = uniform_vector(n, 170)
+        rh[velocity_dirichlet_mask(N)] = 0.0
+        r = torch.from_numpy(rh).cuda()
+        z = torch.empty_like(r)
+        out[f"vcycle_s_{prec}"] = timed_vcycles(s, torch, r, z)
+        out[f"levels_{prec}"] = vcycle_level_table(s, vk, torch, r, z, N, L)
+        s.close()
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(N, levels, nvc, c2=None):
@@ -276,7 +345,7 @@ def bench_c2(a, vk, torch, np):
                                      "patch_updates_per_s": (N2 + 1) ** 2 / t_full}
         b = s.assemble_rhs(torch.from_numpy(fn2.ravel()).cuda(),
                            torch.from_numpy(gd2.ravel()).cuda())
-        x0 = torch.where(torch.from_numpy(mask).cuda(), b, torch.zeros_like(b))
+        x0 = s.dirichlet_lift(b)
         x = x0.clone()
         s.fgmres_solve(b, x, rtol=1e-8)  # warm
         torch.cuda.synchronize()
@@ -301,13 +370,12 @@ def bench_c4(a, vk, torch, np):
     multigrid.  Times exclude setup and the right-hand-side assembly."""
     from concurrent.futures import ThreadPoolExecutor
 
-    from stokes_inputs import gaussian_random_field, lid_boundary_values, velocity_dirichlet_mask
+    from stokes_inputs import gaussian_random_field, lid_boundary_values
 
     N4, L4, B = 512, 7, a.c4_batch
     with ThreadPoolExecutor(8) as ex:
         fs = list(ex.map(lambda k: gaussian_random_field(N4, 1000 + k).ravel(), range(B)))
     g = lid_boundary_values(N4).ravel()
-    mask = torch.from_numpy(velocity_dirichlet_mask(N4)).cuda()
     ups = sum(4 * ((N4 >> (L4 - 1 - l)) + 1) ** 2 for l in range(1, L4))
     res = {"config": (f"512x512 elements, 7 levels, {B} right-hand sides (GRF body force l=0.1 "
                       "seeds 1000+k, lid u=(1,0) on the top edge), FGMRES(30) rtol 1e-8, "
@@ -320,7 +388,7 @@ def bench_c4(a, vk, torch, np):
         s = vk.VkmgSolver(N4, L4, precision=prec, interior_apply=a.interior_apply, batch=B)
         n = s.layout["n"]
         b = s.assemble_rhs(fd, gd)
-        x0 = torch.where(mask.repeat(B), b, torch.zeros_like(b))
+        x0 = s.dirichlet_lift(b)
         x = x0.clone()
         s.fgmres_solve(b, x, rtol=1e-8, restart=30, max_iters=500)  # warm (captures graphs)
         x = x0.clone()
@@ -342,13 +410,13 @@ def bench_c4(a, vk, torch, np):
         log(f"[bench] 512x512 x{B} sequential {prec}")
         s1 = vk.VkmgSolver(N4, L4, precision=prec, interior_apply=a.interior_apply)
         bs = [s1.assemble_rhs(fd[k * len(g):(k + 1) * len(g)], gd[:len(g)]) for k in range(B)]
-        x1 = torch.where(mask, bs[0], torch.zeros_like(bs[0]))
+        x1 = s1.dirichlet_lift(bs[0])
         s1.fgmres_solve(bs[0], x1, rtol=1e-8, restart=30, max_iters=500)  # warm
         xs, its1 = [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(B):
-            x1 = torch.where(mask, bs[k], torch.zeros_like(bs[k]))
+            x1 = s1.dirichlet_lift(bs[k])
             info = s1.fgmres_solve(bs[k], x1, rtol=1e-8, restart=30, max_iters=500)
             its1.append(info["iterations"])
             xs.append(x1)
@@ -531,6 +599,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
                                    "not supported (use --gpus 1)"}))
         sys.exit(2)
+    if a.vcycle_only:
+        vcycle_only(a)
+        return
     import numpy as np
     import torch
 

@@ -233,6 +233,18 @@ vkmg_status vkmg_viscosity_gradient(vkmg_ctx* ctx, const double* lam, const doub
 vkmg_status vkmg_remove_pressure_mean(vkmg_ctx* ctx, double* x, void* stream);
 
 /*
+ * Dirichlet lifting of an FP64 finest-level vector: x = b on the Dirichlet
+ * DoFs (both velocity components at every boundary Q2 node; paper, section
+ * "Problem setup": Dirichlet velocity on every edge), x = 0 on every other
+ * DoF.  Since the Dirichlet rows of the constrained system are identity
+ * rows with b_D = g_D, lifting the right-hand side gives the initial guess
+ * that vkmg_fgmres_solve expects (and, for an adjoint system A lam = r,
+ * the exact values of lam on the decoupled Dirichlet rows).  b, x: n
+ * doubles (B vectors in a batched context); x may alias b.  Asynchronous.
+ */
+vkmg_status vkmg_dirichlet_lift(vkmg_ctx* ctx, const double* b, double* x, void* stream);
+
+/*
  * One additive Vanka sweep on `level` (1 <= level <= levels-1), in the
  * context's multigrid precision (x, b are double for VKMG_FP64 contexts and
  * float for VKMG_FP32 contexts): r = b - A_l x, then

@@ -35,7 +35,7 @@ STATUS = {
 EXPORTED = [
     "vkmg_default_options", "vkmg_setup", "vkmg_setup_viscosity", "vkmg_destroy", "vkmg_layout_of", "vkmg_level_layout",
     "vkmg_num_levels", "vkmg_residual", "vkmg_apply", "vkmg_assemble_rhs", "vkmg_vanka_sweep",
-    "vkmg_vanka_update", "vkmg_relax", "vkmg_assemble_rhs_adjoint", "vkmg_remove_pressure_mean",
+    "vkmg_vanka_update", "vkmg_relax", "vkmg_assemble_rhs_adjoint", "vkmg_remove_pressure_mean", "vkmg_dirichlet_lift",
     "vkmg_viscosity_gradient",
     "vkmg_restrict", "vkmg_prolong_add", "vkmg_coarse_solve", "vkmg_vcycle",
     "vkmg_fgmres_solve", "vkmg_set_timing", "vkmg_kernel_timing", "vkmg_host_patch_matrix",
@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH):
         "vkmg_relax": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_assemble_rhs_adjoint": (c_int32, [P, P, P, P]),
         "vkmg_remove_pressure_mean": (c_int32, [P, P, P]),
+        "vkmg_dirichlet_lift": (c_int32, [P, P, P, P]),
         "vkmg_viscosity_gradient": (c_int32, [P, P, P, P, P]),
         "vkmg_restrict": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_prolong_add": (c_int32, [P, c_int32, P, P, P]),
@@ -197,6 +198,10 @@ class VkmgSolver:
         self.N, self.levels, self.nu, self.batch = N, levels, nu, batch
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.mg_dtype = torch.float32 if precision == "fp32" else torch.float64
+        # the field on the device, for the identity check of the tensors
+        # passed to the differentiable solve (check_viscosity)
+        self._nu_dev = None if nu_elem is None else torch.from_numpy(arr).to(self.device)
+        self._nu_checked = None
 
     # ---------------------------------------------------------------- plumbing
     def _stream(self):
@@ -233,6 +238,20 @@ class VkmgSolver:
 
     def __exit__(self, *exc):
         self.close()
+
+    def check_viscosity(self, nu):
+        """Raise unless `nu` (a device tensor of N*N values) holds the
+        per-element viscosity this context was set up with.  Compared on the
+        device, once per tensor version (no host copy)."""
+        if self._nu_dev is None:
+            raise ValueError("nu given but the solver has a constant viscosity")
+        key = (nu.data_ptr(), nu._version, nu.numel(), str(nu.device))
+        if key == self._nu_checked:
+            return
+        if nu.numel() != self._nu_dev.numel() or not self._torch.equal(
+                nu.detach().reshape(-1).to(self._nu_dev.device, self._torch.float64), self._nu_dev):
+            raise ValueError("nu differs from the field the solver was set up with")
+        self._nu_checked = key
 
     # ---------------------------------------------------------------- queries
     @property
@@ -283,19 +302,15 @@ class VkmgSolver:
         _check(st, "vkmg_assemble_rhs")
         return b
 
-    def dirichlet_mask(self):
-        """Boolean tensor (n * batch) marking the Dirichlet velocity DoFs
-        (boundary Q2 nodes, both components): where vkmg_fgmres_solve's
-        initial guess must carry the boundary values of b."""
-        if getattr(self, "_dmask", None) is None:
-            lay = self.layout
-            s2 = lay["q2_side"]
-            node = self._torch.zeros((s2, s2), dtype=self._torch.bool)
-            node[0, :] = node[-1, :] = node[:, 0] = node[:, -1] = True
-            m = self._torch.zeros(lay["n"], dtype=self._torch.bool)
-            m[:2 * s2 * s2] = node.reshape(-1).repeat(2)
-            self._dmask = m.repeat(self.batch).to(self.device)
-        return self._dmask
+    def dirichlet_lift(self, b, x=None):
+        """x = b on the Dirichlet DoFs, 0 elsewhere (vkmg_dirichlet_lift):
+        the initial guess vkmg_fgmres_solve expects for right-hand side b."""
+        n = self.layout["n"] * self.batch
+        x = self._empty(n, self._torch.float64) if x is None else x
+        st = _lib.vkmg_dirichlet_lift(self._ctx, self._ptr(b, self._torch.float64, n, "b"),
+                                      self._ptr(x, self._torch.float64, n, "x"), self._stream())
+        _check(st, "vkmg_dirichlet_lift")
+        return x
 
     def assemble_rhs_adjoint(self, lam, grad_f=None):
         """Transpose of the force-to-load map of assemble_rhs applied to lam."""

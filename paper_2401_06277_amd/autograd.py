@@ -22,7 +22,6 @@ only supplies the tensors.
 
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from ._vkmg import VkmgError
@@ -33,7 +32,7 @@ class _StokesSolve(torch.autograd.Function):
     def forward(ctx, f, nu, solver, g, rtol, restart, max_iters):
         b = solver.assemble_rhs(f.detach().contiguous(), g)
         # initial guess: the Dirichlet lifting (boundary rows of b)
-        x = torch.where(solver.dirichlet_mask(), b, torch.zeros_like(b))
+        x = solver.dirichlet_lift(b)
         info = solver.fgmres_solve(b, x, rtol=rtol, restart=restart, max_iters=max_iters)
         _require_converged(info, "forward solve")
         solver.remove_pressure_mean(x)
@@ -51,7 +50,7 @@ class _StokesSolve(torch.autograd.Function):
         solver.remove_pressure_mean(rhs)
         # the adjoint's Dirichlet rows are identity rows decoupled from the
         # free DoFs: start from their exact values
-        lam = torch.where(solver.dirichlet_mask(), rhs, torch.zeros_like(rhs))
+        lam = solver.dirichlet_lift(rhs)
         info = solver.fgmres_solve(rhs, lam, rtol=rtol, restart=restart, max_iters=max_iters)
         _require_converged(info, "adjoint solve")
         grad_f = solver.assemble_rhs_adjoint(lam) if ctx.needs_input_grad[0] else None
@@ -73,11 +72,7 @@ def stokes_solve(f, solver, g=None, nu=None, rtol: float = 1e-10, restart: int =
     differentiable with respect to f and, for solvers set up with a
     per-element viscosity, to that viscosity passed as `nu`."""
     if nu is not None:
-        ref = getattr(solver, "nu_elem", None)
-        if ref is None:
-            raise ValueError("nu given but the solver has a constant viscosity")
-        if not np.array_equal(nu.detach().cpu().numpy().ravel(), ref):
-            raise ValueError("nu differs from the field the solver was set up with")
+        solver.check_viscosity(nu)
     else:
         nu = torch.zeros(0, dtype=torch.float64, device=f.device)
     return _StokesSolve.apply(f, nu, solver, g, rtol, restart, max_iters)

@@ -1008,6 +1008,14 @@ vkmg_status vkmg_remove_pressure_mean(vkmg_ctx* ctx, double* x, void* stream) {
     return VKMG_OK;
 }
 
+vkmg_status vkmg_dirichlet_lift(vkmg_ctx* ctx, const double* b, double* x, void* stream) {
+    if (!ctx || !b || !x) return fail(VKMG_ERR_INVALID_ARG, "dirichlet_lift: NULL argument");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    launch_lift(ctx->top(), b, x, as_stream(stream), ctx->nb());
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
 vkmg_status vkmg_vanka_sweep(vkmg_ctx* ctx, int32_t level, void* x, const void* b, void* stream) {
     if (!x || !b || !check_level(ctx, level, true))
         return fail(VKMG_ERR_INVALID_ARG, "vanka_sweep: NULL argument or level not in [1, levels)");

@@ -103,6 +103,8 @@ template <typename T>
 void launch_fill_zero(T* x, int64_t n, hipStream_t s);
 template <typename Ti, typename To>
 void launch_cast(const Ti* in, To* out, int64_t n, hipStream_t s);
+// x = b on the Dirichlet DoFs of level g, 0 elsewhere (nb vectors, FP64).
+void launch_lift(const Geom& g, const double* b, double* x, hipStream_t s, int nb = 1);
 
 // Krylov kernels (FP64).  V: k vectors of length n with stride ldv; with
 // nb > 1 the batch entries of every vector are sb apart.  Partial sums:

@@ -1779,6 +1779,23 @@ __global__ void fill_zero_kernel(T* __restrict__ x, int64_t n) {
         x[i] = T(0);
 }
 
+// Dirichlet lifting: x = b on the Dirichlet DoFs (both velocity components
+// at the boundary Q2 nodes), 0 elsewhere, for nb vectors of g.n back to back.
+__global__ void lift_kernel(Geom g, const double* __restrict__ b, double* __restrict__ x,
+                            int64_t total) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t k = i % g.n;
+        bool dir = false;
+        if (k < 2 * g.nq2) {
+            const int64_t node = k % g.nq2;
+            const int qi = int(node % g.s2), qj = int(node / g.s2);
+            dir = qi == 0 || qj == 0 || qi == g.s2 - 1 || qj == g.s2 - 1;
+        }
+        x[i] = dir ? b[i] : 0.0;
+    }
+}
+
 template <typename Ti, typename To>
 __global__ void cast_kernel(const Ti* __restrict__ in, To* __restrict__ out, int64_t n) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
@@ -2325,6 +2342,11 @@ void launch_cast(const Ti* in, To* out, int64_t n, hipStream_t s) {
 }
 template void launch_cast<double, float>(const double*, float*, int64_t, hipStream_t);
 template void launch_cast<float, double>(const float*, double*, int64_t, hipStream_t);
+
+void launch_lift(const Geom& g, const double* b, double* x, hipStream_t s, int nb) {
+    const int64_t total = g.n * nb;
+    lift_kernel<<<elementwise_blocks(total), 256, 0, s>>>(g, b, x, total);
+}
 
 void launch_scale(const double* in, double alpha, double* out, int64_t n, hipStream_t s) {
     scale_kernel<<<elementwise_blocks(n), 256, 0, s>>>(in, alpha, out, n);

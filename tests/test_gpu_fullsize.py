@@ -3,11 +3,14 @@ configuration that the benchmark times.
 
 The oracle cannot assemble this system in test time, so the local steps are
 compared at sampled outputs that it computes one at a time from the element
-matrices (residual rows, Vanka updates, transfer rows), and the global ones
-through properties that hold at any size: multigrid contraction, FGMRES
-convergence to the requested residual, the Taylor-Hood convergence orders
-between 512 x 512 and 1024 x 1024, and the mixed-precision solve meeting the
-same residual.  Samples cover every boundary class, tile seams of the Vanka
+matrices (residual rows, Vanka updates, transfer rows); the global ones are
+compared with values the oracle wrote beforehand for this exact workload
+(tests/golden/c3_oracle_1024.json, written by make_c3_oracle.py beside it:
+one V-cycle and the FGMRES solve at sampled DoFs, the iteration count), and
+checked through properties that hold at any size: multigrid contraction,
+FGMRES convergence to the requested residual, the Taylor-Hood convergence
+orders between 512 x 512 and 1024 x 1024, and the mixed-precision solve
+meeting the same residual.  Samples cover every boundary class, tile seams of the Vanka
 and residual kernels and random interior DoFs.
 """
 
@@ -241,3 +244,75 @@ def test_fullsize_fp32_multigrid_matches_fp64():
     err = np.linalg.norm(a - c) / np.linalg.norm(c)
     note(f"fp32-MG vs fp64 solution rel diff {err:.3e}")
     assert err <= 1e-5
+
+
+# ------------------------------------------------------- oracle golden values
+
+def _golden(golden_dir):
+    import json
+    import os
+    with open(os.path.join(golden_dir, "c3_oracle_1024.json")) as fh:
+        d = json.load(fh)
+    assert d["N"] == N_FULL and d["levels"] == LEVELS_FULL
+    return d
+
+
+def _per_field_sampled(got, want, dofs, field_max, tol, what):
+    """Errors at the sampled DoFs, each field against the magnitude of the
+    whole field (from the oracle's full vector)."""
+    g = grid_sizes(N_FULL)
+    field = np.searchsorted([g.off_uy, g.off_p], dofs, side="right")
+    worst = []
+    for f in range(3):
+        sel = field == f
+        assert sel.sum() > 1000, (what, f, sel.sum())
+        err = np.abs(got[sel] - want[sel]).max() / field_max[f]
+        worst.append(err)
+    note(f"{what}: per-field max error at {len(dofs)} samples {['%.2e' % e for e in worst]}")
+    assert max(worst) <= tol, (what, worst)
+
+
+def test_fullsize_vcycle_matches_oracle_golden(golden_dir):
+    """One FP64 V(2,2) cycle at 1024 x 1024 (the launch configuration of the
+    benchmark: parked tile kernel on the two finest levels, separate
+    prolongation above 256 x 256) against the oracle's cycle written by
+    tests/golden/make_c3_oracle.py, at ~5600 sampled DoFs: 1e-11 per field
+    (u_x, u_y, p each against its whole-field maximum)."""
+    d = _golden(golden_dir)
+    s = solver()
+    g = grid_sizes(N_FULL)
+    r = uniform_vector(g.n, d["vcycle_input"]["seed"])
+    r[velocity_dirichlet_mask(N_FULL)] = 0.0
+    z = host(s.vcycle(dev(r)))
+    dofs = np.array(d["dofs"])
+    _per_field_sampled(z[dofs], np.array(d["vcycle"]), dofs, d["vcycle_field_max"], 1e-11,
+                       "V-cycle vs oracle")
+
+
+def test_fullsize_fgmres_matches_oracle_golden(golden_dir):
+    """The benchmark's solve (GRF force seed 5, x0 = 0, FGMRES(30), rtol
+    1e-8) against the oracle's (tests/golden/make_c3_oracle.py): iteration
+    count within one of the oracle's; after exactly the oracle's count
+    (rtol 0 and that cap) the solution, pressure reduced to zero
+    mass-weighted mean, within 1e-10 per field at the sampled DoFs, and the
+    true relative residual equal to the oracle's to 1e-3 relative."""
+    d = _golden(golden_dir)
+    s = solver()
+    g = grid_sizes(N_FULL)
+    f = gaussian_random_field(N_FULL, 5, length=0.1)
+    b = s.assemble_rhs(dev(f.ravel()))
+    x = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info = s.fgmres_solve(b, x, rtol=1e-8, restart=30, max_iters=500)
+    note(f"fgmres N={N_FULL}: {info}; oracle {d['iterations']} iterations, "
+         f"true rel res {d['true_rel_res']:.3e}")
+    assert info["status_name"] == "VKMG_OK"
+    assert abs(info["iterations"] - d["iterations"]) <= 1
+    k = d["iterations"]
+    x = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info_k = s.fgmres_solve(b, x, rtol=0.0, restart=30, max_iters=k)
+    assert info_k["iterations"] == k
+    assert abs(info_k["true_rel_res"] - d["true_rel_res"]) <= 1e-3 * d["true_rel_res"]
+    xn = fem.normalise_pressure(N_FULL, host(x))
+    dofs = np.array(d["dofs"])
+    _per_field_sampled(xn[dofs], np.array(d["solution"]), dofs, d["solution_field_max"], 1e-10,
+                       f"FGMRES solution after {k} steps vs oracle")

@@ -1,6 +1,8 @@
 """GPU parity: every step of the hot path through the C ABI against the CPU
 oracle on the same seeded inputs (small meshes spanning several tiles and
 ragged tails).  Tolerances (relative, FP64 path):
+(each of u_x, u_y and p against its own magnitude: after a sweep or a
+V-cycle the pressure is ~1/h^2 larger than the velocity)
   residual / operator apply / right-hand side / transfers   1e-13
   one Vanka sweep                                          1e-12
   coarse solve, V-cycle application                         1e-11
@@ -22,6 +24,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_2401_06277_amd as vk  # noqa: E402
+from fieldwise import rel, rel2  # noqa: E402  (each field against its own magnitude)
 
 
 def dev(a, dtype=None):
@@ -34,10 +37,6 @@ def dev(a, dtype=None):
 def host(t):
     torch.cuda.synchronize()
     return t.double().cpu().numpy()
-
-
-def rel(a, b):
-    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
 def note(msg):
@@ -274,7 +273,7 @@ def test_fgmres_iterations_and_solution(N, levels, name):
     ok = fgmres.fgmres(A, b, xl, H.vcycle, rtol=0.0, restart=30, fixed_iters=k)
     xa = fem.normalise_pressure(N, host(x))
     xo = fem.normalise_pressure(N, ok.x)
-    assert np.linalg.norm(xa - xo) <= 1e-10 * np.linalg.norm(xo)
+    assert rel2(xa, xo) <= 1e-10
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -351,7 +350,7 @@ def test_fgmres_restarts_match_oracle():
     assert info["restarts"] >= 1
     xa = fem.normalise_pressure(N, host(x))
     xo = fem.normalise_pressure(N, ro.x)
-    assert np.linalg.norm(xa - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert rel2(xa, xo) <= 1e-8
 
 
 def test_fgmres_long_restart_classical_path():
@@ -370,7 +369,7 @@ def test_fgmres_long_restart_classical_path():
     assert info["status_name"] == "VKMG_OK"
     assert abs(info["iterations"] - ro.iterations) <= 1
     xo = fem.normalise_pressure(N, ro.x)
-    assert np.linalg.norm(fem.normalise_pressure(N, host(x)) - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert rel2(fem.normalise_pressure(N, host(x)), xo) <= 1e-8
     x = dev(xl)
     info = s.fgmres_solve(dev(b), x, rtol=0.0, restart=40, max_iters=36)
     assert info["iterations"] == 36 and info["restarts"] == 0
@@ -378,7 +377,7 @@ def test_fgmres_long_restart_classical_path():
     xh = host(x)
     r0 = np.linalg.norm(b - A @ xl)
     assert np.linalg.norm(b - A @ xh) <= 1e-12 * r0
-    assert np.linalg.norm(fem.normalise_pressure(N, xh) - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert rel2(fem.normalise_pressure(N, xh), xo) <= 1e-8
 
 
 def test_fgmres_edge_cases():
@@ -445,8 +444,8 @@ def test_fp32_multigrid_fgmres_reaches_fp64_tolerance():
     # conditioning of the system times that tolerance
     xa = fem.normalise_pressure(N, host(x))
     xo = fem.normalise_pressure(N, ro.x)
-    note(f"fp32-MG vs fp64 oracle rel err {np.linalg.norm(xa - xo) / np.linalg.norm(xo):.3e}")
-    assert np.linalg.norm(xa - xo) <= 1e-5 * np.linalg.norm(xo)
+    note(f"fp32-MG vs fp64 oracle rel err per field {rel2(xa, xo):.3e}")
+    assert rel2(xa, xo) <= 1e-5
 
 
 def test_kernel_timing_counts_launches():

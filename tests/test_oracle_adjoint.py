@@ -61,3 +61,23 @@ def test_viscosity_gradient_matches_central_differences():
         eps = 1e-4
         fd = (loss(nu + eps * d) - loss(nu - eps * d)) / (2 * eps)
         assert abs(fd - float(grad @ d)) <= 1e-6 * abs(fd)
+
+
+def test_iterative_gradients_match_dense_path():
+    """The multigrid-FGMRES route to both gradients (for meshes too large for
+    dense solves) against the dense bordered solves, per-element viscosity
+    log nu ~ U[-1, 1]: solves to rtol 1e-12, gradients within 1e-9."""
+    N, levels = 16, 3
+    gs = grid_sizes(N)
+    f = gaussian_random_field(N, 3, length=0.3)
+    nu = np.exp(log_viscosity_field(N, 7))
+    xt = uniform_vector(gs.n, 4) * 0.01
+    x_hat, gf, gnu, fw, aw = adjoint.iterative_gradients(N, levels, f, lambda x: x - xt, nu,
+                                                          rtol=1e-12)
+    assert fw.converged and aw.converged
+    x = adjoint.solve(N, f, nu=nu)
+    assert np.linalg.norm(x_hat - x) <= 1e-9 * np.linalg.norm(x)
+    gf_d = adjoint.force_gradient(N, x - xt, nu=nu)
+    gnu_d = adjoint.viscosity_gradient(N, x - xt, x, nu)
+    assert np.linalg.norm(gf - gf_d) <= 1e-9 * np.linalg.norm(gf_d)
+    assert np.linalg.norm(gnu - gnu_d) <= 1e-9 * np.linalg.norm(gnu_d)

@@ -648,9 +648,10 @@ def main():
     classes = {"vanka": vk.KERNEL_VANKA, "residual": vk.KERNEL_RESIDUAL,
                "transfer": vk.KERNEL_TRANSFER, "coarse": vk.KERNEL_COARSE,
                "krylov": vk.KERNEL_KRYLOV}
-    s64.set_timing(sum(1 << c for c in classes.values()))
+    s64.set_timing(sum(1 << c for c in classes.values()) | (1 << vk.KERNEL_VANKA_TILE))
     dt64_ev, _, _ = run_solves(s64, b, x, a.steps, True)
     nl, ms = s64.kernel_timing(vk.KERNEL_VANKA, L - 1)
+    nt, ms_tile = s64.kernel_timing(vk.KERNEL_VANKA_TILE, L - 1)
     breakdown = {k: s64.kernel_timing(c)[1] / a.steps for k, c in classes.items()}
     s64.set_timing(0)
     for inf in inf64:
@@ -659,11 +660,19 @@ def main():
             sys.exit(1)
     x64 = x.clone()
     value = ups_per_cycle * sum(it64) / dt64
+    # algorithmic bytes of the finest-level updates, 8 bytes per scalar: each
+    # reads the residual and writes the iterate over all n DoFs, and reads
+    # the iterate too except in the first pre-smoothing sweep of a cycle,
+    # which starts from x = 0 (16 n bytes there, 24 n elsewhere); V(2,2):
+    # 4 updates per cycle, 22 n bytes per launch on average
+    per_cycle = 4
+    assert nl % per_cycle == 0 and nt == nl, (nl, nt)
+    alg_bytes_total = nl // per_cycle * (16 + 24 * (per_cycle - 1)) * n
+    alg_bytes = alg_bytes_total / nl
+    avg_tile_s = ms_tile / 1e3 / max(nt, 1)
     avg_launch_s = ms / 1e3 / max(nl, 1)
-    # algorithmic bytes of one finest-level Vanka update: read the residual
-    # and the iterate, write the iterate, 8 bytes each, over all n DoFs
-    alg_bytes = 3 * 8 * n
-    achieved = alg_bytes / avg_launch_s / 1e9
+    achieved = alg_bytes / avg_tile_s / 1e9
+    achieved_update = alg_bytes / avg_launch_s / 1e9
 
     # standalone V-cycle rate (median of 20)
     r = torch.randn(n, dtype=torch.float64, device="cuda")
@@ -724,20 +733,28 @@ def main():
                      "modelled",
         },
         "roofline": {
-            "kernel": ("Vanka update at the finest level (boundary-patch kernel + "
+            "kernel": ("interior-tile kernel of the finest-level Vanka update ("
                        + ("vanka_mfma_kernel" if a.interior_apply == "matrix"
-                          else "vanka_sweep_kernel") + ")"),
+                          else "vanka_sweep_kernel<double,false,true>") + ")"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(),
-            "launches": nl,
-            "avg_launch_us": avg_launch_s * 1e6,
+            "launches": nt,
+            "avg_launch_us": avg_tile_s * 1e6,
             "alg_bytes_per_launch": alg_bytes,
-            "timing": "HIP events around each finest-level update on the solve stream, "
-                      "event-timed pass of the same solves",
+            "alg_bytes_rule": "16 n bytes for the update from x = 0 (first pre-smoothing "
+                              "sweep), 24 n for the other three of each V(2,2) cycle; "
+                              "n = DoFs of the finest level",
+            "timing": "HIP events around each finest-level tile-kernel launch on the solve "
+                      "stream, event-timed pass of the same solves",
+            "with_boundary_kernel": {
+                "avg_launch_us": avg_launch_s * 1e6,
+                "achieved": achieved_update,
+                "frac": achieved_update / HBM_PEAK_GBS,
+            },
         },
     }
     s64.close()

@@ -120,7 +120,10 @@ typedef enum {
     VKMG_KERNEL_TRANSFER = 2,    /* restriction and prolongation */
     VKMG_KERNEL_COARSE = 3,      /* coarsest-level dense solve */
     VKMG_KERNEL_KRYLOV = 4,      /* FGMRES vector kernels */
-    VKMG_KERNEL_COUNT = 5
+    VKMG_KERNEL_VANKA_TILE = 5,  /* the interior-tile kernel of a Vanka update alone (the
+                                    boundary-patch kernel before it excluded); constant-
+                                    viscosity Vanka only */
+    VKMG_KERNEL_COUNT = 6
 } vkmg_kernel_class;
 
 /*

@@ -10,6 +10,10 @@ the Galerkin product P^T A P for constant viscosity, which a test checks);
 a per-element viscosity (array of N^2 values, index ey*N + ex) is coarsened
 by the arithmetic mean of the four children, and its Vanka patches are then
 all distinct ("simple" Vanka: one stored inverse per patch);
+with coarse_operator="galerkin" the coarse operators are instead the
+products A_{l-1} = P^T A_l P formed from the finest level down (identity
+rows on the coarse Dirichlet DoFs, whose columns of P are zero), the
+alternative for a per-element viscosity;
 the relaxation is the additive Vanka sweep (or, with relaxation="bs", the
 inexact Braess-Sarazin step of braess_sarazin.py), nu_pre sweeps before and
 nu_post after the coarse correction; the level-0 solve is exact, with the
@@ -22,8 +26,10 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.linalg as sla
+import scipy.sparse as sp
 
 from stokes_inputs import grid_sizes
+from stokes_inputs import velocity_dirichlet_mask
 from .fem import stokes_system
 from .transfer import prolongation
 from .braess_sarazin import BraessSarazinSmoother
@@ -32,9 +38,12 @@ from .vanka import VankaSmoother
 
 class Level:
     def __init__(self, N: int, nu, omega: float, shared, relax: bool, relaxation: str = "vanka",
-                 bs=None):
+                 bs=None, A=None):
         self.N = N
-        self.A, _, self.dmask, _ = stokes_system(N, nu)
+        if A is None:
+            self.A, _, self.dmask, _ = stokes_system(N, nu)
+        else:
+            self.A, self.dmask = A, velocity_dirichlet_mask(N)
         self.n = self.A.shape[0]
         if not relax:
             self.smoother = None
@@ -51,7 +60,7 @@ class Hierarchy:
 
     def __init__(self, N: int, levels: int, nu: float = 1.0, omega: float = 0.5,
                  nu_pre: int = 2, nu_post: int = 2, shared=None, relaxation: str = "vanka",
-                 bs=None):
+                 bs=None, coarse_operator: str = "rediscretise"):
         if levels < 2:
             raise ValueError("need at least two levels")
         if N % (1 << (levels - 1)):
@@ -67,12 +76,24 @@ class Hierarchy:
         else:
             nus = [nu] * levels
         self.nu_levels = nus[::-1]  # index l = level (0 coarsest)
+        if coarse_operator not in ("rediscretise", "galerkin"):
+            raise ValueError("coarse_operator must be 'rediscretise' or 'galerkin'")
+        self.P = [None] + [prolongation(N >> (levels - l)) for l in range(1, levels)]
+        ops = [None] * levels
+        if coarse_operator == "galerkin":
+            ops[-1], _, _, _ = stokes_system(N, nus[0])
+            for l in range(levels - 1, 0, -1):
+                Nc = N >> (levels - l)
+                Ac = (self.P[l].T @ ops[l] @ self.P[l]).tocsr()
+                Ac = (Ac + sp.diags(velocity_dirichlet_mask(Nc).astype(np.float64))).tocsr()
+                Ac.eliminate_zeros()
+                Ac.sort_indices()
+                ops[l - 1] = Ac
         self.levels = []
         for l in range(levels):
             Nl = N >> (levels - 1 - l)
             self.levels.append(Level(Nl, self.nu_levels[l], omega, shared, relax=(l > 0),
-                                     relaxation=relaxation, bs=bs))
-        self.P = [None] + [prolongation(self.levels[l - 1].N) for l in range(1, levels)]
+                                     relaxation=relaxation, bs=bs, A=ops[l]))
         # bordered coarse matrix
         A0 = self.levels[0].A.toarray()
         g0 = grid_sizes(self.levels[0].N)

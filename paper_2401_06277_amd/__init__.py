@@ -14,6 +14,7 @@ from ._vkmg import (  # noqa: F401
     KERNEL_RESIDUAL,
     KERNEL_TRANSFER,
     KERNEL_VANKA,
+    KERNEL_VANKA_TILE,
     LIB_PATH,
     STATUS,
     VkmgError,

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvkmg.so"
 FP64, FP32 = 0, 1
 APPLY = {"vector": 0, "matrix": 1}
 RELAX = {"vanka": 0, "braess_sarazin": 1}
-KERNEL_VANKA, KERNEL_RESIDUAL, KERNEL_TRANSFER, KERNEL_COARSE, KERNEL_KRYLOV = range(5)
+(KERNEL_VANKA, KERNEL_RESIDUAL, KERNEL_TRANSFER, KERNEL_COARSE, KERNEL_KRYLOV,
+ KERNEL_VANKA_TILE) = range(6)
 
 STATUS = {
     0: "VKMG_OK",

@@ -200,9 +200,12 @@ void sweep_t(vkmg_ctx* c, int l, const T* b, T* x, bool x_zero, hipStream_t s,
                            c->nb());
         return;
     }
-    launch_vanka_update<T>(L.g, r, xin, x, static_cast<const T*>(L.W),
-                           static_cast<const T*>(c->mtab), static_cast<T*>(L.dbuf), c->opt.omega,
-                           c->opt.interior_apply == VKMG_APPLY_MATRIX, s, c->nb());
+    launch_vanka_boundary<T>(L.g, r, static_cast<const T*>(L.W), static_cast<T*>(L.dbuf), s,
+                             c->nb());
+    Timed tt(c, VKMG_KERNEL_VANKA_TILE, s, l);
+    launch_vanka_tiles<T>(L.g, r, xin, x, static_cast<const T*>(c->mtab),
+                          static_cast<const T*>(L.dbuf), c->opt.omega,
+                          c->opt.interior_apply == VKMG_APPLY_MATRIX, s, c->nb());
 }
 
 // Largest FP64 level on which the coarse-grid correction is added by the

@@ -66,6 +66,14 @@ template <typename T>
 void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const T* table,
                          const T* mtab, T* dbuf, double omega, bool mfma, hipStream_t s,
                          int nb = 1);
+// The two launches of launch_vanka_update, in that order: the boundary-patch
+// corrections into dbuf, then the interior tiles (which also commit dbuf).
+template <typename T>
+void launch_vanka_boundary(const Geom& g, const T* r, const T* table, T* dbuf, hipStream_t s,
+                           int nb = 1);
+template <typename T>
+void launch_vanka_tiles(const Geom& g, const T* r, const T* xin, T* xout, const T* mtab,
+                        const T* dbuf, double omega, bool mfma, hipStream_t s, int nb = 1);
 int64_t vanka_boundary_scratch(int N);
 // Vanka update with one stored weighted inverse per patch ("simple" Vanka,
 // for a per-element viscosity): `tables` holds (N+1)^2 transposed 51 x 51

@@ -2266,9 +2266,8 @@ template void launch_vanka_simple<float>(const Geom&, const float*, const float*
 int64_t vanka_boundary_scratch(int N) { return int64_t(n_boundary_patches(N)) * 64; }
 
 template <typename T>
-void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const T* table,
-                         const T* mtab, T* dbuf, double omega, bool mfma, hipStream_t s,
-                         int nrhs) {
+void launch_vanka_boundary(const Geom& g, const T* r, const T* table, T* dbuf, hipStream_t s,
+                           int nrhs) {
     const int nb = n_boundary_patches(g.N);
     const int per = boundary_patches_per_wave(nb * nrhs);
     const dim3 bgrid((nb + 4 * per - 1) / (4 * per), nrhs);
@@ -2280,6 +2279,15 @@ void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const
         vanka_boundary_kernel<T, 2><<<bgrid, 256, 0, s>>>(g, r, table, dbuf);
     else
         vanka_boundary_kernel<T, 1><<<bgrid, 256, 0, s>>>(g, r, table, dbuf);
+}
+template void launch_vanka_boundary<double>(const Geom&, const double*, const double*, double*,
+                                            hipStream_t, int);
+template void launch_vanka_boundary<float>(const Geom&, const float*, const float*, float*,
+                                           hipStream_t, int);
+
+template <typename T>
+void launch_vanka_tiles(const Geom& g, const T* r, const T* xin, T* xout, const T* mtab,
+                        const T* dbuf, double omega, bool mfma, hipStream_t s, int nrhs) {
     const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
     const dim3 grid(8 * ((ntile + 7) / 8), nrhs);
     if (mfma)
@@ -2291,6 +2299,20 @@ void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const
     else
         vanka_sweep_kernel<T><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf, T(omega / g.nu),
                                                    T(g.nu / g.h));
+}
+template void launch_vanka_tiles<double>(const Geom&, const double*, const double*, double*,
+                                         const double*, const double*, double, bool, hipStream_t,
+                                         int);
+template void launch_vanka_tiles<float>(const Geom&, const float*, const float*, float*,
+                                        const float*, const float*, double, bool, hipStream_t,
+                                        int);
+
+template <typename T>
+void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const T* table,
+                         const T* mtab, T* dbuf, double omega, bool mfma, hipStream_t s,
+                         int nrhs) {
+    launch_vanka_boundary<T>(g, r, table, dbuf, s, nrhs);
+    launch_vanka_tiles<T>(g, r, xin, xout, mtab, dbuf, omega, mfma, s, nrhs);
 }
 template void launch_vanka_update<double>(const Geom&, const double*, const double*, double*,
                                           const double*, const double*, double*, double, bool,

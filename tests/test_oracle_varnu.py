@@ -88,3 +88,60 @@ def test_variable_viscosity_multigrid_contracts_and_solves():
     xs[off_p:] -= xs[off_p:].mean()
     # the viscosity contrast (e^2) worsens the conditioning: error ~ cond * rtol
     assert np.linalg.norm(xs - xt) <= 1e-7 * np.linalg.norm(xt)
+
+
+def test_galerkin_coarse_operator_equals_rediscretisation_for_constant_viscosity():
+    """Nested Q2-Q1 spaces: with a constant viscosity the product P^T A P is
+    the coarse finite-element operator itself, so both hierarchies hold the
+    same matrices and give the same V-cycle."""
+    N, levels = 16, 3
+    Hr = multigrid.Hierarchy(N, levels)
+    Hg = multigrid.Hierarchy(N, levels, coarse_operator="galerkin")
+    for lr, lg in zip(Hr.levels, Hg.levels):
+        d = abs(lr.A - lg.A).max()
+        assert d <= 1e-12 * abs(lr.A).max()
+    r = np.random.default_rng(4).standard_normal(Hr.A.shape[0])
+    r[velocity_dirichlet_mask(N)] = 0.0
+    zr, zg = Hr.vcycle(r), Hg.vcycle(r)
+    assert np.abs(zr - zg).max() <= 1e-10 * np.abs(zr).max()
+
+
+def test_galerkin_coarse_operator_of_blockwise_viscosity_is_the_coarse_assembly():
+    """A viscosity that is constant on each 2x2 block of fine elements is a
+    coarse-element field; the coarse integrals are then exactly the sums of
+    the fine ones, so P^T A P equals the coarse finite-element assembly with
+    that field (an identity of the discretisation, independent of P's
+    construction)."""
+    N, levels = 8, 2
+    nc = _nu(N // 2, seed=9).reshape(N // 2, N // 2)
+    nf = np.repeat(np.repeat(nc, 2, axis=0), 2, axis=1).ravel()
+    Hg = multigrid.Hierarchy(N, levels, nu=nf, coarse_operator="galerkin")
+    Ac, _, _, _ = fem.stokes_system(N // 2, nc.ravel())
+    d = abs(Hg.levels[0].A - Ac).max()
+    assert d <= 1e-12 * abs(Ac).max()
+
+
+def test_galerkin_coarse_operator_structure_for_variable_viscosity():
+    """Symmetric, constant-pressure null space, identity Dirichlet rows, and
+    couplings only between DoFs of a common coarse element (the pattern of
+    a coarse assembly with a generic per-element viscosity, which has no
+    exact cancellations), so the Vanka patches see the same local
+    structure."""
+    N, levels = 16, 3
+    Hg = multigrid.Hierarchy(N, levels, nu=_nu(N), coarse_operator="galerkin")
+    for l in range(levels - 1):
+        Nl = Hg.levels[l].N
+        A = Hg.levels[l].A
+        g = grid_sizes(Nl)
+        assert abs(A - A.T).max() <= 1e-13 * abs(A).max()
+        c = np.zeros(g.n)
+        c[g.off_p:] = 1.0
+        assert np.abs(A @ c).max() <= 1e-12 * abs(A).max()
+        dm = velocity_dirichlet_mask(Nl)
+        Ad = A.toarray()
+        assert np.array_equal(Ad[dm][:, dm], np.eye(int(dm.sum())))
+        assert not np.any(Ad[dm][:, ~dm]) and not np.any(Ad[~dm][:, dm])
+        Ar, _, _, _ = fem.stokes_system(Nl, _nu(Nl, seed=11))
+        # entries outside it are rounding residue of exact cancellations
+        outside = np.abs(Ad[Ar.toarray() == 0])
+        assert outside.max(initial=0.0) <= 1e-14 * np.abs(Ad).max()

@@ -53,17 +53,23 @@ typedef enum {
     VKMG_ERR_HIP = 4,            /* a HIP runtime call failed (message says which) */
     VKMG_ERR_SINGULAR_PATCH = 5, /* a Vanka patch or the coarse matrix is singular */
     VKMG_ERR_NOT_CONVERGED = 6,  /* FGMRES hit max_iters above the tolerance */
-    VKMG_ERR_NONFINITE = 7       /* NaN/Inf met in the right-hand side or a residual */
+    VKMG_ERR_NONFINITE = 7,      /* NaN/Inf met in the right-hand side or a residual */
+    VKMG_STATUS_FORCE_INT32 = 0x7fffffff /* not a status: keeps the type 32-bit and makes every
+                                            non-negative int a valid value of it */
 } vkmg_status;
 
-typedef enum { VKMG_FP64 = 0, VKMG_FP32 = 1 } vkmg_precision;
+typedef enum { VKMG_FP64 = 0, VKMG_FP32 = 1, VKMG_PRECISION_FORCE_INT32 = 0x7fffffff } vkmg_precision;
 
 /* How the interior Vanka patches (all patches two or more elements from the
  * boundary, which share one inverse) are applied: one patch per lane on the
  * vector ALUs (default, the faster on MI355X), or as 16-patch dense
  * products on the matrix cores.  Both give the same result up to rounding
  * order. */
-typedef enum { VKMG_APPLY_VECTOR = 0, VKMG_APPLY_MATRIX = 1 } vkmg_interior_apply;
+typedef enum {
+    VKMG_APPLY_VECTOR = 0,
+    VKMG_APPLY_MATRIX = 1,
+    VKMG_APPLY_FORCE_INT32 = 0x7fffffff
+} vkmg_interior_apply;
 
 /* Relaxation inside the V-cycle: additive Vanka (paper, "Vanka relaxation
  * scheme", Algorithm 3; default) or inexact Braess-Sarazin (paper,
@@ -71,7 +77,11 @@ typedef enum { VKMG_APPLY_VECTOR = 0, VKMG_APPLY_MATRIX = 1 } vkmg_interior_appl
  * S = -(1/t) B D^{-1} B^T, weighted-Jacobi sweeps on
  * S dp = r_p - (1/t) B D^{-1} r_u from dp = 0, du = (1/t) D^{-1}(r_u - B^T dp),
  * x += omega_bs (du, dp). */
-typedef enum { VKMG_RELAX_VANKA = 0, VKMG_RELAX_BRAESS_SARAZIN = 1 } vkmg_relaxation;
+typedef enum {
+    VKMG_RELAX_VANKA = 0,
+    VKMG_RELAX_BRAESS_SARAZIN = 1,
+    VKMG_RELAX_FORCE_INT32 = 0x7fffffff
+} vkmg_relaxation;
 
 typedef struct {
     int32_t nx, ny; /* elements per side on [0,1]^2; nx == ny required */
@@ -123,7 +133,8 @@ typedef enum {
     VKMG_KERNEL_VANKA_TILE = 5,  /* the interior-tile kernel of a Vanka update alone (the
                                     boundary-patch kernel before it excluded); constant-
                                     viscosity Vanka only */
-    VKMG_KERNEL_COUNT = 6
+    VKMG_KERNEL_COUNT = 6,
+    VKMG_KERNEL_FORCE_INT32 = 0x7fffffff
 } vkmg_kernel_class;
 
 /*

@@ -90,5 +90,52 @@ def build(verbose: bool = False, extra_flags=None) -> str:
     return LIB
 
 
+def _llvm_bin(name: str) -> str:
+    for cand in (os.path.join("/opt/rocm/llvm/bin", name), shutil.which(name)):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError(f"{name} not found (ROCm's LLVM is required for the sanitizer build)")
+
+
+def asan_runtime() -> str:
+    """Path of the shared AddressSanitizer runtime of ROCm's clang (to be
+    preloaded into a process that loads the sanitized library)."""
+    res = subprocess.run([_llvm_bin("clang++"), "-print-file-name=libclang_rt.asan-x86_64.so"],
+                         capture_output=True, text=True)
+    path = res.stdout.strip()
+    if res.returncode != 0 or not os.path.exists(path):
+        raise RuntimeError("clang's shared ASan runtime not found")
+    return path
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """CPU-only build of the library with AddressSanitizer and
+    UndefinedBehaviorSanitizer on the host code (the setup, the argument
+    validation and every host path of the C ABI); device code unchanged.
+    Writes _build/sanitize/libvkmg_sanitized.so, which a process loads with
+    the runtime of asan_runtime() preloaded.  Never used on a GPU."""
+    out_dir = os.path.join(BUILD, "sanitize")
+    os.makedirs(out_dir, exist_ok=True)
+    generate_headers(verbose)
+    hipcc = _hipcc()
+    host_san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+    objs = []
+    for src in HIP_SOURCES:
+        obj = os.path.join(out_dir, src + ".o")
+        _run([hipcc, *HIPCC_FLAGS, *host_san, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    cxx = _llvm_bin("clang++")
+    san = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-g"]
+    for src in HOST_SOURCES:
+        obj = os.path.join(out_dir, src + ".o")
+        _run([cxx, *GXX_FLAGS, *san, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    lib = os.path.join(out_dir, "libvkmg_sanitized.so")
+    _run([cxx, "-shared", "-fPIC", *san, "-shared-libsan", "-o", lib, *objs,
+          "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"], verbose)
+    return lib
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))

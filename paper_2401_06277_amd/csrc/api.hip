@@ -671,6 +671,7 @@ const char* vkmg_status_string(vkmg_status s) {
         case VKMG_ERR_SINGULAR_PATCH: return "singular patch or coarse matrix";
         case VKMG_ERR_NOT_CONVERGED: return "not converged";
         case VKMG_ERR_NONFINITE: return "non-finite value";
+        case VKMG_STATUS_FORCE_INT32: break;
     }
     return "unknown status";
 }

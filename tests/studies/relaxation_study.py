@@ -1,6 +1,6 @@
 """Iteration study of the relaxation schemes with the CPU oracle.
 
-    python tests/studies/relaxation_study.py [--sizes 64 128 256] > tests/studies/relaxation_study.txt
+    python tests/studies/relaxation_study.py > tests/studies/relaxation_study.txt
 
 Runs only the oracle (plain NumPy/SciPy FP64).  Two questions:
 
@@ -11,8 +11,9 @@ Runs only the oracle (plain NumPy/SciPy FP64).  Two questions:
    and V(2,2), for additive Vanka with the partition-of-unity weights
    W_i = omega diag(1/m_j) (several omega) and with a plain scalar weight
    W_i = omega I (the other reading of the paper's unspecified weight
-   matrix), and for inexact Braess-Sarazin (t = 1, omega_BS = 1, Jacobi
-   weight 1, two Jacobi sweeps on the Schur complement).
+   matrix), and for inexact Braess-Sarazin (t = 1, omega_BS = 1; two
+   Jacobi sweeps of weight 1 on the Schur complement, the library's
+   default, or one sweep of weight 0.8 or 0.6).
 
 2. Coarse operators for a per-element viscosity (log nu ~ U[-1, 1], seed
    7): rediscretisation with the mean of the four children against the
@@ -75,7 +76,12 @@ def study_relaxation(sizes):
             ("Vanka, W = omega I, omega = 0.15", "vanka", 0.15, "scalar"),
             ("Vanka, W = omega I, omega = 0.2", "vanka", 0.2, "scalar"),
             ("Vanka, W = omega I, omega = 0.3", "vanka", 0.3, "scalar"),
-            ("Braess-Sarazin (t = 1, omega_BS = 1, Jacobi 2 x weight 1)", "bs", None, None)]
+            ("Braess-Sarazin (t = 1, omega_BS = 1, Jacobi 2 x weight 1)", "bs", None,
+             dict(jacobi_sweeps=2, jacobi_weight=1.0)),
+            ("Braess-Sarazin (t = 1, omega_BS = 1, Jacobi 1 x weight 0.8)", "bs", None,
+             dict(jacobi_sweeps=1, jacobi_weight=0.8)),
+            ("Braess-Sarazin (t = 1, omega_BS = 1, Jacobi 1 x weight 0.6)", "bs", None,
+             dict(jacobi_sweeps=1, jacobi_weight=0.6))]
     header = "| Relaxation | " + " | ".join(
         f"{N}^2 V({c},{c})" for N in sizes for c in (1, 2)) + " |"
     print(header)
@@ -89,7 +95,7 @@ def study_relaxation(sizes):
             for name, relax, omega, mode in rows:
                 t0 = time.perf_counter()
                 if relax == "bs":
-                    H = multigrid.Hierarchy(N, L, nu_pre=c, nu_post=c, relaxation="bs")
+                    H = multigrid.Hierarchy(N, L, nu_pre=c, nu_post=c, relaxation="bs", bs=mode)
                 else:
                     H = multigrid.Hierarchy(N, L, omega=omega, nu_pre=c, nu_post=c)
                     if mode == "scalar":

@@ -116,7 +116,8 @@ void launch_lift(const Geom& g, const double* b, double* x, hipStream_t s, int n
 
 // Krylov kernels (FP64).  V: k vectors of length n with stride ldv; with
 // nb > 1 the batch entries of every vector are sb apart.  Partial sums:
-// dot_blocks(nb) per row and batch entry.
+// dot_blocks(nb) = kDotBlocks per row and batch entry (the same partition
+// for every batch size).
 constexpr int kDotBlocks = 2048;
 int dot_blocks(int nb);
 // part[(b * k + v) * G + blk] = partial dot of V_v and w of batch entry b

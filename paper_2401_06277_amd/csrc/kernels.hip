@@ -2386,11 +2386,10 @@ void launch_scale(const double* in, double alpha, double* out, int64_t n, hipStr
 // bases are processed in chunks of 32 vectors (single right-hand side).
 constexpr int kChunk = 32;
 
-int dot_blocks(int nb) {
-    if (nb <= 1) return kDotBlocks;
-    const int b = kDotBlocks / nb;
-    return b < 64 ? 64 : b;
-}
+// Every batch entry is reduced over the same kDotBlocks partial sums as a
+// single right-hand side, so batched dot products (and with them the whole
+// batched solve) are bitwise those of single solves.
+int dot_blocks(int) { return kDotBlocks; }
 
 void launch_scale_batched(const double* in, int64_t sin, const double* alpha, int64_t sa,
                           double* out, int64_t sout, int64_t n, int nb, hipStream_t s) {

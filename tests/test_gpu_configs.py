@@ -8,14 +8,17 @@ FP32-multigrid solve reaches the FP64 tolerance within one iteration of it.
 
 C4 (512 x 512, 7 levels, 32 right-hand sides: Gaussian random forces seeds
 1000 + k under the watertight lid): one batched solve against 32 single
-solves of the same systems, iteration counts equal and solutions within
-1e-12 per field (the same arithmetic in batched launches).
+solves of the same systems: iteration counts equal and solutions bitwise
+equal (batched launches do the arithmetic of single ones, and every batch
+entry is reduced over the same partial sums as a single right-hand side).
 
 C5 (256 x 256, 6 levels, log nu ~ U[-1, 1] seed 7, Gaussian random force
 seed 5, L = |x - x_t|^2 / 2 with x_t = 0.01 GRF seed 6 on the velocity):
 the autograd gradients with respect to the log-viscosity and the force
 against central differences of the GPU solve on 20 seeded directions
-(seed 8), 1e-6 relative (solves at rtol 1e-12).
+(seed 8), 1e-6 relative (solves at rtol 1e-10: with this viscosity field
+the adjoint system's FP64 rounding floor at 256 x 256 is a relative
+residual of about 1.5e-11, so 1e-12 is out of reach).
 """
 
 import numpy as np
@@ -108,9 +111,10 @@ def test_c4_batched_32_equals_single_solves():
             info = s1.fgmres_solve(bk, xk, rtol=1e-8)
             assert infos[k]["status_name"] == "VKMG_OK" and info["status_name"] == "VKMG_OK"
             assert infos[k]["iterations"] == info["iterations"], (k, infos[k], info)
-            e = rel(xb[k], host(xk))
+            xs = host(xk)
+            e = rel(xb[k], xs)
             worst = max(worst, e)
-            assert e <= 1e-12, (k, e)
+            assert np.array_equal(xb[k], xs), (k, e)
     note(f"[C4] {B} systems: iterations {[i['iterations'] for i in infos]}, "
          f"worst batched-vs-single difference {worst:.2e}")
 
@@ -130,13 +134,13 @@ def test_c5_gradients_match_central_differences_at_256():
     s = vk.VkmgSolver(N, levels, nu_elem=nu)
     fd = dev(f).requires_grad_(True)
     nud = dev(nu).requires_grad_(True)
-    x = stokes_solve(fd, s, nu=nud, rtol=1e-12)
+    x = stokes_solve(fd, s, nu=nud, rtol=1e-10)
     (0.5 * torch.sum((x - xt_d) ** 2)).backward()
     g_theta, g_f = host(nud.grad) * nu, host(fd.grad)  # dL/dtheta = nu dL/dnu
 
     def loss(sv, force):
         with torch.no_grad():
-            return float(0.5 * torch.sum((stokes_solve(dev(force), sv, rtol=1e-12) - xt_d) ** 2))
+            return float(0.5 * torch.sum((stokes_solve(dev(force), sv, rtol=1e-10) - xt_d) ** 2))
 
     rng = np.random.default_rng(8)
     eps = 1e-4

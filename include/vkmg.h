@@ -280,6 +280,27 @@ vkmg_status vkmg_vanka_sweep(vkmg_ctx* ctx, int32_t level, void* x, const void* 
 vkmg_status vkmg_vanka_update(vkmg_ctx* ctx, int32_t level, void* x, const void* r, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * update as vkmg_vanka_update, with the same arguments and results (the
+ * same kernels), except that the patch corrections the update keeps
+ * between its two launches live in a static device array of the library
+ * (4 MiB per GPU, held until the process ends) instead of the context's
+ * buffer.  Calls no hipMalloc, hipFree or other allocating routine.
+ * Limit: the corrections must fit, i.e. 64 * (8N - 8) values of the
+ * multigrid precision per right-hand side for a level of N elements per
+ * side (N <= 1024 in FP64, N <= 2048 in FP32, for one right-hand side), or
+ * 64 * (N + 1)^2 per right-hand side for a per-element viscosity; larger
+ * levels or batches return VKMG_ERR_INVALID_ARG before any launch.  Every
+ * call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (other streams, other contexts, other host threads) race and
+ * must be serialised by the caller.  Nothing in the array needs to start
+ * at zero (each update writes every value it reads).
+ */
+vkmg_status vkmg_vanka_update_noalloc(vkmg_ctx* ctx, int32_t level, void* x, const void* r,
+                                      void* stream);
+
+/*
  * One sweep of the context's relaxation (opts.relaxation) on `level`
  * (1 <= level <= levels-1), in the multigrid precision: r = b - A_l x, then
  * the Vanka update (as vkmg_vanka_sweep) or the Braess-Sarazin update

@@ -36,7 +36,7 @@ STATUS = {
 EXPORTED = [
     "vkmg_default_options", "vkmg_setup", "vkmg_setup_viscosity", "vkmg_destroy", "vkmg_layout_of", "vkmg_level_layout",
     "vkmg_num_levels", "vkmg_residual", "vkmg_apply", "vkmg_assemble_rhs", "vkmg_vanka_sweep",
-    "vkmg_vanka_update", "vkmg_relax", "vkmg_assemble_rhs_adjoint", "vkmg_remove_pressure_mean", "vkmg_dirichlet_lift",
+    "vkmg_vanka_update", "vkmg_vanka_update_noalloc", "vkmg_relax", "vkmg_assemble_rhs_adjoint", "vkmg_remove_pressure_mean", "vkmg_dirichlet_lift",
     "vkmg_viscosity_gradient",
     "vkmg_restrict", "vkmg_prolong_add", "vkmg_coarse_solve", "vkmg_vcycle",
     "vkmg_fgmres_solve", "vkmg_set_timing", "vkmg_kernel_timing", "vkmg_host_patch_matrix",
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
         "vkmg_assemble_rhs": (c_int32, [P, P, P, P, P]),
         "vkmg_vanka_sweep": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_vanka_update": (c_int32, [P, c_int32, P, P, P]),
+        "vkmg_vanka_update_noalloc": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_relax": (c_int32, [P, c_int32, P, P, P]),
         "vkmg_assemble_rhs_adjoint": (c_int32, [P, P, P, P]),
         "vkmg_remove_pressure_mean": (c_int32, [P, P, P]),
@@ -357,6 +358,15 @@ class VkmgSolver:
         st = _lib.vkmg_vanka_update(self._ctx, level, self._ptr(x, self.mg_dtype, n, "x"),
                                     self._ptr(r, self.mg_dtype, n, "r"), self._stream())
         _check(st, "vkmg_vanka_update")
+        return x
+
+    def vanka_update_noalloc(self, level: int, x, r):
+        """vanka_update through the allocation-free entry point (patch
+        corrections in the library's static device scratch)."""
+        n = self.level_layout(level)["n"] * self.batch
+        st = _lib.vkmg_vanka_update_noalloc(self._ctx, level, self._ptr(x, self.mg_dtype, n, "x"),
+                                            self._ptr(r, self.mg_dtype, n, "r"), self._stream())
+        _check(st, "vkmg_vanka_update_noalloc")
         return x
 
     def relax(self, level: int, x, b):

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -49,6 +50,41 @@ struct LevelBuf {
 
 }  // namespace
 
+// Device scratch of vkmg_vanka_update_noalloc: the patch corrections of one
+// Vanka update (the boundary patches', or every patch's for a per-element
+// viscosity), which vkmg_vanka_update keeps in a buffer allocated at setup.
+// Each GPU holds its own copy until the process ends.  Host code never
+// passes `scratch` itself to a kernel: its device address comes from
+// hipGetSymbolAddress, per device (noalloc_scratch below).
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current
+// device; looked up once per device (at the first setup on it).
+vkmg_status noalloc_scratch(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices)
+        return fail(VKMG_ERR_UNSUPPORTED, "setup: device index beyond the scratch table");
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(VKMG_ERR_HIP, std::string("setup: hipGetSymbolAddress(scratch): ") +
+                                          hipGetErrorString(e));
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return VKMG_OK;
+}
+
+}  // namespace
+
 struct vkmg_ctx {
     int device = 0;
     int L = 0;
@@ -75,6 +111,7 @@ struct vkmg_ctx {
     };
     std::vector<EventPair> events[VKMG_KERNEL_COUNT];
     std::vector<void*> allocations;
+    void* noalloc = nullptr;  // device address of `scratch` on this context's device
     // executable graphs of the Arnoldi steps (index j), valid for the
     // current basis allocation; captured on a private stream
     std::vector<hipGraphExec_t> step_graphs;
@@ -636,6 +673,47 @@ vkmg_status fgmres_batched(vkmg_ctx* ctx, const double* b, double* x, double rto
     return first;
 }
 
+// Bytes of patch corrections one Vanka update of `level` keeps between its
+// two launches: the boundary patches' (every patch's for a per-element
+// viscosity), 64 slots each, per right-hand side.
+size_t correction_scratch_bytes(const vkmg_ctx* c, int level) {
+    const Geom& g = c->lev[level].g;
+    const size_t per = c->variable ? size_t(g.N + 1) * (g.N + 1) * 64
+                                   : size_t(vanka_boundary_scratch(g.N));
+    return per * c->esize() * size_t(c->nb());
+}
+
+// The update half of a sweep on `level` with the patch corrections kept in
+// `dbuf` (correction_scratch_bytes of device memory): x += corrections of r.
+void vanka_update_with(vkmg_ctx* ctx, int level, void* x, const void* r, void* dbuf,
+                       hipStream_t s) {
+    LevelBuf& L = ctx->lev[level];
+    const bool mfma = ctx->opt.interior_apply == VKMG_APPLY_MATRIX;
+    if (ctx->variable) {
+        if (ctx->opt.mg_precision == VKMG_FP64)
+            launch_vanka_simple<double>(L.g, static_cast<const double*>(r), static_cast<double*>(x),
+                                        static_cast<double*>(x), static_cast<const double*>(L.W),
+                                        static_cast<double*>(dbuf), s, ctx->nb());
+        else
+            launch_vanka_simple<float>(L.g, static_cast<const float*>(r), static_cast<float*>(x),
+                                       static_cast<float*>(x), static_cast<const float*>(L.W),
+                                       static_cast<float*>(dbuf), s, ctx->nb());
+        return;
+    }
+    if (ctx->opt.mg_precision == VKMG_FP64)
+        launch_vanka_update<double>(L.g, static_cast<const double*>(r), static_cast<double*>(x),
+                                    static_cast<double*>(x), static_cast<const double*>(L.W),
+                                    static_cast<const double*>(ctx->mtab),
+                                    static_cast<double*>(dbuf), ctx->opt.omega, mfma, s,
+                                    ctx->nb());
+    else
+        launch_vanka_update<float>(L.g, static_cast<const float*>(r), static_cast<float*>(x),
+                                   static_cast<float*>(x), static_cast<const float*>(L.W),
+                                   static_cast<const float*>(ctx->mtab),
+                                   static_cast<float*>(dbuf), ctx->opt.omega, mfma, s,
+                                   ctx->nb());
+}
+
 }  // namespace
 
 // =====================================================================================
@@ -813,7 +891,7 @@ static vkmg_status setup_impl(const vkmg_grid* grid, int32_t levels, double nu,
     VKMG_HIP(hipGetDevice(&c->device));
     hipStream_t s = as_stream(hip_stream);
     c->lev.resize(levels);
-    vkmg_status st = VKMG_OK;
+    vkmg_status st = noalloc_scratch(c->device, &c->noalloc);
     const size_t es = c->esize();
     for (int l = 0; l < levels && st == VKMG_OK; ++l) {
         LevelBuf& L = c->lev[l];
@@ -1056,33 +1134,27 @@ vkmg_status vkmg_vanka_update(vkmg_ctx* ctx, int32_t level, void* x, const void*
     if (x == r) return fail(VKMG_ERR_INVALID_ARG, "vanka_update: r must not alias x");
     VKMG_HIP(hipSetDevice(ctx->device));
     hipStream_t s = as_stream(stream);
-    LevelBuf& L = ctx->lev[level];
-    const bool mfma = ctx->opt.interior_apply == VKMG_APPLY_MATRIX;
     Timed t(ctx, VKMG_KERNEL_VANKA, s, level);
-    if (ctx->variable) {
-        if (ctx->opt.mg_precision == VKMG_FP64)
-            launch_vanka_simple<double>(L.g, static_cast<const double*>(r), static_cast<double*>(x),
-                                        static_cast<double*>(x), static_cast<const double*>(L.W),
-                                        static_cast<double*>(L.dbuf), s, ctx->nb());
-        else
-            launch_vanka_simple<float>(L.g, static_cast<const float*>(r), static_cast<float*>(x),
-                                       static_cast<float*>(x), static_cast<const float*>(L.W),
-                                       static_cast<float*>(L.dbuf), s, ctx->nb());
-        VKMG_HIP(hipGetLastError());
-        return VKMG_OK;
-    }
-    if (ctx->opt.mg_precision == VKMG_FP64)
-        launch_vanka_update<double>(L.g, static_cast<const double*>(r), static_cast<double*>(x),
-                                    static_cast<double*>(x), static_cast<const double*>(L.W),
-                                    static_cast<const double*>(ctx->mtab),
-                                    static_cast<double*>(L.dbuf), ctx->opt.omega, mfma, s,
-                                    ctx->nb());
-    else
-        launch_vanka_update<float>(L.g, static_cast<const float*>(r), static_cast<float*>(x),
-                                   static_cast<float*>(x), static_cast<const float*>(L.W),
-                                   static_cast<const float*>(ctx->mtab),
-                                   static_cast<float*>(L.dbuf), ctx->opt.omega, mfma, s,
-                                   ctx->nb());
+    vanka_update_with(ctx, level, x, r, ctx->lev[level].dbuf, s);
+    VKMG_HIP(hipGetLastError());
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_vanka_update_noalloc(vkmg_ctx* ctx, int32_t level, void* x, const void* r,
+                                      void* stream) {
+    if (!x || !r || !check_level(ctx, level, true))
+        return fail(VKMG_ERR_INVALID_ARG,
+                    "vanka_update_noalloc: NULL argument or level not in [1, levels)");
+    if (x == r) return fail(VKMG_ERR_INVALID_ARG, "vanka_update_noalloc: r must not alias x");
+    const size_t need = correction_scratch_bytes(ctx, level);
+    if (need > kNoAllocScratchBytes)
+        return fail(VKMG_ERR_INVALID_ARG,
+                    "vanka_update_noalloc: the patch corrections of this level need " +
+                        std::to_string(need) + " bytes, more than the " +
+                        std::to_string(kNoAllocScratchBytes) + "-byte static scratch");
+    if (!ctx->noalloc) return fail(VKMG_ERR_HIP, "vanka_update_noalloc: no scratch address");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    vanka_update_with(ctx, level, x, r, ctx->noalloc, as_stream(stream));
     VKMG_HIP(hipGetLastError());
     return VKMG_OK;
 }

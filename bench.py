@@ -90,6 +90,15 @@ def parse():
     ap.add_argument("--vcycle-only", action="store_true",
                     help="only set up the FP64 (and FP32) contexts and time V-cycles: the "
                          "median cycle and the per-level kernel table (for profiling)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="only measure the launch-shape tuning (vkmg_autotune) of the FP64 and "
+                         "FP32 contexts and print it with the V-cycle times it gives")
+    ap.add_argument("--fused-sweep-max-n", type=int, default=-1,
+                    help="override the tuning: sweeps of levels with 16 <= N <= this fused "
+                         "into one launch (0: never); -1: library default")
+    ap.add_argument("--cpu-c3", action="store_true",
+                    help="also time one oracle V(2,2) cycle at 1024x1024, 8 levels (setup of "
+                         "several minutes on the host; not part of the default run)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB "
                          "(3 times) and exit: the reference kernel for scaling HBM "
@@ -220,6 +229,9 @@ def vcycle_only(a):
     for prec in ("fp64", "fp32"):
         log(f"[bench] V-cycles {prec}")
         s = vk.VkmgSolver(N, L, precision=prec, interior_apply=a.interior_apply)
+        if a.fused_sweep_max_n >= 0:
+            s.set_tuning(fused_sweep_max_n=a.fused_sweep_max_n)
+        out[f"tuning_{prec}"] = s.get_tuning()
         n = s.layout["n"]
         rh = uniform_vector(n, 170)
         rh[velocity_dirichlet_mask(N)] = 0.0
@@ -229,6 +241,71 @@ def vcycle_only(a):
         out[f"levels_{prec}"] = vcycle_level_table(s, vk, torch, r, z, N, L)
         s.close()
     print(json.dumps(out), flush=True)
+
+
+def autotune_only(a):
+    """Run the library's autotuner on the benchmark's FP64 and FP32
+    contexts; print the chosen launch shapes and the median V-cycle under
+    the library defaults, with every fusion off, and under the tuned
+    choice."""
+    import torch
+
+    import paper_2401_06277_amd as vk
+    from stokes_inputs import uniform_vector, velocity_dirichlet_mask
+
+    torch.cuda.set_device(0)
+    N, L = a.N, a.levels
+    never = 2**31 - 1
+    plain = dict(fused_sweep_max_n=0, park_min_n=never, fused_prolong_max_n=0,
+                 boundary_per_wave=1)
+    out = {"N": N, "levels": L}
+    for prec in ("fp64", "fp32"):
+        log(f"[bench] autotune {prec}")
+        s = vk.VkmgSolver(N, L, precision=prec)
+        n = s.layout["n"]
+        rh = uniform_vector(n, 170)
+        rh[velocity_dirichlet_mask(N)] = 0.0
+        r = torch.from_numpy(rh).cuda()
+        z = torch.empty_like(r)
+        default = s.get_tuning()
+        t_default = timed_vcycles(s, torch, r, z)
+        s.set_tuning(**plain)
+        t_plain = timed_vcycles(s, torch, r, z)
+        s.set_tuning(**default)
+        t0 = time.perf_counter()
+        tuned = s.autotune(reps=10)
+        t_tune = time.perf_counter() - t0
+        t_tuned = timed_vcycles(s, torch, r, z)
+        out[prec] = {"default": default, "vcycle_s_default": t_default,
+                     "plain": plain, "vcycle_s_plain": t_plain,
+                     "tuned": tuned, "vcycle_s_tuned": t_tuned, "autotune_s": t_tune,
+                     "levels": vcycle_level_table(s, vk, torch, r, z, N, L)}
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_c3():
+    """One oracle V(2,2) cycle at 1024 x 1024, 8 levels, on the host cores
+    (the hierarchy's setup timed separately)."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import fem, multigrid
+    from stokes_inputs import gaussian_random_field
+
+    N, L = 1024, 8
+    t0 = time.perf_counter()
+    H = multigrid.Hierarchy(N, L)
+    setup_s = time.perf_counter() - t0
+    f = gaussian_random_field(N, 5, length=0.1)
+    _, b, _, _ = fem.stokes_system(N, 1.0, f_nodal=f)
+    t0 = time.perf_counter()
+    H.vcycle(b)
+    dt = time.perf_counter() - t0
+    blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": H.patch_updates_per_cycle() / dt, "unit": "patch-updates/s",
+            "cores": int(blas_threads), "kind": "oracle",
+            "sample": f"1 FP64 V(2,2) cycle of the oracle at {N}x{N} elements, {L} levels",
+            "seconds_per_vcycle": dt, "setup_s": setup_s}
 
 
 def cpu_baseline(N, levels, nvc, c2=None):
@@ -602,6 +679,9 @@ def main():
     if a.vcycle_only:
         vcycle_only(a)
         return
+    if a.autotune:
+        autotune_only(a)
+        return
     import numpy as np
     import torch
 
@@ -616,6 +696,8 @@ def main():
 
     def make(prec):
         s = vk.VkmgSolver(N, L, precision=prec, interior_apply=a.interior_apply)
+        if a.fused_sweep_max_n >= 0:
+            s.set_tuning(fused_sweep_max_n=a.fused_sweep_max_n)
         b = s.assemble_rhs(fd)
         x = torch.zeros_like(b)
         return s, b, x
@@ -711,6 +793,7 @@ def main():
                          f"(l=0.1, seed 5), FGMRES(30) + V(2,2) Vanka omega=0.5, rtol {a.rtol:g}"),
             "N": N, "levels": L, "dofs": n, "patch_updates_per_vcycle": ups_per_cycle,
             "interior_apply": a.interior_apply,
+            "tuning": s64.get_tuning(),
         },
         "time_to_1e8_s": dt64 / a.steps,
         "time_to_1e8_s_without_graphs": dt64_ev / a.steps,
@@ -810,6 +893,9 @@ def main():
     if not a.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(a.cpu_N, a.cpu_levels, a.cpu_vcycles, c2)
+        if a.cpu_c3:
+            log("[bench] cpu baseline at 1024x1024 (oracle, one V-cycle)")
+            out["cpu_baseline"]["c3_1024"] = cpu_baseline_c3()
     print(json.dumps(out), flush=True)
 
 

@@ -338,6 +338,51 @@ vkmg_status vkmg_coarse_solve(vkmg_ctx* ctx, const void* r, void* e, void* strea
 vkmg_status vkmg_vcycle(vkmg_ctx* ctx, const double* r, double* z, void* stream);
 
 /*
+ * Launch shapes of the V-cycle, per level size.  No choice changes a
+ * result: every alternative does the same arithmetic in the same order, so
+ * V-cycles and solves are bitwise the same under any tuning.
+ *   fused_sweep_max_n:   levels with 16 <= N <= this run each Vanka sweep
+ *                        of a V-cycle as one launch (residual, boundary
+ *                        patches, interior patches and owner sums of one
+ *                        tile in one workgroup) instead of three; 0: never.
+ *                        Vanka contexts with constant viscosity, vector
+ *                        apply and nu_pre, nu_post >= 1 only.
+ *   park_min_n:          FP64 levels with N >= this use the tile kernel that
+ *                        parks half of a patch in LDS during the interior
+ *                        apply (three waves per SIMD instead of two).
+ *   fused_prolong_max_n: FP64 levels with N <= this add the coarse-grid
+ *                        correction inside the residual launch of the first
+ *                        post-smoothing sweep (FP32 contexts: every level).
+ *   boundary_per_wave:   boundary patches per wavefront in the boundary-
+ *                        patch launch: 1, 2, 4 or 8; 0: from the patch count.
+ * Defaults are the choices measured fastest on MI355X for the context's
+ * precision (vkmg_setup); vkmg_autotune measures them on the running GPU.
+ */
+typedef struct {
+    int32_t fused_sweep_max_n;
+    int32_t park_min_n;
+    int32_t fused_prolong_max_n;
+    int32_t boundary_per_wave;
+} vkmg_tuning;
+
+vkmg_status vkmg_get_tuning(const vkmg_ctx* ctx, vkmg_tuning* out);
+/* Invalid values (negative sizes, boundary_per_wave not 0/1/2/4/8) return
+ * VKMG_ERR_INVALID_ARG and leave the tuning unchanged. */
+vkmg_status vkmg_set_tuning(vkmg_ctx* ctx, const vkmg_tuning* tuning);
+
+/*
+ * Measure the tuning on this GPU: coordinate descent over the four fields
+ * (candidates: the context's level sizes), two rounds, each candidate timed
+ * as the median of three runs of `reps` V-cycles (reps >= 1) replayed from a
+ * captured graph on `stream`, with the context's own work vectors as input
+ * (overwritten); a candidate replaces the current choice only if it is more
+ * than 1 % faster.  The result becomes the context's tuning and, if `out`
+ * is not NULL, is copied there.  Synchronises `stream`; allocates events and
+ * graphs, frees them before returning.
+ */
+vkmg_status vkmg_autotune(vkmg_ctx* ctx, int32_t reps, void* stream, vkmg_tuning* out);
+
+/*
  * Solve A x = b by restarted flexible GMRES right-preconditioned with
  * vkmg_vcycle (paper, section "Overall solver performance"), in FP64.
  * x holds the initial guess on entry (use the Dirichlet lifting: g on D,

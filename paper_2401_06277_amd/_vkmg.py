@@ -39,7 +39,7 @@ EXPORTED = [
     "vkmg_vanka_update", "vkmg_vanka_update_noalloc", "vkmg_relax", "vkmg_assemble_rhs_adjoint", "vkmg_remove_pressure_mean", "vkmg_dirichlet_lift",
     "vkmg_viscosity_gradient",
     "vkmg_restrict", "vkmg_prolong_add", "vkmg_coarse_solve", "vkmg_vcycle",
-    "vkmg_fgmres_solve", "vkmg_set_timing", "vkmg_kernel_timing", "vkmg_host_patch_matrix",
+    "vkmg_fgmres_solve", "vkmg_get_tuning", "vkmg_set_tuning", "vkmg_autotune", "vkmg_set_timing", "vkmg_kernel_timing", "vkmg_host_patch_matrix",
     "vkmg_status_string", "vkmg_last_error",
 ]
 
@@ -67,6 +67,14 @@ class Layout(ctypes.Structure):
     _fields_ = [("n", c_int64), ("n_vel", c_int64), ("n_pres", c_int64), ("off_ux", c_int64),
                 ("off_uy", c_int64), ("off_p", c_int64), ("q2_side", c_int32),
                 ("q1_side", c_int32), ("n_elem", c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("fused_sweep_max_n", c_int32), ("park_min_n", c_int32),
+                ("fused_prolong_max_n", c_int32), ("boundary_per_wave", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -119,6 +127,9 @@ def load_library(path: str = LIB_PATH):
         "vkmg_coarse_solve": (c_int32, [P, P, P, P]),
         "vkmg_vcycle": (c_int32, [P, P, P, P]),
         "vkmg_fgmres_solve": (c_int32, [P, P, P, c_double, c_int32, c_int32, POINTER(Info), P]),
+        "vkmg_get_tuning": (c_int32, [P, POINTER(Tuning)]),
+        "vkmg_set_tuning": (c_int32, [P, POINTER(Tuning)]),
+        "vkmg_autotune": (c_int32, [P, c_int32, P, POINTER(Tuning)]),
         "vkmg_set_timing": (c_int32, [P, c_int32]),
         "vkmg_kernel_timing": (c_int32, [P, c_int32, c_int32, POINTER(c_int64), POINTER(c_double)]),
         "vkmg_host_patch_matrix": (c_int32, [c_int32, c_double, c_double, c_int32, P, P, P, P]),
@@ -426,6 +437,23 @@ class VkmgSolver:
         if self.batch == 1:
             return info[0].as_dict()
         return [i.as_dict() for i in info]
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(_lib.vkmg_get_tuning(self._ctx, byref(t)), "vkmg_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, **fields) -> dict:
+        """Change launch shapes (vkmg_tuning fields by name); returns the new tuning."""
+        t = Tuning(**{**self.get_tuning(), **fields})
+        _check(_lib.vkmg_set_tuning(self._ctx, byref(t)), "vkmg_set_tuning")
+        return self.get_tuning()
+
+    def autotune(self, reps: int = 10) -> dict:
+        """Measure the launch shapes on this GPU (vkmg_autotune); returns them."""
+        t = Tuning()
+        _check(_lib.vkmg_autotune(self._ctx, reps, self._stream(), byref(t)), "vkmg_autotune")
+        return t.as_dict()
 
     def set_timing(self, class_mask: int):
         _check(_lib.vkmg_set_timing(self._ctx, class_mask), "vkmg_set_timing")

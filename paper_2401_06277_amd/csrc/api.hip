@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -112,6 +113,7 @@ struct vkmg_ctx {
     std::vector<EventPair> events[VKMG_KERNEL_COUNT];
     std::vector<void*> allocations;
     void* noalloc = nullptr;  // device address of `scratch` on this context's device
+    vkmg_tuning tune{};       // launch shapes per level size (vkmg_set_tuning)
     // executable graphs of the Arnoldi steps (index j), valid for the
     // current basis allocation; captured on a private stream
     std::vector<hipGraphExec_t> step_graphs;
@@ -129,7 +131,8 @@ struct vkmg_ctx {
 
 namespace {
 
-constexpr int kHostScratch = 1024;  // doubles in the pinned host buffer
+constexpr int kHostScratch = 2048;  // doubles per system in hdev and the pinned hhost
+static_assert(kHostScratch >= GivensLayout::kSize + 32, "coefficient area holds the Givens state");
 // largest restart length orthogonalised by the delayed scheme (its
 // kernels hold up to 32 basis coefficients in registers)
 constexpr int kDelayedMaxRestart = 32;
@@ -206,6 +209,12 @@ vkmg_layout layout_of_geom(const Geom& g) {
 
 // ------------------------------------------------------------------ MG steps
 
+// FP64 tile kernel with half of a patch parked in LDS on this level.
+template <typename T>
+bool parked(const vkmg_ctx* c, int N) {
+    return sizeof(T) == 8 && N >= c->tune.park_min_n;
+}
+
 // One sweep on level l: r = b - A x, then x += corrections (in place).
 // With x_zero the iterate is known to be zero, so r = b and the update
 // writes every DoF of x without reading it.  With xin given, L.r already
@@ -238,22 +247,79 @@ void sweep_t(vkmg_ctx* c, int l, const T* b, T* x, bool x_zero, hipStream_t s,
         return;
     }
     launch_vanka_boundary<T>(L.g, r, static_cast<const T*>(L.W), static_cast<T*>(L.dbuf), s,
-                             c->nb());
+                             c->nb(), c->tune.boundary_per_wave);
     Timed tt(c, VKMG_KERNEL_VANKA_TILE, s, l);
     launch_vanka_tiles<T>(L.g, r, xin, x, static_cast<const T*>(c->mtab),
                           static_cast<const T*>(L.dbuf), c->opt.omega,
-                          c->opt.interior_apply == VKMG_APPLY_MATRIX, s, c->nb());
+                          c->opt.interior_apply == VKMG_APPLY_MATRIX, s, c->nb(),
+                          parked<T>(c, L.g.N));
 }
 
-// Largest FP64 level on which the coarse-grid correction is added by the
-// residual of the first post-smoothing sweep (launch_residual_prolong):
-// there it saves a launch; on larger FP64 levels the separate kernels are
-// faster (measured at 512x512 and 1024x1024).
-constexpr int kFusedProlongMaxN = 256;
+// Whether the V-cycle sweeps of level l run as single fused launches.
+bool fused_sweeps(const vkmg_ctx* c, int l) {
+    const int N = c->lev[l].g.N;
+    return c->opt.relaxation == VKMG_RELAX_VANKA && !c->variable &&
+           c->opt.interior_apply == VKMG_APPLY_VECTOR && c->opt.nu_pre >= 1 &&
+           c->opt.nu_post >= 1 && N >= vanka_fused_min_n() && N <= c->tune.fused_sweep_max_n;
+}
+
+template <typename T>
+void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s);
+
+// MG(l, b) with every sweep of level l fused into one launch.  The fused
+// sweep writes a buffer other than the one it reads, so the iterates
+// alternate between x and the level's x2, arranged so that the last sweep
+// writes x; the coarse-grid correction is added in place to the last
+// pre-smoothed iterate.  Same results as the unfused form.
+template <typename T>
+void mg_fused_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
+    LevelBuf& L = c->lev[l];
+    LevelBuf& Lc = c->lev[l - 1];
+    T* const x2 = static_cast<T*>(L.x2);
+    const T* const W = static_cast<const T*>(L.W);
+    const int S = c->opt.nu_pre + c->opt.nu_post;
+    auto out = [&](int k) { return ((S - k) % 2 == 0) ? x : x2; };
+    T* cur = nullptr;  // x = 0
+    for (int k = 1; k <= c->opt.nu_pre; ++k) {
+        Timed t(c, VKMG_KERNEL_VANKA, s, l);
+        launch_vanka_fused<T>(L.g, b, cur, out(k), W, c->opt.omega, s, c->nb());
+        cur = out(k);
+    }
+    T* r = static_cast<T*>(L.r);
+    {
+        Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
+        launch_residual<T, T>(L.g, b, cur, r, 0, s, c->nb(), c->nu_of<T>(l));
+    }
+    T* bc = static_cast<T*>(Lc.b);
+    T* xc = static_cast<T*>(Lc.x);
+    {
+        Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
+        launch_restrict<T>(L.g, Lc.g, r, bc, s, c->nb());
+    }
+    if (l - 1 == 0) {
+        Timed t(c, VKMG_KERNEL_COARSE, s, 0);
+        launch_coarse_gemv<T>(Lc.g.n, c->C, bc, xc, s, c->nb());
+    } else {
+        mg_t<T>(c, l - 1, bc, xc, s);
+    }
+    {
+        Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
+        launch_prolong_add<T>(L.g, Lc.g, xc, cur, s, c->nb());
+    }
+    for (int k = c->opt.nu_pre + 1; k <= S; ++k) {
+        Timed t(c, VKMG_KERNEL_VANKA, s, l);
+        launch_vanka_fused<T>(L.g, b, cur, out(k), W, c->opt.omega, s, c->nb());
+        cur = out(k);
+    }
+}
 
 // MG(l, b) of Algorithm 1 with zero initial guess, result in x.
 template <typename T>
 void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
+    if (fused_sweeps(c, l)) {
+        mg_fused_t<T>(c, l, b, x, s);
+        return;
+    }
     LevelBuf& L = c->lev[l];
     LevelBuf& Lc = c->lev[l - 1];
     T* r = static_cast<T*>(L.r);
@@ -282,9 +348,10 @@ void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
     } else {
         mg_t<T>(c, l - 1, bc, xc, s);
     }
-    // FP64 levels above kFusedProlongMaxN: the separate prolongation and
-    // residual kernels are faster (the fused one is not bandwidth-bound there)
-    const bool fused = sizeof(T) == 4 || L.g.N <= kFusedProlongMaxN;
+    // the coarse-grid correction inside the next residual (FP32: always;
+    // FP64: up to the tuned size, above which the separate prolongation and
+    // residual kernels are faster)
+    const bool fused = sizeof(T) == 4 || L.g.N <= c->tune.fused_prolong_max_n;
     if (c->opt.nu_post == 0 || !fused) {
         Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
         launch_prolong_add<T>(L.g, Lc.g, xc, x, s, c->nb());
@@ -403,17 +470,23 @@ bool check_level(const vkmg_ctx* c, int32_t level, bool relaxed) {
 
 namespace {
 
-// Restarted FGMRES for the B > 1 independent systems of a batched context:
-// the Arnoldi steps of all B run as one batched launch per kernel (delayed
-// CGS2, the scheme of the single-system solver for restart <= 32), while
-// the Hessenberg matrices, Givens rotations, stopping tests and restarts
-// are kept per system on the host.  A system that has converged (or broken
-// down) keeps riding along in the batched launches until the cycle ends;
-// its values are ignored.  Device coefficient areas: kHostScratch doubles
-// per system (2j+3 reduced values at 0, alpha/gamma/d/sigma at 300, the
-// starting scale at 900, y at 600).
-vkmg_status fgmres_batched(vkmg_ctx* ctx, const double* b, double* x, double rtol, int m,
+// Restarted FGMRES with the delayed CGS2 Arnoldi process (restart <= 32)
+// for the B >= 1 independent systems of a context.  Each Arnoldi step is
+// one batched launch per kernel (V-cycle, operator, the two Gram-Schmidt
+// passes) followed by the Givens kernel, which updates every system's
+// Hessenberg column, rotations and residual estimate on the device and
+// takes the stopping decision there (GivensLayout areas, kHostScratch
+// doubles per system in hdev).  The host reads back only two values per
+// system and step (estimate, active flag), one step behind the GPU: step
+// j+1 is enqueued before the host waits for step j's flags unless every
+// active system's estimate, extrapolated at its last rate, may reach the
+// tolerance at step j (factor 8 of margin).  A system that has stopped
+// rides along with its state frozen until the cycle ends.  At the end of a
+// cycle the device solves R y = g and updates x += Z y; the restart
+// decision needs the true residual norms (one synchronisation per cycle).
+vkmg_status fgmres_delayed(vkmg_ctx* ctx, const double* b, double* x, double rtol, int m,
                            int max_iters, vkmg_info* info, hipStream_t s) {
+    using GL = GivensLayout;
     const int B = ctx->nb();
     const Geom& g = ctx->top();
     const int64_t n = g.n;
@@ -425,10 +498,7 @@ vkmg_status fgmres_batched(vkmg_ctx* ctx, const double* b, double* x, double rto
     double* Z = ctx->Z;
     double* hd = ctx->hdev;
     double* hh = ctx->hhost;
-    double* dco = hd;
-    double* dcf = hd + 300;
-    double* yd = hd + 600;
-    double* alph = hd + 900;
+    constexpr int kStatus = 1950;  // pinned host: per-step flags, two buffers of 2 doubles
 
     auto norms = [&](const double* v, std::vector<double>& out) -> vkmg_status {
         {
@@ -446,41 +516,13 @@ vkmg_status fgmres_batched(vkmg_ctx* ctx, const double* b, double* x, double rto
         launch_residual<double, double>(g, b, x, r, 0, s, B, ctx->nu64);
     };
     struct Sys {
-        std::vector<double> Hu, R, cs, sn, gbase, gv, y;
-        double beta0 = 0, beta = 0, target = 0, est = 1, true_rel = 0, sigma_prev = 0;
-        int iters = 0, restarts = 0, kdone = 0;
-        bool done = false, active = false, cycled = false;
+        double beta0 = 0, beta = 0, target = 0, est = 1, true_rel = 0;
+        double est_last = 1, est_prev = 0;  // estimates after the last two steps (this cycle)
+        int iters = 0, restarts = 0;
+        bool done = false, active = false;
         vkmg_status status = VKMG_OK;
-        double& H(int i, int j, int m_) { return Hu[size_t(i) * m_ + j]; }
-        double& RR(int i, int j, int m_) { return R[size_t(i) * m_ + j]; }
     };
     std::vector<Sys> sys(B);
-    for (Sys& q : sys) {
-        q.Hu.assign(size_t(m + 1) * m, 0.0);
-        q.R.assign(size_t(m + 1) * m, 0.0);
-        q.cs.assign(m, 0.0);
-        q.sn.assign(m, 0.0);
-        q.gbase.assign(m + 1, 0.0);
-        q.gv.assign(m + 1, 0.0);
-        q.y.assign(m, 0.0);
-    }
-    auto rotate_column = [&](Sys& q, int j) {
-        for (int i = 0; i <= j + 1; ++i) q.RR(i, j, m) = q.H(i, j, m);
-        for (int i = 0; i < j; ++i) {
-            const double t = q.cs[i] * q.RR(i, j, m) + q.sn[i] * q.RR(i + 1, j, m);
-            q.RR(i + 1, j, m) = -q.sn[i] * q.RR(i, j, m) + q.cs[i] * q.RR(i + 1, j, m);
-            q.RR(i, j, m) = t;
-        }
-        const double denom = std::hypot(q.RR(j, j, m), q.RR(j + 1, j, m));
-        q.cs[j] = q.RR(j, j, m) / denom;
-        q.sn[j] = q.RR(j + 1, j, m) / denom;
-        q.RR(j, j, m) = denom;
-        q.RR(j + 1, j, m) = 0.0;
-    };
-    auto rotate_rhs = [&](Sys& q, std::vector<double>& gg, int j) {
-        gg[j + 1] = -q.sn[j] * gg[j];
-        gg[j] = q.cs[j] * gg[j];
-    };
 
     residual();
     std::vector<double> nrm(B);
@@ -499,8 +541,8 @@ vkmg_status fgmres_batched(vkmg_ctx* ctx, const double* b, double* x, double rto
             q.est = q.true_rel = 0.0;
         }
     }
-    // FP32 multigrid: as in the single solve, the update kernel rounds the
-    // next V-cycle inputs and the apply widens the V-cycle outputs
+    // FP32 multigrid: the update kernel rounds the next V-cycle input and the
+    // apply widens the V-cycle output (as the precision casts, fused)
     const bool fp32_mg = ctx->opt.mg_precision == VKMG_FP32;
     auto step = [&](int j, hipStream_t ss) {
         double* vj = V + int64_t(j) * S;
@@ -516,131 +558,138 @@ vkmg_status fgmres_batched(vkmg_ctx* ctx, const double* b, double* x, double rto
         }
         Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);
         launch_dcgs_dots(V, S, j, vj, w, n, ctx->part, ss, B, n);
-        launch_reduce_partials(ctx->part, 2 * j + 3, dco, ss, B, HS);
-        launch_dcgs_update(V, S, j, dco, vj, w, V + int64_t(j + 1) * S, n, dcf, ss, B, n, HS,
+        launch_reduce_partials(ctx->part, 2 * j + 3, hd + GL::kDots, ss, B, HS);
+        launch_dcgs_update(V, S, j, hd + GL::kDots, vj, w, V + int64_t(j + 1) * S, n,
+                           hd + GL::kCoef, ss, B, n, HS,
                            fp32_mg ? static_cast<float*>(ctx->lev.back().b) : nullptr);
+        launch_givens_step(hd, HS, j, B, ss);
     };
     const bool use_graphs = ctx->opt.use_graphs != 0 && ctx->timing_mask == 0;
-    if (use_graphs && ctx->graphs_scheme != 2) {
+    if (use_graphs && ctx->graphs_scheme != 3) {
         drop_graphs(ctx);
-        ctx->graphs_scheme = 2;
+        ctx->graphs_scheme = 3;
     }
+    for (auto& e : ctx->step_done)
+        if (!e) VKMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    auto enqueue_step = [&](int j) -> vkmg_status {
+        if (use_graphs) {
+            vkmg_status sg = step_graph(ctx, j, step);
+            if (sg != VKMG_OK) return sg;
+            VKMG_HIP(hipGraphLaunch(ctx->step_graphs[j], s));
+        } else {
+            step(j, s);
+        }
+        VKMG_HIP(hipMemcpy2DAsync(hh + kStatus + 2 * (j & 1), HS * 8, hd + GL::kScalars + GL::kEst,
+                                  HS * 8, 2 * sizeof(double), B, hipMemcpyDeviceToHost, s));
+        VKMG_HIP(hipEventRecord(ctx->step_done[j & 1], s));
+        return VKMG_OK;
+    };
     for (;;) {
         int nactive = 0;
         for (int k = 0; k < B; ++k) {
             Sys& q = sys[k];
-            q.cycled = q.active = !q.done;
-            q.kdone = 0;
-            q.sigma_prev = 0.0;
-            std::fill(q.Hu.begin(), q.Hu.end(), 0.0);
-            std::fill(q.gbase.begin(), q.gbase.end(), 0.0);
-            q.gbase[0] = q.beta;
-            hh[k * HS + 900] = q.active ? 1.0 / q.beta : 0.0;
+            q.active = !q.done;
+            q.est_last = 1.0;
+            q.est_prev = 0.0;
+            double* sc = hh + k * HS + GL::kScalars;
+            sc[GL::kBeta0] = q.beta0;
+            sc[GL::kTarget] = q.target;
+            sc[GL::kBeta] = q.beta;
+            sc[GL::kSigmaPrev] = 0.0;
+            sc[GL::kEst] = q.est;
+            sc[GL::kActive] = q.active ? 1.0 : 0.0;
+            sc[GL::kIters] = double(q.iters);
+            sc[GL::kKdone] = 0.0;
+            sc[GL::kStatus] = 0.0;
+            sc[GL::kMaxIters] = double(max_iters);
+            sc[GL::kCycled] = q.active ? 1.0 : 0.0;
+            hh[k * HS + GL::kScale] = q.active ? 1.0 / q.beta : 0.0;
             nactive += q.active;
         }
         if (nactive == 0) break;
-        VKMG_HIP(hipMemcpy2DAsync(alph, HS * 8, hh + 900, HS * 8, 8, B, hipMemcpyHostToDevice, s));
+        VKMG_HIP(hipMemcpy2DAsync(hd + GL::kScalars, HS * 8, hh + GL::kScalars, HS * 8,
+                                  (GL::kCycled + 1) * sizeof(double), B, hipMemcpyHostToDevice, s));
+        VKMG_HIP(hipMemcpy2DAsync(hd + GL::kScale, HS * 8, hh + GL::kScale, HS * 8, 8, B,
+                                  hipMemcpyHostToDevice, s));
         {
             Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
-            launch_scale_batched(r, n, alph, HS, V, n, n, B, s);
+            launch_scale_batched(r, n, hd + GL::kScale, HS, V, n, n, B, s);
         }
+        int steps = 0;
+        bool queued = false;  // step j already enqueued
         for (int j = 0; j < m; ++j) {
-            if (use_graphs) {
-                st = step_graph(ctx, j, step);
+            if (!queued) {
+                st = enqueue_step(j);
                 if (st != VKMG_OK) return st;
-                VKMG_HIP(hipGraphLaunch(ctx->step_graphs[j], s));
-            } else {
-                step(j, s);
             }
-            VKMG_HIP(hipMemcpy2DAsync(hh, HS * 8, dco, HS * 8, sizeof(double) * (2 * j + 3), B,
-                                      hipMemcpyDeviceToHost, s));
-            VKMG_HIP(hipMemcpy2DAsync(hh + 300, HS * 8, dcf, HS * 8, sizeof(double) * 4, B,
-                                      hipMemcpyDeviceToHost, s));
-            VKMG_HIP(hipStreamSynchronize(s));
+            queued = false;
+            steps = j + 1;
+            // pre-enqueue step j+1 unless every active system may stop at j
+            if (j >= 1 && j + 1 < m) {
+                bool more = false;
+                for (const Sys& q : sys)
+                    if (q.active && q.iters + 1 < max_iters &&
+                        q.est_last * (q.est_last / q.est_prev) > 8.0 * rtol)
+                        more = true;
+                if (more) {
+                    st = enqueue_step(j + 1);
+                    if (st != VKMG_OK) return st;
+                    queued = true;
+                }
+            }
+            VKMG_HIP(hipEventSynchronize(ctx->step_done[j & 1]));
             int still = 0;
             for (int k = 0; k < B; ++k) {
                 Sys& q = sys[k];
                 if (!q.active) continue;
-                const double* c = hh + k * HS;
-                const double alpha = c[300], gamma = c[301], d = c[302], sigma = c[303];
-                bool finite = true;
-                if (j > 0) {  // finalise column j-1
-                    for (int i = 0; i < j; ++i) q.H(i, j - 1, m) += c[j + i] / q.sigma_prev;
-                    q.H(j, j - 1, m) = alpha / q.sigma_prev;
-                    for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(q.H(i, j - 1, m));
-                }
-                for (int i = 0; i < j; ++i) q.H(i, j, m) = c[i];
-                q.H(j, j, m) = gamma;
-                const double hnext = d > 0.0 ? std::sqrt(d) : 0.0;
-                q.sigma_prev = sigma;
-                for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(q.H(i, j, m));
-                q.H(j + 1, j, m) = hnext;
+                const double* f = hh + k * HS + kStatus + 2 * (j & 1);
                 ++q.iters;
-                if (!finite || !std::isfinite(hnext)) {
-                    q.active = q.cycled = false;
-                    q.done = true;
-                    q.status = VKMG_ERR_NONFINITE;
-                    q.est = q.true_rel = NAN;
-                    continue;
-                }
-                if (j > 0) {
-                    rotate_column(q, j - 1);
-                    rotate_rhs(q, q.gbase, j - 1);
-                }
-                rotate_column(q, j);
-                q.gv = q.gbase;
-                rotate_rhs(q, q.gv, j);
-                q.kdone = j + 1;
-                q.est = std::fabs(q.gv[j + 1]) / q.beta0;
-                if (std::fabs(q.gv[j + 1]) <= q.target || hnext == 0.0 || q.iters >= max_iters)
-                    q.active = false;
-                else
-                    ++still;
+                q.est_prev = q.est_last;
+                q.est_last = f[0];
+                q.est = f[0];
+                q.active = f[1] != 0.0;
+                still += q.active;
             }
             if (still == 0) break;
         }
+        // (a step enqueued past the stop runs with every system frozen; its
+        // basis slot is not read, and the launches below follow it in order)
         // x += Z y per system (zero coefficients beyond its own cycle length)
-        int kmax = 0;
-        for (int k = 0; k < B; ++k) {
-            Sys& q = sys[k];
-            const int kk = q.cycled ? q.kdone : 0;
-            for (int i = kk - 1; i >= 0; --i) {
-                double acc = q.gv[i];
-                for (int l = i + 1; l < kk; ++l) acc -= q.RR(i, l, m) * q.y[l];
-                q.y[i] = acc / q.RR(i, i, m);
-            }
-            kmax = std::max(kmax, kk);
-        }
-        if (kmax > 0) {
-            for (int k = 0; k < B; ++k) {
-                const Sys& q = sys[k];
-                const int kk = q.cycled ? q.kdone : 0;
-                for (int i = 0; i < kmax; ++i) hh[k * HS + 600 + i] = i < kk ? q.y[i] : 0.0;
-            }
-            VKMG_HIP(hipMemcpy2DAsync(yd, HS * 8, hh + 600, HS * 8, sizeof(double) * kmax, B,
-                                      hipMemcpyHostToDevice, s));
+        {
             Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
-            launch_axpy_multi(Z, S, kmax, yd, x, n, s, B, n, HS);
+            launch_givens_solve(hd, HS, steps, B, s);
+            launch_axpy_multi(Z, S, steps, hd + GL::kY, x, n, s, B, n, HS);
         }
+        // state of each system at the end of the cycle
+        VKMG_HIP(hipMemcpy2DAsync(hh + GL::kScalars, HS * 8, hd + GL::kScalars, HS * 8,
+                                  (GL::kCycled + 1) * sizeof(double), B, hipMemcpyDeviceToHost, s));
+        VKMG_HIP(hipMemcpy2DAsync(hh + GL::kGv, HS * 8, hd + GL::kGv, HS * 8,
+                                  (GL::kMaxRestart + 1) * sizeof(double), B,
+                                  hipMemcpyDeviceToHost, s));
         residual();
-        st = norms(r, nrm);
+        st = norms(r, nrm);  // synchronises the stream
         if (st != VKMG_OK) return st;
         bool all_done = true;
         for (int k = 0; k < B; ++k) {
             Sys& q = sys[k];
-            if (q.cycled) {
+            const double* sc = hh + k * HS + GL::kScalars;
+            if (sc[GL::kCycled] != 0.0) {
+                q.iters = int(sc[GL::kIters]);
+                q.est = sc[GL::kEst];
+                const int kd = int(sc[GL::kKdone]);
                 const double rn = nrm[k];
                 q.true_rel = rn / q.beta0;
-                if (!std::isfinite(rn)) {
+                if (sc[GL::kStatus] != 0.0 || !std::isfinite(rn)) {
                     q.done = true;
                     q.status = VKMG_ERR_NONFINITE;
+                    q.est = q.true_rel = NAN;
                 } else if (rn <= q.target) {
                     q.done = true;
                     q.status = VKMG_OK;
                 } else if (q.iters >= max_iters) {
                     q.done = true;
                     q.status = VKMG_ERR_NOT_CONVERGED;
-                } else if (std::fabs(q.gv[q.kdone]) <= q.target && rn > 0.5 * q.beta) {
+                } else if (std::fabs(hh[k * HS + GL::kGv + kd]) <= q.target && rn > 0.5 * q.beta) {
                     // estimate met, true residual did not and did not halve:
                     // below the rounding floor of the system
                     q.done = true;
@@ -667,9 +716,12 @@ vkmg_status fgmres_batched(vkmg_ctx* ctx, const double* b, double* x, double rto
         if (first == VKMG_OK && q.status != VKMG_OK) first = q.status;
     }
     if (first == VKMG_ERR_NOT_CONVERGED)
-        g_last_error = "fgmres_solve: a right-hand side of the batch did not converge";
+        g_last_error = B > 1 ? "fgmres_solve: a right-hand side of the batch did not converge"
+                             : "fgmres_solve: maximum iterations reached or true residual "
+                               "stagnating above the tolerance";
     if (first == VKMG_ERR_NONFINITE)
-        g_last_error = "fgmres_solve: non-finite residual in a right-hand side of the batch";
+        g_last_error = B > 1 ? "fgmres_solve: non-finite residual in a right-hand side of the batch"
+                             : "fgmres_solve: non-finite residual";
     return first;
 }
 
@@ -705,13 +757,126 @@ void vanka_update_with(vkmg_ctx* ctx, int level, void* x, const void* r, void* d
                                     static_cast<double*>(x), static_cast<const double*>(L.W),
                                     static_cast<const double*>(ctx->mtab),
                                     static_cast<double*>(dbuf), ctx->opt.omega, mfma, s,
-                                    ctx->nb());
+                                    ctx->nb(), parked<double>(ctx, L.g.N),
+                                    ctx->tune.boundary_per_wave);
     else
         launch_vanka_update<float>(L.g, static_cast<const float*>(r), static_cast<float*>(x),
                                    static_cast<float*>(x), static_cast<const float*>(L.W),
                                    static_cast<const float*>(ctx->mtab),
                                    static_cast<float*>(dbuf), ctx->opt.omega, mfma, s,
-                                   ctx->nb());
+                                   ctx->nb(), false, ctx->tune.boundary_per_wave);
+}
+
+// Launch shapes measured fastest on MI355X (profiles/ holds the autotuner
+// tables they come from).  Fused sweeps are off: one workgroup then does a
+// tile's residual and boundary-patch work too, which the separate launches
+// spread over the whole GPU, and on the small levels, where every launch is
+// latency-bound, that makes the fused launch longer than the three it
+// replaces.
+vkmg_tuning default_tuning(vkmg_precision p) {
+    vkmg_tuning t;
+    t.fused_sweep_max_n = 0;
+    t.park_min_n = p == VKMG_FP64 ? 512 : std::numeric_limits<int32_t>::max();
+    t.fused_prolong_max_n = 256;
+    t.boundary_per_wave = 0;
+    return t;
+}
+
+bool valid_tuning(const vkmg_tuning& t) {
+    const int b = t.boundary_per_wave;
+    return t.fused_sweep_max_n >= 0 && t.park_min_n >= 0 && t.fused_prolong_max_n >= 0 &&
+           (b == 0 || b == 1 || b == 2 || b == 4 || b == 8);
+}
+
+// Median time of three runs of `reps` V-cycles (graph replays on s), in ms.
+vkmg_status time_vcycles(vkmg_ctx* c, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                         double* ms) {
+    drop_graphs(c);
+    if (!c->capture_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(VKMG_ERR_HIP, std::string("autotune stream: ") + hipGetErrorString(e));
+    }
+    VKMG_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    vcycle_impl(c, c->r64, c->w64, c->capture_stream);
+    hipGraph_t graph = nullptr;
+    VKMG_HIP(hipStreamEndCapture(c->capture_stream, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    VKMG_HIP(ei);
+    double t[3];
+    hipError_t e = hipSuccess;
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = hipGraphLaunch(exec, s);
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+        e = hipEventRecord(e0, s);
+        for (int i = 0; i < reps && e == hipSuccess; ++i) e = hipGraphLaunch(exec, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float f = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+        t[k] = double(f) / reps;
+    }
+    (void)hipGraphExecDestroy(exec);
+    VKMG_HIP(e);
+    std::sort(t, t + 3);
+    *ms = t[1];
+    return VKMG_OK;
+}
+
+vkmg_status autotune_impl(vkmg_ctx* c, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    // input: zeros (timing does not depend on the values)
+    launch_fill_zero<double>(c->r64, c->top().n * c->nb(), s);
+    VKMG_HIP(hipGetLastError());
+    std::vector<int32_t> sizes;  // relaxed level sizes, coarse to fine
+    for (int l = 1; l < c->L; ++l) sizes.push_back(c->lev[l].g.N);
+    const int32_t never = std::numeric_limits<int32_t>::max();
+    const bool fp64 = c->opt.mg_precision == VKMG_FP64;
+    struct Knob {
+        int32_t vkmg_tuning::*field;
+        std::vector<int32_t> cand;
+    };
+    std::vector<Knob> knobs;
+    {
+        std::vector<int32_t> fs{0};
+        for (int32_t N : sizes)
+            if (N >= vanka_fused_min_n()) fs.push_back(N);
+        knobs.push_back({&vkmg_tuning::fused_sweep_max_n, fs});
+    }
+    if (fp64) {
+        std::vector<int32_t> ps(sizes.begin(), sizes.end());
+        ps.push_back(never);
+        knobs.push_back({&vkmg_tuning::park_min_n, ps});
+        std::vector<int32_t> fp{0};
+        fp.insert(fp.end(), sizes.begin(), sizes.end());
+        knobs.push_back({&vkmg_tuning::fused_prolong_max_n, fp});
+    }
+    knobs.push_back({&vkmg_tuning::boundary_per_wave, {0, 1, 2, 4, 8}});
+    double best = 0.0;
+    vkmg_status st = time_vcycles(c, reps, s, e0, e1, &best);
+    if (st != VKMG_OK) return st;
+    for (int round = 0; round < 2; ++round) {
+        for (const Knob& k : knobs) {
+            const int32_t keep = c->tune.*k.field;
+            int32_t choice = keep;
+            for (int32_t v : k.cand) {
+                if (v == keep) continue;
+                c->tune.*k.field = v;
+                double ms = 0.0;
+                st = time_vcycles(c, reps, s, e0, e1, &ms);
+                if (st != VKMG_OK) {
+                    c->tune.*k.field = keep;
+                    return st;
+                }
+                if (ms < 0.99 * best) {
+                    best = ms;
+                    choice = v;
+                }
+            }
+            c->tune.*k.field = choice;
+        }
+    }
+    drop_graphs(c);
+    return VKMG_OK;
 }
 
 }  // namespace
@@ -887,6 +1052,7 @@ static vkmg_status setup_impl(const vkmg_grid* grid, int32_t levels, double nu,
     std::unique_ptr<vkmg_ctx> c(new vkmg_ctx);
     c->L = levels;
     c->opt = o;
+    c->tune = default_tuning(o.mg_precision);
     c->variable = nu_elem != nullptr;
     VKMG_HIP(hipGetDevice(&c->device));
     hipStream_t s = as_stream(hip_stream);
@@ -1159,6 +1325,49 @@ vkmg_status vkmg_vanka_update_noalloc(vkmg_ctx* ctx, int32_t level, void* x, con
     return VKMG_OK;
 }
 
+vkmg_status vkmg_get_tuning(const vkmg_ctx* ctx, vkmg_tuning* out) {
+    if (!ctx || !out) return fail(VKMG_ERR_INVALID_ARG, "get_tuning: NULL argument");
+    *out = ctx->tune;
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_set_tuning(vkmg_ctx* ctx, const vkmg_tuning* tuning) {
+    if (!ctx || !tuning) return fail(VKMG_ERR_INVALID_ARG, "set_tuning: NULL argument");
+    if (!valid_tuning(*tuning))
+        return fail(VKMG_ERR_INVALID_ARG,
+                    "set_tuning: sizes must be >= 0 and boundary_per_wave 0, 1, 2, 4 or 8");
+    ctx->tune = *tuning;
+    drop_graphs(ctx);  // captured Arnoldi steps follow the old launch shapes
+    return VKMG_OK;
+}
+
+vkmg_status vkmg_autotune(vkmg_ctx* ctx, int32_t reps, void* stream, vkmg_tuning* out) {
+    if (!ctx) return fail(VKMG_ERR_INVALID_ARG, "autotune: NULL context");
+    if (reps < 1) return fail(VKMG_ERR_INVALID_ARG, "autotune: reps must be >= 1");
+    if (ctx->timing_mask)
+        return fail(VKMG_ERR_INVALID_ARG, "autotune: kernel timing is on (vkmg_set_timing)");
+    VKMG_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    VKMG_HIP(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        VKMG_HIP(e);
+    }
+    const vkmg_tuning before = ctx->tune;
+    const vkmg_status st = autotune_impl(ctx, reps, s, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != VKMG_OK) {
+        ctx->tune = before;
+        drop_graphs(ctx);
+        return st;
+    }
+    if (out) *out = ctx->tune;
+    return VKMG_OK;
+}
+
 vkmg_status vkmg_restrict(vkmg_ctx* ctx, int32_t level, const void* r_fine, void* b_coarse,
                           void* stream) {
     if (!r_fine || !b_coarse || !check_level(ctx, level, true))
@@ -1240,7 +1449,8 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
     hipStream_t s = as_stream(stream);
     vkmg_status st = ensure_basis(ctx, restart);
     if (st != VKMG_OK) return st;
-    if (ctx->nb() > 1) return fgmres_batched(ctx, b, x, rtol, restart, max_iters, info, s);
+    if (restart <= kDelayedMaxRestart)
+        return fgmres_delayed(ctx, b, x, rtol, restart, max_iters, info, s);
     const Geom& g = ctx->top();
     const int64_t n = g.n;
     const int64_t ld = basis_stride(n);
@@ -1278,8 +1488,9 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
     double beta = beta0;
     // Hu: the Hessenberg matrix as built; R: its columns after the Givens
     // rotations; gbase: the right-hand side beta e1 after the rotations of
-    // the columns before the previous one (whose rotation is redone each
-    // step, as the delayed scheme finalises that column one step late)
+    // the columns before the previous one (the same bookkeeping as the
+    // device Givens kernel of the delayed scheme, where that column is
+    // finalised one step late; here redoing its rotation changes nothing)
     std::vector<double> Hu(size_t(m + 1) * m), R(size_t(m + 1) * m), cs(m), sn(m), gbase(m + 1),
         gv(m + 1), y(m);
     auto Hij = [&](int i, int j) -> double& { return Hu[size_t(i) * m + j]; };
@@ -1304,18 +1515,9 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
     double est = 1.0;
     double* h1 = ctx->hdev;        // first Gram-Schmidt pass, j+1 values
     double* h2 = ctx->hdev + 300;  // second pass, j+1 values, then ||w||^2 at [j+1]
-    // Both schemes are classical Gram-Schmidt with one reorthogonalisation
-    // (orthogonal to working accuracy; multi-vector passes over the basis).
-    // Delayed (restart <= 32): the reorthogonalisation of basis vector j
-    // shares the sweep that first orthogonalises w = A z_j, two passes per
-    // step.  Step j sees final v_0..v_{j-1} and u_j in slot j, the
-    // once-orthogonalised successor of step j-1 scaled by sigma_{j-1};
-    // pass 1 takes V^T w, V^T u, u.u, u.w, w.w, pass 2 writes
-    // v_j = (u_j - V s) / alpha over slot j and u_{j+1} into slot j+1.
-    // Column j-1 of H becomes final in step j (H(i,j-1) += s_i / sigma_{j-1},
-    // H(j,j-1) = alpha_j / sigma_{j-1}); column j is provisional with
-    // H(j+1,j) = sqrt(d), which the stopping test uses.
-    // Classical (restart > 32, Giraud et al.'s CGS2): h1 = V^T w;
+    // Restarts > 32 (shorter ones take fgmres_delayed): classical
+    // Gram-Schmidt with one reorthogonalisation (Giraud et al.'s CGS2,
+    // orthogonal to working accuracy; multi-vector passes): h1 = V^T w;
     // w' = w - V h1 with h2 = V^T w' and |w'|^2 in the same pass;
     // v_{j+1} = (w' - V h2) / |w' - V h2| in a third, with
     // |w' - V h2|^2 = |w'|^2 - |h2|^2 (V orthonormal).  Beyond 32 basis
@@ -1323,20 +1525,14 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
     // request.
     // Every pointer depends only on j, so a step can be captured once per j
     // and replayed.
-    const bool delayed = m <= kDelayedMaxRestart;
     const bool fp32_mg = ctx->opt.mg_precision == VKMG_FP32;
-    // delayed: the 2j+3 reduced values of pass 1 of step j, followed by its
-    // alpha, gamma, d, sigma (one copy to the host per step)
-    double* dco = ctx->hdev;
     auto arnoldi_step = [&](int j, hipStream_t ss) {
         double* vj = V + int64_t(j) * ld;
         double* zj = Z + int64_t(j) * ld;
         const int kb = j + 1;
-        // delayed scheme, FP32 multigrid: the V-cycle input of step j >= 1
-        // was rounded to FP32 by the update kernel of step j-1
         // FP32 multigrid: z_j stays FP32 and the apply w = A z_j writes it
         // widened into the basis
-        vcycle_impl(ctx, vj, zj, ss, delayed && fp32_mg && j >= 1, fp32_mg);
+        vcycle_impl(ctx, vj, zj, ss, false, fp32_mg);
         {
             Timed t(ctx, VKMG_KERNEL_RESIDUAL, ss);
             if (fp32_mg)
@@ -1344,14 +1540,6 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
                                    ctx->nu64);
             else
                 launch_residual<double, double>(g, nullptr, zj, w, 1, ss, 1, ctx->nu64);
-        }
-        if (delayed) {
-            Timed t(ctx, VKMG_KERNEL_KRYLOV, ss);
-            launch_dcgs_dots(V, ld, j, vj, w, n, ctx->part, ss);
-            launch_reduce_partials(ctx->part, 2 * j + 3, dco, ss);
-            launch_dcgs_update(V, ld, j, dco, vj, w, V + int64_t(kb) * ld, n, dco + 2 * j + 3, ss,
-                               1, 0, 0, fp32_mg ? static_cast<float*>(ctx->lev.back().b) : nullptr);
-            return;
         }
         dots_async(ctx, V, ld, kb, w, h1, ss);
         if (kb <= 32) {
@@ -1376,21 +1564,10 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
     // kernels are timed (events recorded inside a replayed graph cannot be
     // read back with hipEventElapsedTime)
     const bool use_graphs = ctx->opt.use_graphs != 0 && ctx->timing_mask == 0;
-    if (use_graphs && ctx->graphs_scheme != int(delayed)) {
+    if (use_graphs && ctx->graphs_scheme != 0) {
         drop_graphs(ctx);
-        ctx->graphs_scheme = int(delayed);
+        ctx->graphs_scheme = 0;
     }
-    // Pipelined steps (delayed scheme with graphs): step j+1 needs nothing
-    // from the host, so it is enqueued before the host waits for the
-    // coefficients of step j (double-buffered pinned copies, one event per
-    // buffer), unless the residual estimate, extrapolated at its last rate,
-    // may reach the tolerance at step j; a step enqueued past convergence is
-    // left unused.
-    const bool pipe = use_graphs && delayed;
-    if (pipe)
-        for (auto& e : ctx->step_done)
-            if (!e) VKMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    double* const hbuf[2] = {ctx->hhost + 650, ctx->hhost + 800};
     auto enqueue_step = [&](int j) -> vkmg_status {
         if (use_graphs) {
             vkmg_status sg = step_graph(ctx, j, arnoldi_step);
@@ -1398,11 +1575,6 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
             VKMG_HIP(hipGraphLaunch(ctx->step_graphs[j], s));
         } else {
             arnoldi_step(j, s);
-        }
-        if (delayed) {
-            VKMG_HIP(hipMemcpyAsync(hbuf[j & 1], dco, sizeof(double) * (2 * j + 7),
-                                    hipMemcpyDeviceToHost, s));
-            if (pipe) VKMG_HIP(hipEventRecord(ctx->step_done[j & 1], s));
         }
         return VKMG_OK;
     };
@@ -1415,59 +1587,27 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
         std::fill(gbase.begin(), gbase.end(), 0.0);
         gbase[0] = beta;
         int k = 0;
-        double sigma_prev = 0.0;
-        bool queued = false;              // step j already enqueued
-        double g_last = beta, g_prev = 0.0;  // |g| after the last two steps
         for (int j = 0; j < m; ++j) {
             const int kb = j + 1;  // basis vectors so far
             const bool normalized = kb <= 32;
             double hnext = 0.0;
-            if (!queued) {
-                st = enqueue_step(j);
-                if (st != VKMG_OK) return st;
-            }
-            queued = false;
-            if (pipe && j >= 1 && j + 1 < m && total + 1 < max_iters &&
-                g_last * (g_last / g_prev) > 8.0 * target) {
-                st = enqueue_step(j + 1);
-                if (st != VKMG_OK) return st;
-                queued = true;
-            }
+            st = enqueue_step(j);
+            if (st != VKMG_OK) return st;
             bool finite = true;
-            if (delayed) {
-                if (pipe) {
-                    VKMG_HIP(hipEventSynchronize(ctx->step_done[j & 1]));
-                } else {
-                    VKMG_HIP(hipStreamSynchronize(s));
-                }
-                const double* c = hbuf[j & 1];
-                const double alpha = c[2 * j + 3], gamma = c[2 * j + 4];
-                const double d = c[2 * j + 5], sigma = c[2 * j + 6];
-                if (j > 0) {  // finalise column j-1
-                    for (int i = 0; i < j; ++i) Hij(i, j - 1) += c[j + i] / sigma_prev;
-                    Hij(j, j - 1) = alpha / sigma_prev;
-                    for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(Hij(i, j - 1));
-                }
-                for (int i = 0; i < j; ++i) Hij(i, j) = c[i];
-                Hij(j, j) = gamma;
+            VKMG_HIP(hipMemcpyAsync(ctx->hhost, h1, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
+            VKMG_HIP(hipMemcpyAsync(ctx->hhost + 300, h2, sizeof(double) * (kb + 1), hipMemcpyDeviceToHost, s));
+            VKMG_HIP(hipStreamSynchronize(s));
+            double hh = 0.0;
+            for (int i = 0; i <= j; ++i) {
+                Hij(i, j) = ctx->hhost[i] + ctx->hhost[300 + i];
+                hh += ctx->hhost[300 + i] * ctx->hhost[300 + i];
+            }
+            if (normalized) {
+                // the formula of the normalisation kernel
+                const double d = ctx->hhost[300 + kb] - hh;
                 hnext = d > 0.0 ? std::sqrt(d) : 0.0;
-                sigma_prev = sigma;
             } else {
-                VKMG_HIP(hipMemcpyAsync(ctx->hhost, h1, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
-                VKMG_HIP(hipMemcpyAsync(ctx->hhost + 300, h2, sizeof(double) * (kb + 1), hipMemcpyDeviceToHost, s));
-                VKMG_HIP(hipStreamSynchronize(s));
-                double hh = 0.0;
-                for (int i = 0; i <= j; ++i) {
-                    Hij(i, j) = ctx->hhost[i] + ctx->hhost[300 + i];
-                    hh += ctx->hhost[300 + i] * ctx->hhost[300 + i];
-                }
-                if (normalized) {
-                    // the formula of the normalisation kernel
-                    const double d = ctx->hhost[300 + kb] - hh;
-                    hnext = d > 0.0 ? std::sqrt(d) : 0.0;
-                } else {
-                    hnext = std::sqrt(ctx->hhost[300 + kb]);
-                }
+                hnext = std::sqrt(ctx->hhost[300 + kb]);
             }
             for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(Hij(i, j));
             Hij(j + 1, j) = hnext;
@@ -1481,14 +1621,12 @@ vkmg_status vkmg_fgmres_solve(vkmg_ctx* ctx, const double* b, double* x, double 
             gv = gbase;
             rotate_rhs(gv, j);
             const bool breakdown = hnext == 0.0;
-            if (!delayed && !breakdown && !normalized) {
+            if (!breakdown && !normalized) {
                 Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
                 launch_scale(w, 1.0 / hnext, V + int64_t(j + 1) * ld, n, s);
             }
             ++total;
             k = j + 1;
-            g_prev = g_last;
-            g_last = std::fabs(gv[j + 1]);
             est = std::fabs(gv[j + 1]) / beta0;
             if (std::fabs(gv[j + 1]) <= target) break;
             if (breakdown || total >= max_iters) break;

@@ -61,20 +61,34 @@ void launch_pressure_mean_zero(const Geom& g, double* x, double* part, double* s
 // patches (vanka_boundary_scratch(N) values per right-hand side).  The
 // interior patches are applied on the matrix instructions with the operand
 // table `mtab` (kMfmaTable values, mfma_interior_table) when `mfma`, else on
-// the vector ALUs with the compile-time constants.
+// the vector ALUs with the compile-time constants.  Launch shape only (the
+// results do not depend on them): `park` selects the FP64 tile kernel that
+// parks half of a patch in LDS during the apply (160 instead of 229 VGPRs,
+// three waves per SIMD instead of two); `per_wave` boundary patches per
+// wavefront (1, 2, 4 or 8; 0: from the patch count).
 template <typename T>
 void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const T* table,
                          const T* mtab, T* dbuf, double omega, bool mfma, hipStream_t s,
-                         int nb = 1);
+                         int nb = 1, bool park = false, int per_wave = 0);
 // The two launches of launch_vanka_update, in that order: the boundary-patch
 // corrections into dbuf, then the interior tiles (which also commit dbuf).
 template <typename T>
 void launch_vanka_boundary(const Geom& g, const T* r, const T* table, T* dbuf, hipStream_t s,
-                           int nb = 1);
+                           int nb = 1, int per_wave = 0);
 template <typename T>
 void launch_vanka_tiles(const Geom& g, const T* r, const T* xin, T* xout, const T* mtab,
-                        const T* dbuf, double omega, bool mfma, hipStream_t s, int nb = 1);
+                        const T* dbuf, double omega, bool mfma, hipStream_t s, int nb = 1,
+                        bool park = false);
 int64_t vanka_boundary_scratch(int N);
+// One complete Vanka sweep in one launch (levels with N >= vanka_fused_min_n()):
+// r = b - A x_in and x_out = x_in + sum_i V_i^T W_i A_i^{-1} V_i r, bitwise
+// the residual launch followed by launch_vanka_update (vector apply).
+// x_out must not alias x_in; x_in == nullptr means x_in = 0 (r = b).
+// `table` as for launch_vanka_update.  No scratch.
+template <typename T>
+void launch_vanka_fused(const Geom& g, const T* b, const T* xin, T* xout, const T* table,
+                        double omega, hipStream_t s, int nb = 1);
+int vanka_fused_min_n();
 // Vanka update with one stored weighted inverse per patch ("simple" Vanka,
 // for a per-element viscosity): `tables` holds (N+1)^2 transposed 51 x 51
 // inverses (simple_vanka_tables), `dbuf` (N+1)^2 * 64 values per
@@ -113,6 +127,40 @@ template <typename Ti, typename To>
 void launch_cast(const Ti* in, To* out, int64_t n, hipStream_t s);
 // x = b on the Dirichlet DoFs of level g, 0 elsewhere (nb vectors, FP64).
 void launch_lift(const Geom& g, const double* b, double* x, hipStream_t s, int nb = 1);
+
+// Per-system area of the device-side FGMRES of the delayed scheme
+// (restart <= kMaxRestart), `stride` doubles apart (offsets in doubles):
+// the reduced dots of a step, its pass-2 coefficients, the solution of the
+// small system, the pressure-mean scratch, then the Givens state.  The
+// scalars are doubles (flags 0/1, counts exact).
+struct GivensLayout {
+    static constexpr int kMaxRestart = 32;
+    static constexpr int kDots = 0;       // 2j + 3 reduced values of pass 1
+    static constexpr int kCoef = 300;     // alpha, gamma, d, sigma of pass 2
+    static constexpr int kY = 600;        // y (kMaxRestart)
+    static constexpr int kScale = 900;    // 1 / beta at the start of a cycle
+    static constexpr int kMean = 1000;    // pressure-mean scratch
+    static constexpr int kCs = 1100;      // cos of the rotations (kMaxRestart)
+    static constexpr int kSn = 1140;      // sin
+    static constexpr int kGbase = 1180;   // rhs after the final rotations (kMaxRestart + 1)
+    static constexpr int kGv = 1220;      // rhs after the provisional rotation too
+    static constexpr int kHcol = 34;      // one unrotated Hessenberg column
+    static constexpr int kHcols = 1260;   // two of them (step parity)
+    static constexpr int kR = 1330;       // rotated columns, column j at j(j+3)/2, j+2 values
+    static constexpr int kScalars = 1900;
+    // scalar slots (kScalars + ...)
+    static constexpr int kBeta0 = 0, kTarget = 1, kBeta = 2, kSigmaPrev = 3, kEst = 4,
+                         kActive = 5, kIters = 6, kKdone = 7, kStatus = 8, kMaxIters = 9,
+                         kCycled = 10;
+    static constexpr int kSize = 1920;
+};
+static_assert(GivensLayout::kR + 32 * 35 / 2 <= GivensLayout::kScalars, "packed R fits");
+
+// One Givens step of the delayed-scheme FGMRES for nsys systems (areas
+// `stride` apart), after the Gram-Schmidt kernels of Arnoldi step j.
+void launch_givens_step(double* area, int64_t stride, int j, int nsys, hipStream_t s);
+// y of every system from its rotated system (zeros from kdone to kmax).
+void launch_givens_solve(double* area, int64_t stride, int kmax, int nsys, hipStream_t s);
 
 // Krylov kernels (FP64).  V: k vectors of length n with stride ldv; with
 // nb > 1 the batch entries of every vector are sb apart.  Partial sums:

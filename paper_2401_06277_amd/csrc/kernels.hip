@@ -743,11 +743,6 @@ __device__ __forceinline__ void pin(T& a) {
 // and 2 while blocks 0 and 3 are.  `park` is this lane's column of a
 // [26][VNT] LDS area that no other lane touches.
 constexpr int kPark = 26;
-// FP64 tile kernel with parking (160 VGPRs, three waves per SIMD, 52 KiB of
-// LDS) on levels with at least this many elements per side; below, where a
-// launch is one or two waves per SIMD, the extra LDS round trips and barrier
-// lengthen each wave and the two-wave form (229 VGPRs) is faster.
-constexpr int kParkMinN = 512;
 template <typename T>
 __device__ __forceinline__ void sym_apply_parked(T (&v)[kSlots], T t, T* park) {
     const D4Table& d = kD4Table;
@@ -1264,6 +1259,338 @@ __global__ __launch_bounds__(VNT, PARK ? 3 : 2) void vanka_sweep_kernel(Geom g, 
     if (valid && tx >= 1 && tx <= VT && ty >= 1 && ty <= VT) {
         const int64_t q = 2 * g.nq2 + int64_t(J) * g.s1 + I;
         xout[q] = ob.p + rv[50];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused sweep for the small levels (latency-bound there): r = b - A x_in
+// and the Vanka update x_out = x_in + sum_i V_i^T W_i A_i^{-1} V_i r in ONE
+// launch, instead of the residual, boundary-patch and tile launches.  Same
+// tile, patch order and owner sums as vanka_sweep_kernel, and the same
+// arithmetic in the same order as those three kernels (results bitwise
+// equal), with x_out != x_in (a tile reads x_in up to three elements beyond
+// the DoFs it owns).  XIN = false: x_in = 0, so r = b.
+//
+// Workgroup of 12 waves:
+//   * all waves stage x_in (Q2 nodes [2E0-6, 2E0+2VT+6), Q1 [E0-3, E0+VT+3),
+//     Dirichlet and outside nodes zero, as residual_kernel) and then form
+//     the residual of the tile's r region (18 x 18 cells, two row parities:
+//     cell_row_pair on the staged values) into LDS, unscaled;
+//   * waves 0-3: one patch per lane as in vanka_sweep_kernel (gather with
+//     the scaling of stage_residual_region, interior operator, owner sums);
+//   * waves 4-11: the tile's boundary patches row-parallel, as
+//     vanka_boundary_kernel, one class per wave so that its coefficient rows
+//     are loaded once, during the staging: waves 4/5 the non-corner patches
+//     of the (at most two) boundary patch rows of the tile, 6/7 those of the
+//     boundary patch columns, 8-11 the (at most four) corner patches.  Their
+//     corrections go to an LDS slot table that the boundary lanes of waves
+//     0-3 read before the owner sums.
+// Needs N >= 16 (a tile then meets at most two boundary patch rows and two
+// boundary patch columns).
+// ---------------------------------------------------------------------------
+
+constexpr int FX2 = 2 * VT + 12;  // staged Q2 nodes of x_in per side (offset -6)
+constexpr int FX1 = VT + 6;       // staged Q1 nodes of x_in per side (offset -3)
+constexpr int FC = VT + 4;        // cells per side whose rows are formed (offset -2)
+constexpr int FNT = 3 * VNT;      // threads per workgroup
+constexpr int kFItems = 2 * FC * FC;                     // (cell, row parity) items
+constexpr int kFX = 2 * FX2 * FX2 + FX1 * FX1;           // staged x_in
+constexpr int kFSlots = 68;                              // rows 0-31, columns 32-63, corners 64-67
+constexpr int kFSlotStride = 52;
+constexpr int kFArea = (kPark * VNT > kFX) ? kPark * VNT : kFX;  // x_in, then park, then exchange
+constexpr int kFusedLds = kFArea + kRRegion + kFSlots * kFSlotStride;
+constexpr int kFusedMinN = 16;
+static_assert(kFItems <= FNT, "one residual item per thread");
+static_assert(kExchange <= kFArea, "exchange fits the staging area");
+
+// The boundary patch rows (J) or columns (I) that a tile window
+// [E0 - 1, E0 + VP - 2] meets, in increasing order: at most two for N >= 16.
+__device__ __forceinline__ int tile_boundary_lines(int E0, int N, int (&line)[2]) {
+    const int cand[4] = {0, 1, N - 1, N};
+    int k = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int v = cand[c];
+        if (v >= E0 - 1 && v <= E0 + VP - 2 && k < 2) line[k++] = v;
+    }
+    if (k < 2) line[1] = -1;
+    if (k < 1) line[0] = -1;
+    return k;
+}
+
+template <typename T, bool XIN>
+__global__ __launch_bounds__(FNT, 1) void vanka_fused_kernel(Geom g, const T* __restrict__ b,
+                                                             const T* __restrict__ xin,
+                                                             T* __restrict__ xout,
+                                                             const T* __restrict__ table,
+                                                             T scale, T t) {
+    constexpr bool kPark = std::is_same<T, double>::value;  // FP64: parked interior apply
+    __shared__ T s_buf[kFusedLds];
+    T* const sx0 = s_buf;                 // staged x_in (phase 1)
+    T* const sx1 = sx0 + FX2 * FX2;
+    T* const sxp = sx1 + FX2 * FX2;
+    T* const sr0 = s_buf + kFArea;        // residual of the r region (unscaled)
+    T* const sr1 = sr0 + VR * VR;
+    T* const srp = sr1 + VR * VR;
+    T* const sdel = sr0 + kRRegion;       // boundary-patch corrections by slot
+    const int tiles = vanka_tiles(g.N);
+    const int ntile = tiles * tiles;
+    const int per_xcd = (ntile + 7) / 8;
+    const int tlin = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (tlin >= ntile) return;
+    {  // right-hand side blockIdx.y of a batch
+        const int64_t bo = int64_t(blockIdx.y) * g.n;
+        b += bo;
+        if (XIN) xin += bo;
+        xout += bo;
+    }
+    const int E0x = (tlin % tiles) * VT, E0y = (tlin / tiles) * VT;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    int brow[2], bcol[2];
+    const int nbr = tile_boundary_lines(E0y, g.N, brow);
+    const int nbc = tile_boundary_lines(E0x, g.N, bcol);
+
+    // ---- phase 0: every global load of the staging is issued first (the
+    // owners' x_in loads too, except with the parked apply, which has no
+    // registers to spare for them: there they follow the apply)
+    OwnerBase<T> ob;
+    if (!kPark && wave < 4) owner_prefetch(g, E0x, E0y, XIN ? xin : nullptr, ob);
+
+    // boundary waves: their group (class) and its coefficient rows
+    const int bw = wave - 4;
+    int gcls = -1;
+    if (bw >= 0) {
+        if (bw < 2) {
+            if (bw < nbr) gcls = 5 * dclass(brow[bw], g.N) + 2;
+        } else if (bw < 4) {
+            if (bw - 2 < nbc) gcls = 10 + dclass(bcol[bw - 2], g.N);
+        } else {
+            const int rr = (bw - 4) >> 1, cc = (bw - 4) & 1;
+            if (rr < nbr && cc < nbc) gcls = 5 * dclass(brow[rr], g.N) + dclass(bcol[cc], g.N);
+        }
+    }
+    // (loaded with the staging when no residual is formed, else once this
+    // thread's residual item is done: registers)
+    const int cs = lane < kSlots ? lane : 0;
+    T m[kSlots];
+    if (!XIN && gcls >= 0) {
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) m[k] = table[(gcls * kSlots + k) * kSlots + cs];
+    }
+
+    // residual item of this thread: cell (ex, ey), row parity bb
+    const int item = tid;
+    const bool has_item = XIN && item < kFItems;
+    const int bb = (item / (FC * FC)) & 1;
+    const int cidx = item % (FC * FC);
+    const int cx = cidx % FC, cy = cidx / FC;
+    const int ex = E0x - 2 + cx, ey = E0y - 2 + cy;
+    int64_t qn[2];
+    bool inm[2], dir[2];
+    T bxv[2], byv[2], xdx[2], xdy[2];
+    T bp = 0;
+    const bool pitem = has_item && bb == 0 && cx >= 1 && cx <= VT + 2 && cy >= 1 && cy <= VT + 2;
+    const bool pin = pitem && ex >= 0 && ey >= 0 && ex <= g.N && ey <= g.N;
+    if (XIN) {
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) {
+            const int i = 2 * ex + aa, j = 2 * ey + bb;
+            inm[aa] = has_item && i >= 0 && j >= 0 && i < g.s2 && j < g.s2;
+            dir[aa] = inm[aa] && (i == 0 || j == 0 || i == g.s2 - 1 || j == g.s2 - 1);
+            qn[aa] = inm[aa] ? int64_t(j) * g.s2 + i : 0;
+            bxv[aa] = b[qn[aa]];
+            byv[aa] = b[g.nq2 + qn[aa]];
+            xdx[aa] = xin[qn[aa]];
+            xdy[aa] = xin[g.nq2 + qn[aa]];
+        }
+        bp = b[2 * g.nq2 + (pin ? int64_t(ey) * g.s1 + ex : 0)];
+
+        // x_in on the staged nodes (clamped addresses, zeroed afterwards)
+        constexpr int kI2 = (FX2 * FX2 + FNT - 1) / FNT, kI1 = (FX1 * FX1 + FNT - 1) / FNT;
+        T v0[kI2], v1[kI2], vp[kI1];
+        bool f2[kI2], f1[kI1];
+        const int ox = 2 * E0x - 6, oy = 2 * E0y - 6;
+#pragma unroll
+        for (int it = 0; it < kI2; ++it) {
+            const int k = tid + it * FNT;
+            const int qi = ox + k % FX2, qj = oy + k / FX2;
+            f2[it] = k < FX2 * FX2 && qi > 0 && qj > 0 && qi < g.s2 - 1 && qj < g.s2 - 1;
+            const int64_t q = f2[it] ? int64_t(qj) * g.s2 + qi : 0;
+            v0[it] = xin[q];
+            v1[it] = xin[g.nq2 + q];
+        }
+#pragma unroll
+        for (int it = 0; it < kI1; ++it) {
+            const int k = tid + it * FNT;
+            const int I = E0x - 3 + k % FX1, J = E0y - 3 + k / FX1;
+            f1[it] = k < FX1 * FX1 && I >= 0 && J >= 0 && I <= g.N && J <= g.N;
+            vp[it] = xin[2 * g.nq2 + (f1[it] ? int64_t(J) * g.s1 + I : 0)];
+        }
+#pragma unroll
+        for (int it = 0; it < kI2; ++it) {
+            const int k = tid + it * FNT;
+            if (k < FX2 * FX2) {
+                sx0[k] = f2[it] ? v0[it] : T(0);
+                sx1[k] = f2[it] ? v1[it] : T(0);
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < kI1; ++it) {
+            const int k = tid + it * FNT;
+            if (k < FX1 * FX1) sxp[k] = f1[it] ? vp[it] : T(0);
+        }
+    } else {
+        // r = b on the r region (nodes outside the mesh zero)
+        constexpr int kIt = (VR * VR + FNT - 1) / FNT;
+        const int ox = 2 * E0x - 4, oy = 2 * E0y - 4;
+        T v0[kIt], v1[kIt];
+        bool in[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int k = tid + it * FNT;
+            const int qi = ox + k % VR, qj = oy + k / VR;
+            in[it] = k < VR * VR && qi >= 0 && qj >= 0 && qi < g.s2 && qj < g.s2;
+            const int64_t q = in[it] ? int64_t(qj) * g.s2 + qi : 0;
+            v0[it] = b[q];
+            v1[it] = b[g.nq2 + q];
+        }
+        const int I = E0x - 1 + tid % VR1, J = E0y - 1 + tid / VR1;
+        const bool pv = tid < VR1 * VR1 && I >= 0 && J >= 0 && I <= g.N && J <= g.N;
+        const T vpp = b[2 * g.nq2 + (pv ? int64_t(J) * g.s1 + I : 0)];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int k = tid + it * FNT;
+            if (k < VR * VR) {
+                sr0[k] = in[it] ? v0[it] : T(0);
+                sr1[k] = in[it] ? v1[it] : T(0);
+            }
+        }
+        if (tid < VR1 * VR1) srp[tid] = pv ? vpp : T(0);
+    }
+    __syncthreads();
+
+    // ---- phase 1: residual rows of the r region (cell_row_pair, as residual_kernel)
+    if (XIN && has_item) {
+        T ax[2], ay[2], ap;
+        const int c2 = (2 * cy + 2) * FX2 + 2 * cx + 2, c1 = (cy + 1) * FX1 + cx + 1;
+        const T cl = T(g.nu / 90.0), cb = T(-g.h / 36.0);
+        if (bb == 0)
+            cell_row_pair<FX2, FX1, 0>(sx0, sx1, sxp, c2, c1, cl, cb, ax, ay, ap);
+        else
+            cell_row_pair<FX2, FX1, 1>(sx0, sx1, sxp, c2, c1, cl, cb, ax, ay, ap);
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) {
+            const int rx = 2 * cx + aa, ry = 2 * cy + bb;
+            if (rx >= VR || ry >= VR) continue;
+            const T vx = dir[aa] ? xdx[aa] : ax[aa];
+            const T vy = dir[aa] ? xdy[aa] : ay[aa];
+            sr0[ry * VR + rx] = inm[aa] ? bxv[aa] - vx : T(0);
+            sr1[ry * VR + rx] = inm[aa] ? byv[aa] - vy : T(0);
+        }
+        if (pitem) srp[(cy - 1) * VR1 + cx - 1] = pin ? bp - ap : T(0);
+    }
+    if (XIN) {
+        if (gcls >= 0) {
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) m[k] = table[(gcls * kSlots + k) * kSlots + cs];
+        }
+        __syncthreads();
+    }
+
+    // ---- phase 2: patch solves
+    const int tx = tid % VP, ty = (tid / VP) % VP;
+    const int I = E0x - 1 + tx, J = E0y - 1 + ty;
+    const bool valid = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
+    T rv[kSlots];
+    if (wave < 4) {
+#pragma unroll
+        for (int bq = 0; bq < 5; ++bq)
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                const int l = (2 * ty + bq) * VR + 2 * tx + a;
+                rv[5 * bq + a] = scale * sr0[l];
+                rv[25 + 5 * bq + a] = scale * sr1[l];
+            }
+        rv[50] = (scale * t) * srp[ty * VR1 + tx];
+        if (kPark)
+            sym_apply_parked(rv, t, s_buf + tid);
+        else
+            sym_apply(rv, t);
+    } else if (gcls >= 0) {
+        // this wave's boundary patches: position p of its row, column or corner
+        const int np = bw < 4 ? VP : 1;
+        for (int p = 0; p < np; ++p) {
+            int px, py, slot;
+            if (bw < 2) {
+                px = p;
+                py = brow[bw] - E0y + 1;
+                slot = bw * VP + p;
+            } else if (bw < 4) {
+                px = bcol[bw - 2] - E0x + 1;
+                py = p;
+                slot = 2 * VP + (bw - 2) * VP + p;
+            } else {
+                px = bcol[(bw - 4) & 1] - E0x + 1;
+                py = brow[(bw - 4) >> 1] - E0y + 1;
+                slot = 4 * VP + (bw - 4);
+            }
+            const int pI = E0x - 1 + px, pJ = E0y - 1 + py;
+            const bool mid_i = pI >= 2 && pI <= g.N - 2, mid_j = pJ >= 2 && pJ <= g.N - 2;
+            const bool take = pI >= 0 && pI <= g.N && pJ >= 0 && pJ <= g.N &&
+                              (bw < 2 ? mid_i : bw < 4 ? mid_j : true);
+            if (!take) continue;  // uniform over the wave
+            auto rs = [&](int s) -> T {
+                if (s == kSlots - 1) return srp[py * VR1 + px];
+                const int f = s / 25, l = s % 25;
+                return (f ? sr1 : sr0)[(2 * py + l / 5) * VR + 2 * px + l % 5];
+            };
+            T a0 = 0, a1 = 0;
+#pragma unroll
+            for (int k = 0; k + 1 < kSlots; k += 2) {
+                a0 += m[k] * rs(k);
+                a1 += m[k + 1] * rs(k + 1);
+            }
+            a0 += m[kSlots - 1] * rs(kSlots - 1);
+            if (lane < kSlots) sdel[slot * kFSlotStride + lane] = a0 + a1;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 3: boundary lanes take their corrections; x-sums; owners
+    if (kPark && wave < 4) owner_prefetch(g, E0x, E0y, XIN ? xin : nullptr, ob);
+    if (wave < 4) {
+        const bool interior = valid && I >= 2 && J >= 2 && I <= g.N - 2 && J <= g.N - 2;
+        if (!interior) {
+            const int rr = (nbr > 0 && J == brow[0]) ? 0 : (nbr > 1 && J == brow[1]) ? 1 : -1;
+            const int cc = (nbc > 0 && I == bcol[0]) ? 0 : (nbc > 1 && I == bcol[1]) ? 1 : -1;
+            const int slot = (rr >= 0 && cc >= 0) ? 4 * VP + 2 * rr + cc
+                             : rr >= 0             ? rr * VP + tx
+                                                   : 2 * VP + (cc >= 0 ? cc : 0) * VP + ty;
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s)
+                rv[s] = valid ? sdel[slot * kFSlotStride + s] : T(0);
+        }
+        T* xs = s_buf;  // 20 values per lane: [(b*2 + c)*2 + parity][lane]
+#pragma unroll
+        for (int bq = 0; bq < 5; ++bq)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int o = 25 * c + 5 * bq;
+                const T ev = rv[o + 4] + row_shl<1>(rv[o + 2]) + row_shl<2>(rv[o + 0]);
+                const T od = row_shl<1>(rv[o + 3]) + row_shl<2>(rv[o + 1]);
+                const int base = ((bq * 2 + c) * 2) * VNT;
+                xs[base + tid] = ev;
+                xs[base + VNT + tid] = od;
+            }
+    }
+    __syncthreads();
+    if (wave < 4) {
+        owner_commit(g, s_buf, E0x, E0y, ob, xout);
+        if (valid && tx >= 1 && tx <= VT && ty >= 1 && ty <= VT) {
+            const int64_t q = 2 * g.nq2 + int64_t(J) * g.s1 + I;
+            xout[q] = ob.p + rv[50];
+        }
     }
 }
 
@@ -2124,20 +2451,11 @@ __global__ __launch_bounds__(256) void axpy_multi_kernel(const double* __restric
     }
 }
 
-int boundary_per_wave_override() {
-    static const int v = [] {
-        const char* e = std::getenv("VKMG_BOUNDARY_PER_WAVE");
-        const int x = e ? std::atoi(e) : 0;
-        return (x == 1 || x == 2 || x == 4 || x == 8) ? x : 0;
-    }();
-    return v;
-}
-
-// Boundary patches per wavefront: about one wavefront per SIMD (1024) on
-// the large levels, where the coefficient rows dominate the traffic.
-int boundary_patches_per_wave(int nb) {
-    const int env = boundary_per_wave_override();
-    if (env > 0) return env;
+// Boundary patches per wavefront: `per` (1, 2, 4 or 8) if given, else about
+// one wavefront per SIMD (1024) on the large levels, where the coefficient
+// rows dominate the traffic.
+int boundary_patches_per_wave(int nb, int per) {
+    if (per == 1 || per == 2 || per == 4 || per == 8) return per;
     const int q = nb / 1024;
     return q >= 8 ? 8 : q >= 4 ? 4 : q >= 2 ? 2 : 1;
 }
@@ -2267,9 +2585,9 @@ int64_t vanka_boundary_scratch(int N) { return int64_t(n_boundary_patches(N)) * 
 
 template <typename T>
 void launch_vanka_boundary(const Geom& g, const T* r, const T* table, T* dbuf, hipStream_t s,
-                           int nrhs) {
+                           int nrhs, int per_wave) {
     const int nb = n_boundary_patches(g.N);
-    const int per = boundary_patches_per_wave(nb * nrhs);
+    const int per = boundary_patches_per_wave(nb * nrhs, per_wave);
     const dim3 bgrid((nb + 4 * per - 1) / (4 * per), nrhs);
     if (per == 8)
         vanka_boundary_kernel<T, 8><<<bgrid, 256, 0, s>>>(g, r, table, dbuf);
@@ -2281,19 +2599,20 @@ void launch_vanka_boundary(const Geom& g, const T* r, const T* table, T* dbuf, h
         vanka_boundary_kernel<T, 1><<<bgrid, 256, 0, s>>>(g, r, table, dbuf);
 }
 template void launch_vanka_boundary<double>(const Geom&, const double*, const double*, double*,
-                                            hipStream_t, int);
+                                            hipStream_t, int, int);
 template void launch_vanka_boundary<float>(const Geom&, const float*, const float*, float*,
-                                           hipStream_t, int);
+                                           hipStream_t, int, int);
 
 template <typename T>
 void launch_vanka_tiles(const Geom& g, const T* r, const T* xin, T* xout, const T* mtab,
-                        const T* dbuf, double omega, bool mfma, hipStream_t s, int nrhs) {
+                        const T* dbuf, double omega, bool mfma, hipStream_t s, int nrhs,
+                        bool park) {
     const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
     const dim3 grid(8 * ((ntile + 7) / 8), nrhs);
     if (mfma)
         vanka_mfma_kernel<T><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf, mtab, T(omega / g.nu),
                                                   T(g.nu / g.h));
-    else if (std::is_same<T, double>::value && g.N >= kParkMinN)
+    else if (std::is_same<T, double>::value && park)
         vanka_sweep_kernel<T, false, true><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf,
                                                                 T(omega / g.nu), T(g.nu / g.h));
     else
@@ -2302,24 +2621,42 @@ void launch_vanka_tiles(const Geom& g, const T* r, const T* xin, T* xout, const 
 }
 template void launch_vanka_tiles<double>(const Geom&, const double*, const double*, double*,
                                          const double*, const double*, double, bool, hipStream_t,
-                                         int);
+                                         int, bool);
 template void launch_vanka_tiles<float>(const Geom&, const float*, const float*, float*,
                                         const float*, const float*, double, bool, hipStream_t,
-                                        int);
+                                        int, bool);
+
+template <typename T>
+void launch_vanka_fused(const Geom& g, const T* b, const T* xin, T* xout, const T* table,
+                        double omega, hipStream_t s, int nrhs) {
+    const int ntile = vanka_tiles(g.N) * vanka_tiles(g.N);
+    const dim3 grid(8 * ((ntile + 7) / 8), nrhs);
+    if (xin)
+        vanka_fused_kernel<T, true><<<grid, FNT, 0, s>>>(g, b, xin, xout, table, T(omega / g.nu),
+                                                         T(g.nu / g.h));
+    else
+        vanka_fused_kernel<T, false><<<grid, FNT, 0, s>>>(g, b, xin, xout, table,
+                                                          T(omega / g.nu), T(g.nu / g.h));
+}
+template void launch_vanka_fused<double>(const Geom&, const double*, const double*, double*,
+                                         const double*, double, hipStream_t, int);
+template void launch_vanka_fused<float>(const Geom&, const float*, const float*, float*,
+                                        const float*, double, hipStream_t, int);
+int vanka_fused_min_n() { return kFusedMinN; }
 
 template <typename T>
 void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const T* table,
                          const T* mtab, T* dbuf, double omega, bool mfma, hipStream_t s,
-                         int nrhs) {
-    launch_vanka_boundary<T>(g, r, table, dbuf, s, nrhs);
-    launch_vanka_tiles<T>(g, r, xin, xout, mtab, dbuf, omega, mfma, s, nrhs);
+                         int nrhs, bool park, int per_wave) {
+    launch_vanka_boundary<T>(g, r, table, dbuf, s, nrhs, per_wave);
+    launch_vanka_tiles<T>(g, r, xin, xout, mtab, dbuf, omega, mfma, s, nrhs, park);
 }
 template void launch_vanka_update<double>(const Geom&, const double*, const double*, double*,
                                           const double*, const double*, double*, double, bool,
-                                          hipStream_t, int);
+                                          hipStream_t, int, bool, int);
 template void launch_vanka_update<float>(const Geom&, const float*, const float*, float*,
                                          const float*, const float*, float*, double, bool,
-                                         hipStream_t, int);
+                                         hipStream_t, int, bool, int);
 
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, hipStream_t s, int nb) {
@@ -2385,6 +2722,121 @@ void launch_scale(const double* in, double alpha, double* out, int64_t n, hipStr
 // The Krylov kernels keep up to 32 coefficients in registers; longer
 // bases are processed in chunks of 32 vectors (single right-hand side).
 constexpr int kChunk = 32;
+
+// ---------------------------------------------------------------------------
+// Givens rotations and the stopping test of FGMRES on the device (delayed
+// CGS2 Arnoldi steps): one thread per system of a batch, each owning an area
+// of `stride` doubles (GivensLayout, kernels.h) that holds the reduced dots
+// of pass 1 of the step, the pass-2 coefficients (alpha, gamma, d, sigma),
+// two unrotated Hessenberg columns, the rotated columns R (packed), the
+// rotations and the rotated right-hand sides.  Step j finalises column j-1
+// (H(i,j-1) += s_i / sigma_{j-1}, H(j,j-1) = alpha_j / sigma_{j-1}), redoes its
+// rotation and applies it to gbase, then forms column j (provisional,
+// H(j+1,j) = sqrt(d)), rotates it and applies its rotation to a copy gv of
+// gbase; |gv[j+1]| is the residual estimate.  A system stops at the target,
+// on breakdown (d <= 0), at its iteration limit or on a non-finite value.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int packed_col(int j) { return j * (j + 3) / 2; }
+
+__global__ __launch_bounds__(64) void givens_step_kernel(double* __restrict__ area,
+                                                         int64_t stride, int j, int nsys) {
+    using GL = GivensLayout;
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= nsys) return;
+    double* a = area + int64_t(k) * stride;
+    double* sc = a + GL::kScalars;
+    if (sc[GL::kActive] == 0.0) return;
+    const double* c = a + GL::kDots;
+    const double alpha = a[GL::kCoef + 0], gamma = a[GL::kCoef + 1];
+    const double d = a[GL::kCoef + 2], sigma = a[GL::kCoef + 3];
+    double* cs = a + GL::kCs;
+    double* sn = a + GL::kSn;
+    double* gb = a + GL::kGbase;
+    double* gv = a + GL::kGv;
+    double* Hc = a + GL::kHcols + GL::kHcol * (j & 1);
+    double* Hp = a + GL::kHcols + GL::kHcol * ((j + 1) & 1);
+    auto rotate_column = [&](const double* H, int col) {
+        double* R = a + GL::kR + packed_col(col);
+        for (int i = 0; i <= col + 1; ++i) R[i] = H[i];
+        for (int i = 0; i < col; ++i) {
+            const double t = cs[i] * R[i] + sn[i] * R[i + 1];
+            R[i + 1] = -sn[i] * R[i] + cs[i] * R[i + 1];
+            R[i] = t;
+        }
+        const double denom = hypot(R[col], R[col + 1]);
+        cs[col] = R[col] / denom;
+        sn[col] = R[col + 1] / denom;
+        R[col] = denom;
+        R[col + 1] = 0.0;
+    };
+    if (j == 0) {
+        gb[0] = sc[GL::kBeta];
+        for (int i = 1; i < GL::kMaxRestart + 1; ++i) gb[i] = 0.0;
+    }
+    bool finite = true;
+    const double sigma_prev = sc[GL::kSigmaPrev];
+    if (j > 0) {  // finalise column j-1
+        for (int i = 0; i < j; ++i) Hp[i] += c[j + i] / sigma_prev;
+        Hp[j] = alpha / sigma_prev;
+        for (int i = 0; i <= j; ++i) finite = finite && isfinite(Hp[i]);
+    }
+    for (int i = 0; i < j; ++i) Hc[i] = c[i];
+    Hc[j] = gamma;
+    const double hnext = d > 0.0 ? sqrt(d) : 0.0;
+    sc[GL::kSigmaPrev] = sigma;
+    for (int i = 0; i <= j; ++i) finite = finite && isfinite(Hc[i]);
+    Hc[j + 1] = hnext;
+    sc[GL::kIters] += 1.0;
+    if (!finite || !isfinite(hnext)) {
+        sc[GL::kActive] = 0.0;
+        sc[GL::kStatus] = 1.0;  // non-finite
+        sc[GL::kEst] = __builtin_nan("");
+        return;
+    }
+    if (j > 0) {
+        rotate_column(Hp, j - 1);
+        gb[j] = -sn[j - 1] * gb[j - 1];
+        gb[j - 1] = cs[j - 1] * gb[j - 1];
+    }
+    rotate_column(Hc, j);
+    for (int i = 0; i <= j + 1; ++i) gv[i] = gb[i];
+    gv[j + 1] = -sn[j] * gv[j];
+    gv[j] = cs[j] * gv[j];
+    sc[GL::kKdone] = double(j + 1);
+    const double res = fabs(gv[j + 1]);
+    sc[GL::kEst] = res / sc[GL::kBeta0];
+    if (res <= sc[GL::kTarget] || hnext == 0.0 || sc[GL::kIters] >= sc[GL::kMaxIters])
+        sc[GL::kActive] = 0.0;
+}
+
+// y = R^{-1} gv for the k = kdone columns of each system that ran in this
+// cycle (cycled != 0), zeros up to kmax (the columns x += Z y reads).
+__global__ __launch_bounds__(64) void givens_solve_kernel(double* __restrict__ area,
+                                                          int64_t stride, int kmax, int nsys) {
+    using GL = GivensLayout;
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= nsys) return;
+    double* a = area + int64_t(k) * stride;
+    const double* sc = a + GL::kScalars;
+    const int kk = sc[GL::kCycled] != 0.0 ? int(sc[GL::kKdone]) : 0;
+    const double* gv = a + GL::kGv;
+    double* y = a + GL::kY;
+    for (int i = kk; i < kmax; ++i) y[i] = 0.0;
+    for (int i = kk - 1; i >= 0; --i) {
+        double acc = gv[i];
+        for (int l = i + 1; l < kk; ++l) acc -= a[GL::kR + packed_col(l) + i] * y[l];
+        y[i] = acc / a[GL::kR + packed_col(i) + i];
+    }
+}
+
+void launch_givens_step(double* area, int64_t stride, int j, int nsys, hipStream_t s) {
+    givens_step_kernel<<<(nsys + 63) / 64, 64, 0, s>>>(area, stride, j, nsys);
+}
+
+void launch_givens_solve(double* area, int64_t stride, int kmax, int nsys, hipStream_t s) {
+    givens_solve_kernel<<<(nsys + 63) / 64, 64, 0, s>>>(area, stride, kmax, nsys);
+}
 
 // Every batch entry is reduced over the same kDotBlocks partial sums as a
 // single right-hand side, so batched dot products (and with them the whole

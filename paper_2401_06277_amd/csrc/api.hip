@@ -99,6 +99,8 @@ struct vkmg_ctx {
     double* part = nullptr;   // dot partials
     double* hdev = nullptr;   // coefficients (device)
     double* hhost = nullptr;  // pinned host mirror
+    double* gstat = nullptr;  // FGMRES: per-system summaries (8 each), then cycle init values
+    double* hstat = nullptr;  // pinned: two step summaries and the init values (8 per system each)
     hipEvent_t step_done[2] = {nullptr, nullptr};  // coefficient copies of Arnoldi steps
     // FGMRES basis
     double* V = nullptr;
@@ -176,6 +178,8 @@ void free_all(vkmg_ctx* c) {
     c->allocations.clear();
     if (c->hhost) (void)hipHostFree(c->hhost);
     c->hhost = nullptr;
+    if (c->hstat) (void)hipHostFree(c->hstat);
+    c->hstat = nullptr;
     for (auto& e : c->step_done) {
         if (e) (void)hipEventDestroy(e);
         e = nullptr;
@@ -255,6 +259,20 @@ void sweep_t(vkmg_ctx* c, int l, const T* b, T* x, bool x_zero, hipStream_t s,
                           parked<T>(c, L.g.N));
 }
 
+// b_{l-1} = P^T (b - A_l x): the residual, then the restriction.
+template <typename T>
+void restrict_residual_t(vkmg_ctx* c, int l, const T* b, const T* x, T* bc, hipStream_t s) {
+    LevelBuf& L = c->lev[l];
+    LevelBuf& Lc = c->lev[l - 1];
+    T* r = static_cast<T*>(L.r);
+    {
+        Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
+        launch_residual<T, T>(L.g, b, x, r, 0, s, c->nb(), c->nu_of<T>(l));
+    }
+    Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
+    launch_restrict<T>(L.g, Lc.g, r, bc, s, c->nb());
+}
+
 // Whether the V-cycle sweeps of level l run as single fused launches.
 bool fused_sweeps(const vkmg_ctx* c, int l) {
     const int N = c->lev[l].g.N;
@@ -285,17 +303,9 @@ void mg_fused_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
         launch_vanka_fused<T>(L.g, b, cur, out(k), W, c->opt.omega, s, c->nb());
         cur = out(k);
     }
-    T* r = static_cast<T*>(L.r);
-    {
-        Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
-        launch_residual<T, T>(L.g, b, cur, r, 0, s, c->nb(), c->nu_of<T>(l));
-    }
     T* bc = static_cast<T*>(Lc.b);
     T* xc = static_cast<T*>(Lc.x);
-    {
-        Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
-        launch_restrict<T>(L.g, Lc.g, r, bc, s, c->nb());
-    }
+    restrict_residual_t<T>(c, l, b, cur, bc, s);
     if (l - 1 == 0) {
         Timed t(c, VKMG_KERNEL_COARSE, s, 0);
         launch_coarse_gemv<T>(Lc.g.n, c->C, bc, xc, s, c->nb());
@@ -322,25 +332,19 @@ void mg_t(vkmg_ctx* c, int l, const T* b, T* x, hipStream_t s) {
     }
     LevelBuf& L = c->lev[l];
     LevelBuf& Lc = c->lev[l - 1];
-    T* r = static_cast<T*>(L.r);
     bool x_zero = true;
     for (int i = 0; i < c->opt.nu_pre; ++i) {
         sweep_t<T>(c, l, b, x, x_zero, s);
         x_zero = false;
     }
-    const T* rr = b;
-    if (x_zero) {
-        launch_fill_zero<T>(x, L.g.n * c->nb(), s);
-    } else {
-        Timed t(c, VKMG_KERNEL_RESIDUAL, s, l);
-        launch_residual<T, T>(L.g, b, x, r, 0, s, c->nb(), c->nu_of<T>(l));
-        rr = r;
-    }
     T* bc = static_cast<T*>(Lc.b);
     T* xc = static_cast<T*>(Lc.x);
-    {
+    if (x_zero) {
+        launch_fill_zero<T>(x, L.g.n * c->nb(), s);
         Timed t(c, VKMG_KERNEL_TRANSFER, s, l);
-        launch_restrict<T>(L.g, Lc.g, rr, bc, s, c->nb());
+        launch_restrict<T>(L.g, Lc.g, b, bc, s, c->nb());
+    } else {
+        restrict_residual_t<T>(c, l, b, x, bc, s);
     }
     if (l - 1 == 0) {
         Timed t(c, VKMG_KERNEL_COARSE, s, 0);
@@ -498,7 +502,13 @@ vkmg_status fgmres_delayed(vkmg_ctx* ctx, const double* b, double* x, double rto
     double* Z = ctx->Z;
     double* hd = ctx->hdev;
     double* hh = ctx->hhost;
-    constexpr int kStatus = 1950;  // pinned host: per-step flags, two buffers of 2 doubles
+    // compact per-system summaries (8 doubles each): the device's in gstat,
+    // the host copies of two consecutive steps in hstat[0..16B), the cycle
+    // init values staged in hstat[16B..24B) and copied to gstat[8B..16B)
+    double* const gsum = ctx->gstat;
+    double* const ginit = ctx->gstat + 8 * B;
+    double* const hsum[2] = {ctx->hstat, ctx->hstat + 8 * B};
+    double* const hinit = ctx->hstat + 16 * B;
 
     auto norms = [&](const double* v, std::vector<double>& out) -> vkmg_status {
         {
@@ -561,8 +571,7 @@ vkmg_status fgmres_delayed(vkmg_ctx* ctx, const double* b, double* x, double rto
         launch_reduce_partials(ctx->part, 2 * j + 3, hd + GL::kDots, ss, B, HS);
         launch_dcgs_update(V, S, j, hd + GL::kDots, vj, w, V + int64_t(j + 1) * S, n,
                            hd + GL::kCoef, ss, B, n, HS,
-                           fp32_mg ? static_cast<float*>(ctx->lev.back().b) : nullptr);
-        launch_givens_step(hd, HS, j, B, ss);
+                           fp32_mg ? static_cast<float*>(ctx->lev.back().b) : nullptr, hd, gsum);
     };
     const bool use_graphs = ctx->opt.use_graphs != 0 && ctx->timing_mask == 0;
     if (use_graphs && ctx->graphs_scheme != 3) {
@@ -579,8 +588,8 @@ vkmg_status fgmres_delayed(vkmg_ctx* ctx, const double* b, double* x, double rto
         } else {
             step(j, s);
         }
-        VKMG_HIP(hipMemcpy2DAsync(hh + kStatus + 2 * (j & 1), HS * 8, hd + GL::kScalars + GL::kEst,
-                                  HS * 8, 2 * sizeof(double), B, hipMemcpyDeviceToHost, s));
+        VKMG_HIP(hipMemcpyAsync(hsum[j & 1], gsum, sizeof(double) * 8 * B, hipMemcpyDeviceToHost,
+                                s));
         VKMG_HIP(hipEventRecord(ctx->step_done[j & 1], s));
         return VKMG_OK;
     };
@@ -591,28 +600,22 @@ vkmg_status fgmres_delayed(vkmg_ctx* ctx, const double* b, double* x, double rto
             q.active = !q.done;
             q.est_last = 1.0;
             q.est_prev = 0.0;
-            double* sc = hh + k * HS + GL::kScalars;
-            sc[GL::kBeta0] = q.beta0;
-            sc[GL::kTarget] = q.target;
-            sc[GL::kBeta] = q.beta;
-            sc[GL::kSigmaPrev] = 0.0;
-            sc[GL::kEst] = q.est;
-            sc[GL::kActive] = q.active ? 1.0 : 0.0;
-            sc[GL::kIters] = double(q.iters);
-            sc[GL::kKdone] = 0.0;
-            sc[GL::kStatus] = 0.0;
-            sc[GL::kMaxIters] = double(max_iters);
-            sc[GL::kCycled] = q.active ? 1.0 : 0.0;
-            hh[k * HS + GL::kScale] = q.active ? 1.0 / q.beta : 0.0;
+            double* in = hinit + 8 * k;
+            in[0] = q.beta0;
+            in[1] = q.target;
+            in[2] = q.beta;
+            in[3] = q.est;
+            in[4] = q.active ? 1.0 : 0.0;
+            in[5] = double(q.iters);
+            in[6] = double(max_iters);
+            in[7] = q.active ? 1.0 / q.beta : 0.0;
             nactive += q.active;
         }
         if (nactive == 0) break;
-        VKMG_HIP(hipMemcpy2DAsync(hd + GL::kScalars, HS * 8, hh + GL::kScalars, HS * 8,
-                                  (GL::kCycled + 1) * sizeof(double), B, hipMemcpyHostToDevice, s));
-        VKMG_HIP(hipMemcpy2DAsync(hd + GL::kScale, HS * 8, hh + GL::kScale, HS * 8, 8, B,
-                                  hipMemcpyHostToDevice, s));
+        VKMG_HIP(hipMemcpyAsync(ginit, hinit, sizeof(double) * 8 * B, hipMemcpyHostToDevice, s));
         {
             Timed t(ctx, VKMG_KERNEL_KRYLOV, s);
+            launch_givens_init(hd, HS, ginit, gsum, B, s);
             launch_scale_batched(r, n, hd + GL::kScale, HS, V, n, n, B, s);
         }
         int steps = 0;
@@ -642,7 +645,7 @@ vkmg_status fgmres_delayed(vkmg_ctx* ctx, const double* b, double* x, double rto
             for (int k = 0; k < B; ++k) {
                 Sys& q = sys[k];
                 if (!q.active) continue;
-                const double* f = hh + k * HS + kStatus + 2 * (j & 1);
+                const double* f = hsum[j & 1] + 8 * k;
                 ++q.iters;
                 q.est_prev = q.est_last;
                 q.est_last = f[0];
@@ -661,25 +664,20 @@ vkmg_status fgmres_delayed(vkmg_ctx* ctx, const double* b, double* x, double rto
             launch_axpy_multi(Z, S, steps, hd + GL::kY, x, n, s, B, n, HS);
         }
         // state of each system at the end of the cycle
-        VKMG_HIP(hipMemcpy2DAsync(hh + GL::kScalars, HS * 8, hd + GL::kScalars, HS * 8,
-                                  (GL::kCycled + 1) * sizeof(double), B, hipMemcpyDeviceToHost, s));
-        VKMG_HIP(hipMemcpy2DAsync(hh + GL::kGv, HS * 8, hd + GL::kGv, HS * 8,
-                                  (GL::kMaxRestart + 1) * sizeof(double), B,
-                                  hipMemcpyDeviceToHost, s));
+        VKMG_HIP(hipMemcpyAsync(hsum[0], gsum, sizeof(double) * 8 * B, hipMemcpyDeviceToHost, s));
         residual();
         st = norms(r, nrm);  // synchronises the stream
         if (st != VKMG_OK) return st;
         bool all_done = true;
         for (int k = 0; k < B; ++k) {
             Sys& q = sys[k];
-            const double* sc = hh + k * HS + GL::kScalars;
-            if (sc[GL::kCycled] != 0.0) {
-                q.iters = int(sc[GL::kIters]);
-                q.est = sc[GL::kEst];
-                const int kd = int(sc[GL::kKdone]);
+            const double* f = hsum[0] + 8 * k;  // estimate, active, iters, kdone, status, |g_kdone|, cycled
+            if (f[6] != 0.0) {
+                q.iters = int(f[2]);
+                q.est = f[0];
                 const double rn = nrm[k];
                 q.true_rel = rn / q.beta0;
-                if (sc[GL::kStatus] != 0.0 || !std::isfinite(rn)) {
+                if (f[4] != 0.0 || !std::isfinite(rn)) {
                     q.done = true;
                     q.status = VKMG_ERR_NONFINITE;
                     q.est = q.true_rel = NAN;
@@ -689,7 +687,7 @@ vkmg_status fgmres_delayed(vkmg_ctx* ctx, const double* b, double* x, double rto
                 } else if (q.iters >= max_iters) {
                     q.done = true;
                     q.status = VKMG_ERR_NOT_CONVERGED;
-                } else if (std::fabs(hh[k * HS + GL::kGv + kd]) <= q.target && rn > 0.5 * q.beta) {
+                } else if (f[5] <= q.target && rn > 0.5 * q.beta) {
                     // estimate met, true residual did not and did not halve:
                     // below the rounding floor of the system
                     q.done = true;
@@ -1136,6 +1134,11 @@ static vkmg_status setup_impl(const vkmg_grid* grid, int32_t levels, double nu,
     if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->hdev), 8 * kHostScratch * nbt);
     if (st == VKMG_OK) {
         hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->hhost), 8 * kHostScratch * nbt, hipHostMallocDefault);
+        if (e != hipSuccess) st = fail(VKMG_ERR_OUT_OF_MEMORY, "setup: pinned host buffer");
+    }
+    if (st == VKMG_OK) st = alloc(c.get(), reinterpret_cast<void**>(&c->gstat), 8 * 16 * nbt);
+    if (st == VKMG_OK) {
+        hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->hstat), 8 * 24 * nbt, hipHostMallocDefault);
         if (e != hipSuccess) st = fail(VKMG_ERR_OUT_OF_MEMORY, "setup: pinned host buffer");
     }
     if (st == VKMG_OK) {

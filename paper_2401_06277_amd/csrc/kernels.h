@@ -156,9 +156,14 @@ struct GivensLayout {
 };
 static_assert(GivensLayout::kR + 32 * 35 / 2 <= GivensLayout::kScalars, "packed R fits");
 
-// One Givens step of the delayed-scheme FGMRES for nsys systems (areas
-// `stride` apart), after the Gram-Schmidt kernels of Arnoldi step j.
-void launch_givens_step(double* area, int64_t stride, int j, int nsys, hipStream_t s);
+// Start of a restart cycle for nsys systems (areas `stride` apart): init
+// holds 8 values per system (beta0, target, beta, estimate, active flag,
+// iterations so far, iteration limit, 1/beta); the Givens state is reset
+// and stat (8 values per system: estimate, active, iterations, kdone,
+// status, |g_kdone|, cycled) initialised.  The Givens steps themselves run
+// inside launch_dcgs_update.
+void launch_givens_init(double* area, int64_t stride, const double* init, double* stat, int nsys,
+                        hipStream_t s);
 // y of every system from its rotated system (zeros from kdone to kmax).
 void launch_givens_solve(double* area, int64_t stride, int kmax, int nsys, hipStream_t s);
 
@@ -194,9 +199,13 @@ void launch_dcgs_dots(const double* V, int64_t ldv, int j, const double* u, cons
 // next <- normalised successor; cf = (alpha, gamma, d, 1/sqrt(d)); c and cf
 // of batch entry b at offset b * sc.  next32: if given, also next rounded
 // to FP32 (the input of an FP32 V-cycle), vectors sb apart.
+// With garea (GivensLayout areas sc apart, cf inside them), block 0 of
+// every batch entry also runs the entry's Givens step (summary to
+// gstat[8 * entry ...], see launch_givens_init).
 void launch_dcgs_update(const double* V, int64_t ldv, int j, const double* c, double* u,
                         const double* w, double* next, int64_t n, double* cf, hipStream_t s,
-                        int nb = 1, int64_t sb = 0, int64_t sc = 0, float* next32 = nullptr);
+                        int nb = 1, int64_t sb = 0, int64_t sc = 0, float* next32 = nullptr,
+                        double* garea = nullptr, double* gstat = nullptr);
 // x += sum_v y[v] Z_v; y of batch entry b at offset b * sy
 void launch_axpy_multi(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t n,
                        hipStream_t s, int nb = 1, int64_t sb = 0, int64_t sy = 0);

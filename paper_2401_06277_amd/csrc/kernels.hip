@@ -2279,6 +2279,154 @@ __global__ __launch_bounds__(256) void normalize_kernel(const double* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Givens rotations and the stopping test of FGMRES on the device (delayed
+// CGS2 Arnoldi steps): one thread per system of a batch, each owning an area
+// of `stride` doubles (GivensLayout, kernels.h) that holds the reduced dots
+// of pass 1 of the step, the pass-2 coefficients (alpha, gamma, d, sigma),
+// two unrotated Hessenberg columns, the rotated columns R (packed), the
+// rotations and the rotated right-hand sides.  Step j finalises column j-1
+// (H(i,j-1) += s_i / sigma_{j-1}, H(j,j-1) = alpha_j / sigma_{j-1}), redoes its
+// rotation and applies it to gbase, then forms column j (provisional,
+// H(j+1,j) = sqrt(d)), rotates it and applies its rotation to a copy gv of
+// gbase; |gv[j+1]| is the residual estimate.  A system stops at the target,
+// on breakdown (d <= 0), at its iteration limit or on a non-finite value.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int packed_col(int j) { return j * (j + 3) / 2; }
+
+// One Givens step of one system (area `a`, GivensLayout), after the
+// Gram-Schmidt passes of Arnoldi step j; its summary goes to stat[0..5]
+// (estimate, active flag, iterations, kdone, status, |g_kdone|).
+__device__ __attribute__((noinline)) void givens_step(double* __restrict__ a, int j,
+                                                     double* __restrict__ stat) {
+    using GL = GivensLayout;
+    double* sc = a + GL::kScalars;
+    if (sc[GL::kActive] == 0.0) return;
+    const double* c = a + GL::kDots;
+    const double alpha = a[GL::kCoef + 0], gamma = a[GL::kCoef + 1];
+    const double d = a[GL::kCoef + 2], sigma = a[GL::kCoef + 3];
+    double* cs = a + GL::kCs;
+    double* sn = a + GL::kSn;
+    double* gb = a + GL::kGbase;
+    double* gv = a + GL::kGv;
+    double* Hc = a + GL::kHcols + GL::kHcol * (j & 1);
+    double* Hp = a + GL::kHcols + GL::kHcol * ((j + 1) & 1);
+    auto rotate_column = [&](const double* H, int col) {
+        double* R = a + GL::kR + packed_col(col);
+        for (int i = 0; i <= col + 1; ++i) R[i] = H[i];
+        for (int i = 0; i < col; ++i) {
+            const double t = cs[i] * R[i] + sn[i] * R[i + 1];
+            R[i + 1] = -sn[i] * R[i] + cs[i] * R[i + 1];
+            R[i] = t;
+        }
+        const double denom = hypot(R[col], R[col + 1]);
+        cs[col] = R[col] / denom;
+        sn[col] = R[col + 1] / denom;
+        R[col] = denom;
+        R[col + 1] = 0.0;
+    };
+    if (j == 0) {
+        gb[0] = sc[GL::kBeta];
+        for (int i = 1; i < GL::kMaxRestart + 1; ++i) gb[i] = 0.0;
+    }
+    bool finite = true;
+    const double sigma_prev = sc[GL::kSigmaPrev];
+    if (j > 0) {  // finalise column j-1
+        for (int i = 0; i < j; ++i) Hp[i] += c[j + i] / sigma_prev;
+        Hp[j] = alpha / sigma_prev;
+        for (int i = 0; i <= j; ++i) finite = finite && isfinite(Hp[i]);
+    }
+    for (int i = 0; i < j; ++i) Hc[i] = c[i];
+    Hc[j] = gamma;
+    const double hnext = d > 0.0 ? sqrt(d) : 0.0;
+    sc[GL::kSigmaPrev] = sigma;
+    for (int i = 0; i <= j; ++i) finite = finite && isfinite(Hc[i]);
+    Hc[j + 1] = hnext;
+    sc[GL::kIters] += 1.0;
+    if (!finite || !isfinite(hnext)) {
+        sc[GL::kActive] = 0.0;
+        sc[GL::kStatus] = 1.0;  // non-finite
+        sc[GL::kEst] = __builtin_nan("");
+    } else {
+        if (j > 0) {
+            rotate_column(Hp, j - 1);
+            gb[j] = -sn[j - 1] * gb[j - 1];
+            gb[j - 1] = cs[j - 1] * gb[j - 1];
+        }
+        rotate_column(Hc, j);
+        for (int i = 0; i <= j + 1; ++i) gv[i] = gb[i];
+        gv[j + 1] = -sn[j] * gv[j];
+        gv[j] = cs[j] * gv[j];
+        sc[GL::kKdone] = double(j + 1);
+        const double res = fabs(gv[j + 1]);
+        sc[GL::kEst] = res / sc[GL::kBeta0];
+        if (res <= sc[GL::kTarget] || hnext == 0.0 || sc[GL::kIters] >= sc[GL::kMaxIters])
+            sc[GL::kActive] = 0.0;
+    }
+    stat[0] = sc[GL::kEst];
+    stat[1] = sc[GL::kActive];
+    stat[2] = sc[GL::kIters];
+    stat[3] = sc[GL::kKdone];
+    stat[4] = sc[GL::kStatus];
+    stat[5] = fabs(gv[int(sc[GL::kKdone])]);
+}
+
+// Start of a restart cycle: the per-system values the host staged in
+// init[8k..8k+7] (beta0, target, beta, estimate, active, iterations,
+// iteration limit, 1/beta) into each area, with the Givens state reset.
+__global__ __launch_bounds__(64) void givens_init_kernel(double* __restrict__ area, int64_t stride,
+                                                         const double* __restrict__ init,
+                                                         double* __restrict__ stat, int nsys) {
+    using GL = GivensLayout;
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= nsys) return;
+    double* a = area + int64_t(k) * stride;
+    double* sc = a + GL::kScalars;
+    const double* in = init + 8 * k;
+    sc[GL::kBeta0] = in[0];
+    sc[GL::kTarget] = in[1];
+    sc[GL::kBeta] = in[2];
+    sc[GL::kEst] = in[3];
+    sc[GL::kActive] = in[4];
+    sc[GL::kIters] = in[5];
+    sc[GL::kMaxIters] = in[6];
+    a[GL::kScale] = in[7];
+    sc[GL::kSigmaPrev] = 0.0;
+    sc[GL::kKdone] = 0.0;
+    sc[GL::kStatus] = 0.0;
+    sc[GL::kCycled] = in[4];
+    a[GL::kGv] = 0.0;
+    double* st = stat + 8 * k;
+    st[0] = in[3];
+    st[1] = in[4];
+    st[2] = in[5];
+    st[3] = 0.0;
+    st[4] = 0.0;
+    st[5] = 0.0;
+    st[6] = in[4];
+}
+
+// y = R^{-1} gv for the k = kdone columns of each system that ran in this
+// cycle (cycled != 0), zeros up to kmax (the columns x += Z y reads).
+__global__ __launch_bounds__(64) void givens_solve_kernel(double* __restrict__ area,
+                                                          int64_t stride, int kmax, int nsys) {
+    using GL = GivensLayout;
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= nsys) return;
+    double* a = area + int64_t(k) * stride;
+    const double* sc = a + GL::kScalars;
+    const int kk = sc[GL::kCycled] != 0.0 ? int(sc[GL::kKdone]) : 0;
+    const double* gv = a + GL::kGv;
+    double* y = a + GL::kY;
+    for (int i = kk; i < kmax; ++i) y[i] = 0.0;
+    for (int i = kk - 1; i >= 0; --i) {
+        double acc = gv[i];
+        for (int l = i + 1; l < kk; ++l) acc -= a[GL::kR + packed_col(l) + i] * y[l];
+        y[i] = acc / a[GL::kR + packed_col(i) + i];
+    }
+}
+
 // Delayed classical Gram-Schmidt with reorthogonalisation (the DCGS2 of
 // Bielich, Langou, Thomas, Swirydowicz, Yamazaki and Boman): the second
 // pass for basis vector j shares its sweep with the first pass for
@@ -2358,7 +2506,9 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(const double* __restri
                                                           double* uv, const double* __restrict__ w,
                                                           double* __restrict__ next, int64_t n,
                                                           double* __restrict__ cf, int64_t sb,
-                                                          int64_t sc, float* __restrict__ next32) {
+                                                          int64_t sc, float* __restrict__ next32,
+                                                          double* __restrict__ garea,
+                                                          double* __restrict__ gstat) {
     {  // batch entry blockIdx.y: vectors sb apart, coefficients sc apart
         const int64_t bo = int64_t(blockIdx.y) * sb;
         V += bo;
@@ -2391,6 +2541,8 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(const double* __restri
         cf[1] = gamma;
         cf[2] = d;
         cf[3] = sigma;
+        // the Givens step of this system (area and summary sc apart per entry)
+        if (garea) givens_step(garea + int64_t(blockIdx.y) * sc, j, gstat + 8 * blockIdx.y);
     }
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * 256) {
@@ -2723,115 +2875,9 @@ void launch_scale(const double* in, double alpha, double* out, int64_t n, hipStr
 // bases are processed in chunks of 32 vectors (single right-hand side).
 constexpr int kChunk = 32;
 
-// ---------------------------------------------------------------------------
-// Givens rotations and the stopping test of FGMRES on the device (delayed
-// CGS2 Arnoldi steps): one thread per system of a batch, each owning an area
-// of `stride` doubles (GivensLayout, kernels.h) that holds the reduced dots
-// of pass 1 of the step, the pass-2 coefficients (alpha, gamma, d, sigma),
-// two unrotated Hessenberg columns, the rotated columns R (packed), the
-// rotations and the rotated right-hand sides.  Step j finalises column j-1
-// (H(i,j-1) += s_i / sigma_{j-1}, H(j,j-1) = alpha_j / sigma_{j-1}), redoes its
-// rotation and applies it to gbase, then forms column j (provisional,
-// H(j+1,j) = sqrt(d)), rotates it and applies its rotation to a copy gv of
-// gbase; |gv[j+1]| is the residual estimate.  A system stops at the target,
-// on breakdown (d <= 0), at its iteration limit or on a non-finite value.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ int packed_col(int j) { return j * (j + 3) / 2; }
-
-__global__ __launch_bounds__(64) void givens_step_kernel(double* __restrict__ area,
-                                                         int64_t stride, int j, int nsys) {
-    using GL = GivensLayout;
-    const int k = blockIdx.x * 64 + threadIdx.x;
-    if (k >= nsys) return;
-    double* a = area + int64_t(k) * stride;
-    double* sc = a + GL::kScalars;
-    if (sc[GL::kActive] == 0.0) return;
-    const double* c = a + GL::kDots;
-    const double alpha = a[GL::kCoef + 0], gamma = a[GL::kCoef + 1];
-    const double d = a[GL::kCoef + 2], sigma = a[GL::kCoef + 3];
-    double* cs = a + GL::kCs;
-    double* sn = a + GL::kSn;
-    double* gb = a + GL::kGbase;
-    double* gv = a + GL::kGv;
-    double* Hc = a + GL::kHcols + GL::kHcol * (j & 1);
-    double* Hp = a + GL::kHcols + GL::kHcol * ((j + 1) & 1);
-    auto rotate_column = [&](const double* H, int col) {
-        double* R = a + GL::kR + packed_col(col);
-        for (int i = 0; i <= col + 1; ++i) R[i] = H[i];
-        for (int i = 0; i < col; ++i) {
-            const double t = cs[i] * R[i] + sn[i] * R[i + 1];
-            R[i + 1] = -sn[i] * R[i] + cs[i] * R[i + 1];
-            R[i] = t;
-        }
-        const double denom = hypot(R[col], R[col + 1]);
-        cs[col] = R[col] / denom;
-        sn[col] = R[col + 1] / denom;
-        R[col] = denom;
-        R[col + 1] = 0.0;
-    };
-    if (j == 0) {
-        gb[0] = sc[GL::kBeta];
-        for (int i = 1; i < GL::kMaxRestart + 1; ++i) gb[i] = 0.0;
-    }
-    bool finite = true;
-    const double sigma_prev = sc[GL::kSigmaPrev];
-    if (j > 0) {  // finalise column j-1
-        for (int i = 0; i < j; ++i) Hp[i] += c[j + i] / sigma_prev;
-        Hp[j] = alpha / sigma_prev;
-        for (int i = 0; i <= j; ++i) finite = finite && isfinite(Hp[i]);
-    }
-    for (int i = 0; i < j; ++i) Hc[i] = c[i];
-    Hc[j] = gamma;
-    const double hnext = d > 0.0 ? sqrt(d) : 0.0;
-    sc[GL::kSigmaPrev] = sigma;
-    for (int i = 0; i <= j; ++i) finite = finite && isfinite(Hc[i]);
-    Hc[j + 1] = hnext;
-    sc[GL::kIters] += 1.0;
-    if (!finite || !isfinite(hnext)) {
-        sc[GL::kActive] = 0.0;
-        sc[GL::kStatus] = 1.0;  // non-finite
-        sc[GL::kEst] = __builtin_nan("");
-        return;
-    }
-    if (j > 0) {
-        rotate_column(Hp, j - 1);
-        gb[j] = -sn[j - 1] * gb[j - 1];
-        gb[j - 1] = cs[j - 1] * gb[j - 1];
-    }
-    rotate_column(Hc, j);
-    for (int i = 0; i <= j + 1; ++i) gv[i] = gb[i];
-    gv[j + 1] = -sn[j] * gv[j];
-    gv[j] = cs[j] * gv[j];
-    sc[GL::kKdone] = double(j + 1);
-    const double res = fabs(gv[j + 1]);
-    sc[GL::kEst] = res / sc[GL::kBeta0];
-    if (res <= sc[GL::kTarget] || hnext == 0.0 || sc[GL::kIters] >= sc[GL::kMaxIters])
-        sc[GL::kActive] = 0.0;
-}
-
-// y = R^{-1} gv for the k = kdone columns of each system that ran in this
-// cycle (cycled != 0), zeros up to kmax (the columns x += Z y reads).
-__global__ __launch_bounds__(64) void givens_solve_kernel(double* __restrict__ area,
-                                                          int64_t stride, int kmax, int nsys) {
-    using GL = GivensLayout;
-    const int k = blockIdx.x * 64 + threadIdx.x;
-    if (k >= nsys) return;
-    double* a = area + int64_t(k) * stride;
-    const double* sc = a + GL::kScalars;
-    const int kk = sc[GL::kCycled] != 0.0 ? int(sc[GL::kKdone]) : 0;
-    const double* gv = a + GL::kGv;
-    double* y = a + GL::kY;
-    for (int i = kk; i < kmax; ++i) y[i] = 0.0;
-    for (int i = kk - 1; i >= 0; --i) {
-        double acc = gv[i];
-        for (int l = i + 1; l < kk; ++l) acc -= a[GL::kR + packed_col(l) + i] * y[l];
-        y[i] = acc / a[GL::kR + packed_col(i) + i];
-    }
-}
-
-void launch_givens_step(double* area, int64_t stride, int j, int nsys, hipStream_t s) {
-    givens_step_kernel<<<(nsys + 63) / 64, 64, 0, s>>>(area, stride, j, nsys);
+void launch_givens_init(double* area, int64_t stride, const double* init, double* stat, int nsys,
+                        hipStream_t s) {
+    givens_init_kernel<<<(nsys + 63) / 64, 64, 0, s>>>(area, stride, init, stat, nsys);
 }
 
 void launch_givens_solve(double* area, int64_t stride, int kmax, int nsys, hipStream_t s) {
@@ -2894,9 +2940,11 @@ void launch_dcgs_dots(const double* V, int64_t ldv, int j, const double* u, cons
 
 void launch_dcgs_update(const double* V, int64_t ldv, int j, const double* c, double* u,
                         const double* w, double* next, int64_t n, double* cf, hipStream_t s,
-                        int nb, int64_t sb, int64_t sc, float* next32) {
+                        int nb, int64_t sb, int64_t sc, float* next32, double* garea,
+                        double* gstat) {
     const dim3 kgrid(dot_blocks(nb), nb);
-    VKMG_KDISPATCH(j, dcgs_update_kernel, V, ldv, j, c, u, w, next, n, cf, sb, sc, next32);
+    VKMG_KDISPATCH(j, dcgs_update_kernel, V, ldv, j, c, u, w, next, n, cf, sb, sc, next32, garea,
+                   gstat);
 }
 
 void launch_axpy_multi(const double* Z, int64_t ldz, int k, const double* y, double* x, int64_t n,

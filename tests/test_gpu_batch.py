@@ -231,13 +231,11 @@ def test_batched_fp32_multigrid_matches_single(N, levels):
     system is rounded into the top level by the Gram-Schmidt kernel and the
     output widened by the operator apply, both at a per-system offset; a
     stale or misplaced FP32 input would still converge (FGMRES is flexible),
-    only in more steps.  So each system is also solved alone with FP32
-    multigrid: iteration counts equal within one, both within one of the
-    FP64 oracle's count plus one, and at an equal fixed step count the
-    iterates agree to 1e-7 per field (the V-cycles of the batch are bitwise
-    the single ones; only the FP64 Gram-Schmidt sums are reduced in another
-    order, and a last-bit change of a V-cycle input flips FP32 roundings of
-    ~1e-7 relative in its output)."""
+    only in more steps.  Each system is also solved alone: a batch entry
+    does the arithmetic of a single solve (the same V-cycle kernels, dot
+    products over the same partial sums, the same device Givens step), so
+    iteration counts and solutions must be equal bit for bit, and the count
+    within one of the FP64 oracle's plus one."""
     A, systems = _systems(N)
     B = len(systems)
     H = multigrid.Hierarchy(N, levels)
@@ -247,7 +245,6 @@ def test_batched_fp32_multigrid_matches_single(N, levels):
     x = dev(np.concatenate([xl for _, xl in systems]))
     infos = sb.fgmres_solve(bb, x, rtol=1e-8, restart=30, max_iters=500)
     xs = host(x).reshape(B, -1)
-    counts = []
     for k, (b, xl) in enumerate(systems):
         assert infos[k]["status_name"] == "VKMG_OK"
         assert np.linalg.norm(b - A @ xs[k]) <= 1.01e-8 * np.linalg.norm(b - A @ xl)
@@ -256,20 +253,9 @@ def test_batched_fp32_multigrid_matches_single(N, levels):
         ro = fgmres.fgmres(A, b, xl, H.vcycle, rtol=1e-8, restart=30, max_iters=500)
         note(f"fp32-MG batched {infos[k]['iterations']} single {i1['iterations']} "
              f"oracle(fp64) {ro.iterations}")
-        assert abs(infos[k]["iterations"] - i1["iterations"]) <= 1, (k, infos[k], i1)
+        assert infos[k]["iterations"] == i1["iterations"], (k, infos[k], i1)
         assert infos[k]["iterations"] <= ro.iterations + 1, (k, infos[k], ro.iterations)
-        counts.append(min(infos[k]["iterations"], i1["iterations"]))
-    kmin = min(counts)
-    x = dev(np.concatenate([xl for _, xl in systems]))
-    infos = sb.fgmres_solve(bb, x, rtol=0.0, restart=30, max_iters=kmin)
-    xs = host(x).reshape(B, -1)
-    for k, (b, xl) in enumerate(systems):
-        x1 = dev(xl)
-        s1.fgmres_solve(dev(b), x1, rtol=0.0, restart=30, max_iters=kmin)
-        err = rel2(fem.normalise_pressure(N, xs[k]), fem.normalise_pressure(N, host(x1)))
-        note(f"fp32-MG batched vs single at {kmin} steps: {err:.2e}")
-        assert infos[k]["iterations"] == kmin
-        assert err <= 1e-7, k
+        assert np.array_equal(xs[k], host(x1)), k
     sb.close()
     s1.close()
 
@@ -288,11 +274,9 @@ def test_batched_fgmres_rejects_long_restarts():
 @pytest.mark.parametrize("kind", ["braess_sarazin", "variable_viscosity"])
 def test_batched_fgmres_other_operators_match_single(kind):
     """Batched FGMRES with Braess-Sarazin relaxation or a per-element
-    viscosity, every system against its own single-right-hand-side solve:
-    iteration counts within one at rtol 1e-9 and both solutions meeting it
-    (then within 1e-8 of each other per field), and at an equal fixed step
-    count the iterates within 1e-10 per field (the dot products are reduced
-    in a different order, so the iterates differ by rounding only)."""
+    viscosity, every system against its own single-right-hand-side solve
+    at rtol 1e-9: equal iteration counts and bitwise equal solutions (a
+    batch entry does the arithmetic of a single solve)."""
     from stokes_inputs import log_viscosity_field
     N, levels = 16, 3
     kw = {"relaxation": "braess_sarazin"} if kind == "braess_sarazin" else \
@@ -306,27 +290,13 @@ def test_batched_fgmres_other_operators_match_single(kind):
     xb = torch.zeros_like(bb)
     infos = sb.fgmres_solve(bb, xb, rtol=1e-9, restart=20, max_iters=200)
     xs = host(xb).reshape(B, n)
-    counts = []
     for k in range(B):
         b1 = s1.assemble_rhs(dev(fs[k]))
         x1 = torch.zeros_like(b1)
         i1 = s1.fgmres_solve(b1, x1, rtol=1e-9, restart=20, max_iters=200)
+        note(f"{kind}: batched {infos[k]['iterations']} single {i1['iterations']}")
         assert infos[k]["status_name"] == "VKMG_OK" and i1["status_name"] == "VKMG_OK"
-        assert abs(infos[k]["iterations"] - i1["iterations"]) <= 1
-        counts.append(min(infos[k]["iterations"], i1["iterations"]))
-        ref = fem.normalise_pressure(N, host(x1))
-        got = fem.normalise_pressure(N, xs[k])
-        assert rel2(got, ref) <= 1e-8
-    kmin = min(counts)
-    xb = torch.zeros_like(bb)
-    sb.fgmres_solve(bb, xb, rtol=0.0, restart=20, max_iters=kmin)
-    xs = host(xb).reshape(B, n)
-    for k in range(B):
-        b1 = s1.assemble_rhs(dev(fs[k]))
-        x1 = torch.zeros_like(b1)
-        s1.fgmres_solve(b1, x1, rtol=0.0, restart=20, max_iters=kmin)
-        err = rel2(fem.normalise_pressure(N, xs[k]), fem.normalise_pressure(N, host(x1)))
-        note(f"{kind}: batched vs single at {kmin} steps {err:.2e}")
-        assert err <= 1e-10, k
+        assert infos[k]["iterations"] == i1["iterations"]
+        assert np.array_equal(xs[k], host(x1)), k
     sb.close()
     s1.close()

@@ -294,10 +294,12 @@ def cpu_baseline_c3():
 
     N, L = 1024, 8
     t0 = time.perf_counter()
-    H = multigrid.Hierarchy(N, L)
+    H = multigrid.Hierarchy(N, L, progress=lambda m: log(f"[bench] oracle {m}, "
+                                                          f"{time.perf_counter() - t0:.0f} s"))
     setup_s = time.perf_counter() - t0
     f = gaussian_random_field(N, 5, length=0.1)
     _, b, _, _ = fem.stokes_system(N, 1.0, f_nodal=f)
+    log("[bench] oracle V-cycle at 1024x1024")
     t0 = time.perf_counter()
     H.vcycle(b)
     dt = time.perf_counter() - t0

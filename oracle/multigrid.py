@@ -38,12 +38,14 @@ from .vanka import VankaSmoother
 
 class Level:
     def __init__(self, N: int, nu, omega: float, shared, relax: bool, relaxation: str = "vanka",
-                 bs=None, A=None):
+                 bs=None, A=None, progress=None):
         self.N = N
         if A is None:
             self.A, _, self.dmask, _ = stokes_system(N, nu)
         else:
             self.A, self.dmask = A, velocity_dirichlet_mask(N)
+        if progress is not None:
+            progress(f"{N}x{N} operator assembled")
         self.n = self.A.shape[0]
         if not relax:
             self.smoother = None
@@ -60,7 +62,7 @@ class Hierarchy:
 
     def __init__(self, N: int, levels: int, nu: float = 1.0, omega: float = 0.5,
                  nu_pre: int = 2, nu_post: int = 2, shared=None, relaxation: str = "vanka",
-                 bs=None, coarse_operator: str = "rediscretise"):
+                 bs=None, coarse_operator: str = "rediscretise", progress=None):
         if levels < 2:
             raise ValueError("need at least two levels")
         if N % (1 << (levels - 1)):
@@ -93,7 +95,9 @@ class Hierarchy:
         for l in range(levels):
             Nl = N >> (levels - 1 - l)
             self.levels.append(Level(Nl, self.nu_levels[l], omega, shared, relax=(l > 0),
-                                     relaxation=relaxation, bs=bs, A=ops[l]))
+                                     relaxation=relaxation, bs=bs, A=ops[l], progress=progress))
+            if progress is not None:  # (a report only: long setups of large meshes)
+                progress(f"level {l} ({Nl}x{Nl}) built")
         # bordered coarse matrix
         A0 = self.levels[0].A.toarray()
         g0 = grid_sizes(self.levels[0].N)

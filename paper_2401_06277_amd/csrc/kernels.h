@@ -151,7 +151,7 @@ struct GivensLayout {
     // scalar slots (kScalars + ...)
     static constexpr int kBeta0 = 0, kTarget = 1, kBeta = 2, kSigmaPrev = 3, kEst = 4,
                          kActive = 5, kIters = 6, kKdone = 7, kStatus = 8, kMaxIters = 9,
-                         kCycled = 10;
+                         kCycled = 10, kNumScalars = 11;
     static constexpr int kSize = 1920;
 };
 static_assert(GivensLayout::kR + 32 * 35 / 2 <= GivensLayout::kScalars, "packed R fits");

@@ -1023,7 +1023,20 @@ __host__ __device__ inline int vanka_tiles(int N) { return (N + 1 + VT - 1) / VT
 // Staged region of the sweep kernel (per tile, Q2 / Q1 nodes per side):
 //   r region: Q2 [2E0-4, 2E0+2VT+2], Q1 [E0-1, E0+VT]
 constexpr int VR1 = VT + 2;
-constexpr int kRRegion = 2 * VR * VR + VR1 * VR1;
+// The staged residual of a component (VR x VR Q2 nodes) is stored by column
+// parity, even columns then odd ones, each half with row stride VRS: the
+// gather reads column 2tx + a, so the 16 lanes of a patch row then read
+// consecutive words, and with VRS = 24 the four patch rows of a wavefront
+// (two node rows apart) start 32 words apart (no LDS bank conflicts; the
+// plain row-major layout has the lanes of a row two words apart).
+constexpr int VRS = 24;
+constexpr int kRHalf = VR * VRS;
+constexpr int kRComp = 2 * kRHalf;
+__host__ __device__ constexpr int rr_at(int row, int col) {
+    return (col & 1) * kRHalf + row * VRS + (col >> 1);
+}
+static_assert((VR + 1) / 2 <= VRS, "a column-parity half fits its row stride");
+constexpr int kRRegion = 2 * kRComp + VR1 * VR1;
 constexpr int kExchange = 20 * VNT;
 constexpr int kSweepLds = (kRRegion > kExchange) ? kRRegion : kExchange;
 constexpr int kSweepLdsPark = (kSweepLds > kPark * VNT) ? kSweepLds : kPark * VNT;
@@ -1056,8 +1069,9 @@ __device__ __forceinline__ void stage_residual_region(const Geom& g, const T* __
     for (int it = 0; it < kIt; ++it) {
         const int k = threadIdx.x + it * VNT;
         if (k < VR * VR) {
-            sr0[k] = in[it] ? scale * v0[it] : T(0);
-            sr1[k] = in[it] ? scale * v1[it] : T(0);
+            const int l = rr_at(k / VR, k % VR);
+            sr0[l] = in[it] ? scale * v0[it] : T(0);
+            sr1[l] = in[it] ? scale * v1[it] : T(0);
         }
     }
     srp[threadIdx.x] = valid ? (scale * t) * vp : T(0);
@@ -1182,8 +1196,8 @@ __global__ __launch_bounds__(VNT, PARK ? 3 : 2) void vanka_sweep_kernel(Geom g, 
                                                              T t) {
     __shared__ T s_buf[PARK ? kSweepLdsPark : kSweepLds];
     T* const sr0 = s_buf;
-    T* const sr1 = sr0 + VR * VR;
-    T* const srp = sr1 + VR * VR;
+    T* const sr1 = sr0 + kRComp;
+    T* const srp = sr1 + kRComp;
     const int tiles = vanka_tiles(g.N);
     const int ntile = tiles * tiles;
     const int per_xcd = (ntile + 7) / 8;
@@ -1217,7 +1231,7 @@ __global__ __launch_bounds__(VNT, PARK ? 3 : 2) void vanka_sweep_kernel(Geom g, 
         for (int b = 0; b < 5; ++b)
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
-                const int l = (2 * ty + b) * VR + 2 * tx + a;
+                const int l = rr_at(2 * ty + b, 2 * tx + a);
                 rv[5 * b + a] = sr0[l];
                 rv[25 + 5 * b + a] = sr1[l];
             }
@@ -1330,8 +1344,8 @@ __global__ __launch_bounds__(FNT, 1) void vanka_fused_kernel(Geom g, const T* __
     T* const sx1 = sx0 + FX2 * FX2;
     T* const sxp = sx1 + FX2 * FX2;
     T* const sr0 = s_buf + kFArea;        // residual of the r region (unscaled)
-    T* const sr1 = sr0 + VR * VR;
-    T* const srp = sr1 + VR * VR;
+    T* const sr1 = sr0 + kRComp;
+    T* const srp = sr1 + kRComp;
     T* const sdel = sr0 + kRRegion;       // boundary-patch corrections by slot
     const int tiles = vanka_tiles(g.N);
     const int ntile = tiles * tiles;
@@ -1462,8 +1476,9 @@ __global__ __launch_bounds__(FNT, 1) void vanka_fused_kernel(Geom g, const T* __
         for (int it = 0; it < kIt; ++it) {
             const int k = tid + it * FNT;
             if (k < VR * VR) {
-                sr0[k] = in[it] ? v0[it] : T(0);
-                sr1[k] = in[it] ? v1[it] : T(0);
+                const int l = rr_at(k / VR, k % VR);
+                sr0[l] = in[it] ? v0[it] : T(0);
+                sr1[l] = in[it] ? v1[it] : T(0);
             }
         }
         if (tid < VR1 * VR1) srp[tid] = pv ? vpp : T(0);
@@ -1485,8 +1500,8 @@ __global__ __launch_bounds__(FNT, 1) void vanka_fused_kernel(Geom g, const T* __
             if (rx >= VR || ry >= VR) continue;
             const T vx = dir[aa] ? xdx[aa] : ax[aa];
             const T vy = dir[aa] ? xdy[aa] : ay[aa];
-            sr0[ry * VR + rx] = inm[aa] ? bxv[aa] - vx : T(0);
-            sr1[ry * VR + rx] = inm[aa] ? byv[aa] - vy : T(0);
+            sr0[rr_at(ry, rx)] = inm[aa] ? bxv[aa] - vx : T(0);
+            sr1[rr_at(ry, rx)] = inm[aa] ? byv[aa] - vy : T(0);
         }
         if (pitem) srp[(cy - 1) * VR1 + cx - 1] = pin ? bp - ap : T(0);
     }
@@ -1508,7 +1523,7 @@ __global__ __launch_bounds__(FNT, 1) void vanka_fused_kernel(Geom g, const T* __
         for (int bq = 0; bq < 5; ++bq)
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
-                const int l = (2 * ty + bq) * VR + 2 * tx + a;
+                const int l = rr_at(2 * ty + bq, 2 * tx + a);
                 rv[5 * bq + a] = scale * sr0[l];
                 rv[25 + 5 * bq + a] = scale * sr1[l];
             }
@@ -1543,7 +1558,7 @@ __global__ __launch_bounds__(FNT, 1) void vanka_fused_kernel(Geom g, const T* __
             auto rs = [&](int s) -> T {
                 if (s == kSlots - 1) return srp[py * VR1 + px];
                 const int f = s / 25, l = s % 25;
-                return (f ? sr1 : sr0)[(2 * py + l / 5) * VR + 2 * px + l % 5];
+                return (f ? sr1 : sr0)[rr_at(2 * py + l / 5, 2 * px + l % 5)];
             };
             T a0 = 0, a1 = 0;
 #pragma unroll
@@ -1636,8 +1651,8 @@ __global__ __launch_bounds__(VNT, 2) void vanka_mfma_kernel(Geom g, const T* __r
                                                             T t) {
     __shared__ T s_buf[kMfmaLds];
     T* const sr0 = s_buf;
-    T* const sr1 = sr0 + VR * VR;
-    T* const srp = sr1 + VR * VR;
+    T* const sr1 = sr0 + kRComp;
+    T* const srp = sr1 + kRComp;
     T* const xs = s_buf + kRRegion;
     const int tiles = vanka_tiles(g.N);
     const int ntile = tiles * tiles;
@@ -1664,17 +1679,17 @@ __global__ __launch_bounds__(VNT, 2) void vanka_mfma_kernel(Geom g, const T* __r
     stage_residual_region(g, rb, E0x, E0y, scale, t, sr0, sr1, srp);
 
     // per-lane LDS offsets of the quarter's 15 slots for the first round
-    // (patch row 4w); later rounds add 2 VR (velocity) or VP (pressure)
+    // (patch row 4w); later rounds add two node rows (velocity) or VP (pressure)
     const int j = lane & 15, q = lane >> 4;
     int off[kQuarterValues], slot[kQuarterValues];
 #pragma unroll
     for (int k = 0; k < kQuarterValues; ++k) {
         slot[k] = quarter_slot(q, k);
         if (k == 12) {
-            off[k] = 2 * VR * VR + (4 * w) * VP + j;  // the pressure slot
+            off[k] = 2 * kRComp + (4 * w) * VP + j;  // the pressure slot
         } else {
             const int f = slot[k] / 25, rem = slot[k] % 25;
-            off[k] = f * VR * VR + (2 * (4 * w) + rem / 5) * VR + 2 * j + rem % 5;
+            off[k] = f * kRComp + rr_at(2 * (4 * w) + rem / 5, 2 * j + rem % 5);
         }
     }
     // exchange entries written by this quarter: rows b and 4-b of its
@@ -1696,7 +1711,7 @@ __global__ __launch_bounds__(VNT, 2) void vanka_mfma_kernel(Geom g, const T* __r
         T in[kQuarterValues];
 #pragma unroll
         for (int k = 0; k < kQuarterValues; ++k)
-            in[k] = s_buf[off[k] + rho * (k == 12 ? VP : 2 * VR)];
+            in[k] = s_buf[off[k] + rho * (k == 12 ? VP : 2 * VRS)];
         T B[4][4];
         quarter_forward(q, in, B);
         T D[4][4];
@@ -2298,8 +2313,8 @@ __device__ __forceinline__ int packed_col(int j) { return j * (j + 3) / 2; }
 // One Givens step of one system (area `a`, GivensLayout), after the
 // Gram-Schmidt passes of Arnoldi step j; its summary goes to stat[0..5]
 // (estimate, active flag, iterations, kdone, status, |g_kdone|).
-__device__ __attribute__((noinline)) void givens_step(double* __restrict__ a, int j,
-                                                     double* __restrict__ stat) {
+__device__ __forceinline__ void givens_step(double* __restrict__ a, int j,
+                                            double* __restrict__ stat) {
     using GL = GivensLayout;
     double* sc = a + GL::kScalars;
     if (sc[GL::kActive] == 0.0) return;
@@ -2408,23 +2423,28 @@ __global__ __launch_bounds__(64) void givens_init_kernel(double* __restrict__ ar
 }
 
 // y = R^{-1} gv for the k = kdone columns of each system that ran in this
-// cycle (cycled != 0), zeros up to kmax (the columns x += Z y reads).
+// cycle (cycled != 0), zeros up to kmax (the columns x += Z y reads).  One
+// workgroup per system: R and g are staged in LDS, one thread substitutes.
 __global__ __launch_bounds__(64) void givens_solve_kernel(double* __restrict__ area,
-                                                          int64_t stride, int kmax, int nsys) {
+                                                          int64_t stride, int kmax) {
     using GL = GivensLayout;
-    const int k = blockIdx.x * 64 + threadIdx.x;
-    if (k >= nsys) return;
-    double* a = area + int64_t(k) * stride;
+    constexpr int kRSize = GL::kMaxRestart * (GL::kMaxRestart + 3) / 2;
+    __shared__ double sR[kRSize], sg[GL::kMaxRestart + 1], sy[GL::kMaxRestart];
+    double* a = area + int64_t(blockIdx.x) * stride;
+    for (int i = threadIdx.x; i < kRSize; i += 64) sR[i] = a[GL::kR + i];
+    if (threadIdx.x < GL::kMaxRestart + 1) sg[threadIdx.x] = a[GL::kGv + threadIdx.x];
     const double* sc = a + GL::kScalars;
     const int kk = sc[GL::kCycled] != 0.0 ? int(sc[GL::kKdone]) : 0;
-    const double* gv = a + GL::kGv;
-    double* y = a + GL::kY;
-    for (int i = kk; i < kmax; ++i) y[i] = 0.0;
-    for (int i = kk - 1; i >= 0; --i) {
-        double acc = gv[i];
-        for (int l = i + 1; l < kk; ++l) acc -= a[GL::kR + packed_col(l) + i] * y[l];
-        y[i] = acc / a[GL::kR + packed_col(i) + i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = kk - 1; i >= 0; --i) {
+            double acc = sg[i];
+            for (int l = i + 1; l < kk; ++l) acc -= sR[packed_col(l) + i] * sy[l];
+            sy[i] = acc / sR[packed_col(i) + i];
+        }
     }
+    __syncthreads();
+    if (threadIdx.x < kmax) a[GL::kY + threadIdx.x] = threadIdx.x < kk ? sy[threadIdx.x] : 0.0;
 }
 
 // Delayed classical Gram-Schmidt with reorthogonalisation (the DCGS2 of
@@ -2541,8 +2561,6 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(const double* __restri
         cf[1] = gamma;
         cf[2] = d;
         cf[3] = sigma;
-        // the Givens step of this system (area and summary sc apart per entry)
-        if (garea) givens_step(garea + int64_t(blockIdx.y) * sc, j, gstat + 8 * blockIdx.y);
     }
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * 256) {
@@ -2561,6 +2579,26 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(const double* __restri
         const double nx = ((wi - ph) - gamma * vj) * sigma;
         next[i] = nx;
         if (next32) next32[i] = float(nx);
+    }
+    // block 0 of each batch entry: the entry's Givens step, on a copy of its
+    // area in LDS (one thread; global round trips would serialise it)
+    if (garea && blockIdx.x == 0) {
+        using GL = GivensLayout;
+        __shared__ double gl[GL::kSize];
+        double* a = garea + int64_t(blockIdx.y) * sc;
+        constexpr int kState = GL::kScalars + GL::kNumScalars - GL::kCs;
+        for (int i = threadIdx.x; i < 2 * j + 3; i += 256) gl[GL::kDots + i] = a[GL::kDots + i];
+        for (int i = threadIdx.x; i < kState; i += 256) gl[GL::kCs + i] = a[GL::kCs + i];
+        if (threadIdx.x == 0) {
+            gl[GL::kCoef + 0] = alpha;
+            gl[GL::kCoef + 1] = gamma;
+            gl[GL::kCoef + 2] = d;
+            gl[GL::kCoef + 3] = sigma;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) givens_step(gl, j, gstat + 8 * blockIdx.y);
+        __syncthreads();
+        for (int i = threadIdx.x; i < kState; i += 256) a[GL::kCs + i] = gl[GL::kCs + i];
     }
 }
 
@@ -2881,7 +2919,7 @@ void launch_givens_init(double* area, int64_t stride, const double* init, double
 }
 
 void launch_givens_solve(double* area, int64_t stride, int kmax, int nsys, hipStream_t s) {
-    givens_solve_kernel<<<(nsys + 63) / 64, 64, 0, s>>>(area, stride, kmax, nsys);
+    givens_solve_kernel<<<nsys, 64, 0, s>>>(area, stride, kmax);
 }
 
 // Every batch entry is reduced over the same kDotBlocks partial sums as a

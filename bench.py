@@ -18,7 +18,8 @@ V-cycle in FP32 (FGMRES, Arnoldi and the coarse solve kept in FP64) is
 reported under "fp32_mg".
 
 Prints one JSON line.  The roofline object is for the dominant kernel, the
-finest-level Vanka update, timed with HIP events on its launch stream in an
+interior-tile kernel of the finest-level Vanka update (with the boundary-patch
+kernel reported beside it), timed with HIP events on its launch stream in an
 event-timed pass of the same K solves (kernel events bypass the captured
 graphs); that pass also gives the per-class kernel time per solve
 (kernel_ms_per_solve, krylov_share).  "c2_256" reports, at 256 x 256 with 6
@@ -44,11 +45,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
 def measured_traffic():
-    """HBM bytes per finest-level Vanka update measured with rocprofv3 byte
-    counters (profiles/vanka_update_traffic.json), or None if the kernel
+    """HBM bytes per launch of the finest-level Vanka tile kernel measured with rocprofv3 byte
+    counters (profiles/vanka_tile_traffic.json), or None if the kernel
     source has changed since they were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "vanka_update_traffic.json")
+    path = os.path.join(ROOT, "profiles", "vanka_tile_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)

@@ -1212,9 +1212,11 @@ __global__ __launch_bounds__(VNT, PARK ? 3 : 2) void vanka_sweep_kernel(Geom g, 
     }
     const int E0x = (tlin % tiles) * VT, E0y = (tlin / tiles) * VT;
     // the owners' x loads are issued here and land while the patches are
-    // solved (with parking: after the solves, where registers are free)
+    // solved (the boundary-patch index below is formed before the staging:
+    // with it formed after the apply, the parked form had no registers left
+    // for these loads)
     OwnerBase<T> ob;
-    if (!PARK) owner_prefetch(g, E0x, E0y, xin, ob);
+    owner_prefetch(g, E0x, E0y, xin, ob);
     const int tx = threadIdx.x % VP, ty = threadIdx.x / VP;
     const int I = E0x - 1 + tx, J = E0y - 1 + ty;
     const bool valid = I >= 0 && J >= 0 && I <= g.N && J <= g.N;
@@ -1225,6 +1227,8 @@ __global__ __launch_bounds__(VNT, PARK ? 3 : 2) void vanka_sweep_kernel(Geom g, 
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) rv[s] = valid ? dbuf[bi * 64 + s] : T(0);
     } else {
+        const bool interior = valid && I >= 2 && J >= 2 && I <= g.N - 2 && J <= g.N - 2;
+        const int bi = valid && !interior ? boundary_index(I, J, g.N) : 0;
         stage_residual_region(g, rb, E0x, E0y, scale, t, sr0, sr1, srp);
         __syncthreads();
 #pragma unroll
@@ -1243,15 +1247,12 @@ __global__ __launch_bounds__(VNT, PARK ? 3 : 2) void vanka_sweep_kernel(Geom g, 
         } else {
             sym_apply(rv, t);  // interior operator, every lane
         }
-        const bool interior = valid && I >= 2 && J >= 2 && I <= g.N - 2 && J <= g.N - 2;
         if (!interior) {
             // boundary patch: corrections precomputed; outside the domain: none
-            const int bi = valid ? boundary_index(I, J, g.N) : 0;
 #pragma unroll
             for (int s = 0; s < kSlots; ++s) rv[s] = valid ? dbuf[int64_t(bi) * 64 + s] : T(0);
         }
     }
-    if (PARK) owner_prefetch(g, E0x, E0y, xin, ob);
     __syncthreads();  // the staging buffers are reused for the exchange below
 
     // x-sums within the 16-lane rows: column 2tx (even) and 2tx+1 (odd) of

@@ -98,8 +98,9 @@ def parse():
                     help="override the tuning: sweeps of levels with 16 <= N <= this fused "
                          "into one launch (0: never); -1: library default")
     ap.add_argument("--cpu-c3", action="store_true",
-                    help="also time one oracle V(2,2) cycle at 1024x1024, 8 levels (setup of "
-                         "several minutes on the host; not part of the default run)")
+                    help="also time the oracle at 1024x1024, 8 levels: one V(2,2) cycle, one "
+                         "sweep and the full solve, compared with the GPU's FP64 solution "
+                         "(about two minutes on the host; not part of the default run)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB "
                          "(3 times) and exit: the reference kernel for scaling HBM "
@@ -285,12 +286,16 @@ def autotune_only(a):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_c3():
-    """One oracle V(2,2) cycle at 1024 x 1024, 8 levels, on the host cores
-    (the hierarchy's setup timed separately)."""
+def cpu_baseline_c3(x_gpu=None, it_gpu=None):
+    """The oracle at 1024 x 1024, 8 levels, on the host cores: the
+    hierarchy's setup, one V(2,2) cycle, one finest-level sweep (residual and
+    update) and the update alone, and the full FGMRES(30) solve to 1e-8 from
+    x0 = 0; with the GPU's FP64 solution, its distance to the oracle's (the
+    pressure constant removed)."""
+    import numpy as np
     from threadpoolctl import threadpool_info
 
-    from oracle import fem, multigrid
+    from oracle import fem, fgmres, multigrid
     from stokes_inputs import gaussian_random_field
 
     N, L = 1024, 8
@@ -302,13 +307,44 @@ def cpu_baseline_c3():
     _, b, _, _ = fem.stokes_system(N, 1.0, f_nodal=f)
     log("[bench] oracle V-cycle at 1024x1024")
     t0 = time.perf_counter()
-    H.vcycle(b)
+    z = H.vcycle(b)
     dt = time.perf_counter() - t0
+    lev = H.levels[-1]
+    log("[bench] oracle finest-level sweep")
+    t0 = time.perf_counter()
+    lev.smoother.sweep(z, b)
+    sweep_s = time.perf_counter() - t0
+    r = b - lev.A @ z
+    t0 = time.perf_counter()
+    lev.smoother.apply_to_residual(r)
+    apply_s = time.perf_counter() - t0
+    log("[bench] oracle FGMRES solve at 1024x1024")
+    t0 = time.perf_counter()
+    res = fgmres.fgmres(H.A, b, np.zeros_like(b), H.vcycle, rtol=1e-8, restart=30, max_iters=100)
+    solve_s = time.perf_counter() - t0
     blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    return {"value": H.patch_updates_per_cycle() / dt, "unit": "patch-updates/s",
-            "cores": int(blas_threads), "kind": "oracle",
-            "sample": f"1 FP64 V(2,2) cycle of the oracle at {N}x{N} elements, {L} levels",
-            "seconds_per_vcycle": dt, "setup_s": setup_s}
+    out = {"value": H.patch_updates_per_cycle() / dt, "unit": "patch-updates/s",
+           "cores": int(blas_threads), "kind": "oracle",
+           "sample": (f"1 FP64 V(2,2) cycle of the oracle at {N}x{N} elements, {L} levels; "
+                      "one finest-level sweep; the full FGMRES(30) solve to 1e-8"),
+           "seconds_per_vcycle": dt, "setup_s": setup_s,
+           "sweep_s": sweep_s, "sweep_patch_updates_per_s": (N + 1) ** 2 / sweep_s,
+           "update_only_s": apply_s,
+           "solve": {"seconds": solve_s, "iterations": res.iterations,
+                     "true_rel_res": float(np.linalg.norm(b - H.A @ res.x) / np.linalg.norm(b))}}
+    if x_gpu is not None:
+        off_p = 2 * (2 * N + 1) ** 2
+
+        def centred(v):
+            v = np.array(v, dtype=np.float64, copy=True)
+            v[off_p:] -= v[off_p:].mean()
+            return v
+
+        xo = centred(res.x)
+        out["solve"]["fp64_gpu_iterations"] = it_gpu
+        out["solve"]["fp64_gpu_rel_err_vs_oracle"] = float(
+            np.linalg.norm(centred(x_gpu) - xo) / np.linalg.norm(xo))
+    return out
 
 
 def cpu_baseline(N, levels, nvc, c2=None):
@@ -897,8 +933,8 @@ def main():
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(a.cpu_N, a.cpu_levels, a.cpu_vcycles, c2)
         if a.cpu_c3:
-            log("[bench] cpu baseline at 1024x1024 (oracle, one V-cycle)")
-            out["cpu_baseline"]["c3_1024"] = cpu_baseline_c3()
+            log("[bench] cpu baseline at 1024x1024 (oracle: V-cycle, sweep, solve)")
+            out["cpu_baseline"]["c3_1024"] = cpu_baseline_c3(x64.cpu().numpy(), it64[0])
     print(json.dumps(out), flush=True)
 
 

@@ -98,9 +98,10 @@ def parse():
                     help="override the tuning: sweeps of levels with 16 <= N <= this fused "
                          "into one launch (0: never); -1: library default")
     ap.add_argument("--cpu-c3", action="store_true",
-                    help="also time the oracle at 1024x1024, 8 levels: one V(2,2) cycle, one "
-                         "sweep and the full solve, compared with the GPU's FP64 solution "
-                         "(about two minutes on the host; not part of the default run)")
+                    help="also time the oracle at 1024x1024, 8 levels (one V(2,2) cycle, one "
+                         "sweep and the full solve) and one right-hand side of the 512x512 "
+                         "batch, compared with the GPU's FP64 solutions (a few minutes on "
+                         "the host; not part of the default run)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB "
                          "(3 times) and exit: the reference kernel for scaling HBM "
@@ -347,6 +348,47 @@ def cpu_baseline_c3(x_gpu=None, it_gpu=None):
     return out
 
 
+def cpu_baseline_c4(gpu=None, batch=32):
+    """The oracle's solve of right-hand side 0 of the 512 x 512, 7-level
+    batched workload (GRF body force seed 1000, lid u = (1, 0) on the top
+    edge, x0 = the Dirichlet lifting, FGMRES(30) to 1e-8), on the host cores,
+    setup timed apart; the batch's time extrapolated as `batch` such solves;
+    with the GPU's FP64 batched solution of that right-hand side, its distance
+    to the oracle's (the pressure constant removed)."""
+    import numpy as np
+
+    from oracle import fem, fgmres, multigrid
+    from stokes_inputs import gaussian_random_field, lid_boundary_values
+
+    N, L = 512, 7
+    t0 = time.perf_counter()
+    H = multigrid.Hierarchy(N, L)
+    A, b, _, xl = fem.stokes_system(N, 1.0, f_nodal=gaussian_random_field(N, 1000),
+                                    g_nodal=lid_boundary_values(N))
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ro = fgmres.fgmres(A, b, xl, H.vcycle, rtol=1e-8, restart=30, max_iters=500)
+    solve_s = time.perf_counter() - t0
+    out = {"setup_s": setup_s, "seconds_per_rhs": solve_s, "iterations": ro.iterations,
+           f"seconds_for_{batch}_rhs_extrapolated": batch * solve_s,
+           "sample": ("one right-hand side of the 512x512, 7-level batch (seed 1000, lid), "
+                      f"timed once; the batch as {batch} such solves")}
+    if gpu is not None:
+        xg, itg = gpu
+        off_p = 2 * (2 * N + 1) ** 2
+
+        def centred(v):
+            v = np.array(v, dtype=np.float64, copy=True)
+            v[off_p:] -= v[off_p:].mean()
+            return v
+
+        xo = centred(ro.x)
+        out["fp64_gpu_batched_iterations"] = itg
+        out["fp64_gpu_batched_rel_err_vs_oracle"] = float(
+            np.linalg.norm(centred(xg) - xo) / np.linalg.norm(xo))
+    return out
+
+
 def cpu_baseline(N, levels, nvc, c2=None):
     """Oracle V-cycles at N x N (setup excluded), patch-updates/s.  With the
     256 x 256 GPU solutions, also the oracle's own FGMRES solve of that
@@ -382,6 +424,17 @@ def cpu_baseline(N, levels, nvc, c2=None):
     extra["single_thread"] = {"value": H.patch_updates_per_cycle() * n1 / dt1,
                               "unit": "patch-updates/s", "cores": 1,
                               "sample": f"{n1} V(2,2) cycles at {N}x{N}, BLAS limited to 1 thread"}
+    # C1: the 16 x 16, 3-level manufactured-solution solve, setup included
+    from oracle import fgmres
+    from stokes_inputs import manufactured_boundary_values, manufactured_nodal_force
+    t0 = time.perf_counter()
+    H1 = multigrid.Hierarchy(16, 3)
+    A1, b1, _, xl1 = fem.stokes_system(16, 1.0, f_nodal=manufactured_nodal_force(16, "trig"),
+                                       g_nodal=manufactured_boundary_values(16, "trig"))
+    r1 = fgmres.fgmres(A1, b1, xl1, H1.vcycle, rtol=1e-8, restart=30, max_iters=500)
+    extra["oracle_solve_16"] = {"seconds": time.perf_counter() - t0, "iterations": r1.iterations,
+                                "sample": "16x16 elements, 3 levels, trigonometric manufactured "
+                                          "solution, FGMRES(30) to 1e-8, setup included"}
     if c2 is not None and N == 256:
         from oracle import fgmres
         from stokes_inputs import manufactured_boundary_values, manufactured_nodal_force
@@ -552,6 +605,8 @@ def bench_c4(a, vk, torch, np):
                                      "patch_updates_per_s": ups * sum(its1) / ts}
         res[f"batched_speedup_{prec}"] = ts / tb
         res[f"batched_vs_sequential_max_rel_diff_{prec}"] = dmax
+        if prec == "fp64":  # right-hand side 0, for the oracle comparison
+            res["_solution_fp64_rhs0"] = (xb[0].cpu().numpy(), its[0])
         s1.close()
         del xs, bs, b, x, x0, xb
         torch.cuda.empty_cache()
@@ -926,8 +981,10 @@ def main():
     if not a.skip_c5:
         out["c5_256_variable_viscosity"] = bench_c5(a, vk, torch, np)
 
+    c4 = None
     if not a.skip_c4:
-        out["c4_512_batched"] = bench_c4(a, vk, torch, np)
+        c4 = bench_c4(a, vk, torch, np)
+        out["c4_512_batched"] = {k: v for k, v in c4.items() if not k.startswith("_")}
 
     if not a.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
@@ -935,6 +992,9 @@ def main():
         if a.cpu_c3:
             log("[bench] cpu baseline at 1024x1024 (oracle: V-cycle, sweep, solve)")
             out["cpu_baseline"]["c3_1024"] = cpu_baseline_c3(x64.cpu().numpy(), it64[0])
+            log("[bench] cpu baseline at 512x512, one right-hand side (oracle solve)")
+            out["cpu_baseline"]["c4_512"] = cpu_baseline_c4(
+                c4.get("_solution_fp64_rhs0") if c4 else None, a.c4_batch)
     print(json.dumps(out), flush=True)
 
 

@@ -796,7 +796,11 @@ def main():
         x = torch.zeros_like(b)
         return s, b, x
 
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
     s64, b, x = make("fp64")
+    torch.cuda.synchronize()
+    setup64_s = time.perf_counter() - t_setup  # vkmg_setup and the load assembly
     n = s64.layout["n"]
     ups_per_cycle = sum(4 * ((N >> (L - 1 - l)) + 1) ** 2 for l in range(1, L))
 
@@ -890,6 +894,7 @@ def main():
             "tuning": s64.get_tuning(),
         },
         "time_to_1e8_s": dt64 / a.steps,
+        "setup_s": setup64_s,
         "time_to_1e8_s_without_graphs": dt64_ev / a.steps,
         "kernel_ms_per_solve": breakdown,
         "krylov_share": breakdown["krylov"] / max(sum(breakdown.values()), 1e-300),
@@ -937,7 +942,11 @@ def main():
     s64.close()
 
     if not a.skip_fp32:
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter()
         s32, b32, x32 = make("fp32")
+        torch.cuda.synchronize()
+        setup32_s = time.perf_counter() - t_setup
         log("[bench] fp32-mg warmup")
         run_solves(s32, b32, x32, a.warmup, False)
         log("[bench] fp32-mg timed")
@@ -952,6 +961,7 @@ def main():
         diff = float(torch.linalg.norm(centred(x32) - centred(x64)) / torch.linalg.norm(centred(x64)))
         out["fp32_mg"] = {
             "time_to_1e8_s": dt32 / a.steps,
+            "setup_s": setup32_s,
             "fgmres_iterations": it32[0],
             "true_rel_res": inf32[-1]["true_rel_res"],
             "patch_updates_per_s": ups_per_cycle * sum(it32) / dt32,

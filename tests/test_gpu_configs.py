@@ -10,7 +10,13 @@ C4 (512 x 512, 7 levels, 32 right-hand sides: Gaussian random forces seeds
 1000 + k under the watertight lid): one batched solve against 32 single
 solves of the same systems: iteration counts equal and solutions bitwise
 equal (batched launches do the arithmetic of single ones, and every batch
-entry is reduced over the same partial sums as a single right-hand side).
+entry is reduced over the same partial sums as a single right-hand side);
+and, in FP64 multigrid, the batch entries 0 and 31 against the oracle's
+solves of those systems (tests/golden/c4_oracle_512.json, written by
+tests/golden/make_c4_oracle.py): iteration counts within one at rtol 1e-8,
+and after exactly the oracle's count the solutions within 1e-10 of each
+field's maximum at the sampled DoFs and the true relative residuals equal
+to the oracle's to 1e-3 relative.
 
 C5 (256 x 256, 6 levels, log nu ~ U[-1, 1] seed 7, Gaussian random force
 seed 5, L = |x - x_t|^2 / 2 with x_t = 0.01 GRF seed 6 on the velocity):
@@ -117,6 +123,54 @@ def test_c4_batched_32_equals_single_solves():
             assert np.array_equal(xb[k], xs), (k, e)
     note(f"[C4] {B} systems: iterations {[i['iterations'] for i in infos]}, "
          f"worst batched-vs-single difference {worst:.2e}")
+
+
+def test_c4_batched_fp64_matches_oracle_golden():
+    import json
+    import os
+    N, levels, B = 512, 7, 32
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_oracle_512.json")
+    with open(path) as fh:
+        d = json.load(fh)
+    assert d["N"] == N and d["levels"] == levels
+    note(f"[C4 golden] N={N} levels={levels} batch={B} fp64")
+    fs = np.concatenate([gaussian_random_field(N, 1000 + k).ravel() for k in range(B)])
+    g = lid_boundary_values(N).ravel()
+    gs = grid_sizes(N)
+    dofs = np.array(d["dofs"])
+    field = np.searchsorted([gs.off_uy, gs.off_p], dofs, side="right")
+    with vk.VkmgSolver(N, levels, precision="fp64", batch=B) as s:
+        n = s.layout["n"]
+        b = s.assemble_rhs(dev(fs), dev(np.tile(g, B)))
+        x0 = s.dirichlet_lift(b)
+        x = x0.clone()
+        infos = s.fgmres_solve(b, x, rtol=1e-8)
+        for k, ref in d["rhs"].items():
+            k = int(k)
+            note(f"[C4 golden] k={k}: GPU {infos[k]['iterations']} iterations, "
+                 f"oracle {ref['iterations']}")
+            assert infos[k]["status_name"] == "VKMG_OK"
+            assert abs(infos[k]["iterations"] - ref["iterations"]) <= 1
+        for m in sorted({ref["iterations"] for ref in d["rhs"].values()}):
+            x = x0.clone()
+            infos_m = s.fgmres_solve(b, x, rtol=0.0, max_iters=m)
+            xb = host(x).reshape(B, n)
+            for k, ref in d["rhs"].items():
+                if ref["iterations"] != m:
+                    continue
+                k = int(k)
+                assert infos_m[k]["iterations"] == m
+                assert abs(infos_m[k]["true_rel_res"] - ref["true_rel_res"]) <= 1e-3 * ref["true_rel_res"]
+                xn = fem.normalise_pressure(N, xb[k])
+                want = np.array(ref["solution"])
+                worst = []
+                for f in range(3):
+                    sel = field == f
+                    assert sel.sum() > 1000
+                    worst.append(np.abs(xn[dofs][sel] - want[sel]).max() / ref["solution_field_max"][f])
+                note(f"[C4 golden] k={k} after {m} steps: per-field max error "
+                     f"{['%.2e' % e for e in worst]}")
+                assert max(worst) <= 1e-10, (k, worst)
 
 
 def test_c5_gradients_match_central_differences_at_256():

@@ -18,8 +18,15 @@ and after exactly the oracle's count the solutions within 1e-10 of each
 field's maximum at the sampled DoFs and the true relative residuals equal
 to the oracle's to 1e-3 relative.
 
-C5 (256 x 256, 6 levels, log nu ~ U[-1, 1] seed 7, Gaussian random force
-seed 5, L = |x - x_t|^2 / 2 with x_t = 0.01 GRF seed 6 on the velocity):
+C5 forward solve (256 x 256, 6 levels, log nu ~ U[-1, 1] seed 7, Gaussian
+random force seed 5, one inverse per patch): against the oracle's solve
+(tests/golden/c5_oracle_256.json, written by tests/golden/make_c5_oracle.py):
+iteration count within one at rtol 1e-8, and after exactly the oracle's
+count the solution within 1e-10 of each field's maximum at the sampled DoFs
+and the true relative residual equal to the oracle's to 1e-3 relative.
+
+C5 gradients (the same viscosity and force, L = |x - x_t|^2 / 2 with
+x_t = 0.01 GRF seed 6 on the velocity):
 the autograd gradients with respect to the log-viscosity and the force
 against central differences of the GPU solve on 20 seeded directions
 (seed 8), 1e-6 relative (solves at rtol 1e-10: with this viscosity field
@@ -171,6 +178,46 @@ def test_c4_batched_fp64_matches_oracle_golden():
                 note(f"[C4 golden] k={k} after {m} steps: per-field max error "
                      f"{['%.2e' % e for e in worst]}")
                 assert max(worst) <= 1e-10, (k, worst)
+
+
+def _per_field(got, want, dofs, gs, field_max):
+    field = np.searchsorted([gs.off_uy, gs.off_p], dofs, side="right")
+    worst = []
+    for f in range(3):
+        sel = field == f
+        assert sel.sum() > 1000
+        worst.append(float(np.abs(got[sel] - want[sel]).max() / field_max[f]))
+    return worst
+
+
+def test_c5_forward_solve_matches_oracle_golden():
+    import json
+    import os
+    N, levels = 256, 6
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_oracle_256.json")
+    with open(path) as fh:
+        d = json.load(fh)
+    assert d["N"] == N and d["levels"] == levels
+    note(f"[C5 golden] N={N} levels={levels} per-element viscosity")
+    nu = np.exp(log_viscosity_field(N, 7))
+    gs = grid_sizes(N)
+    dofs = np.array(d["dofs"])
+    with vk.VkmgSolver(N, levels, nu_elem=nu) as s:
+        b = s.assemble_rhs(dev(gaussian_random_field(N, 5).ravel()))
+        x = torch.zeros_like(b)
+        info = s.fgmres_solve(b, x, rtol=1e-8)
+        note(f"[C5 golden] GPU {info['iterations']} iterations, oracle {d['iterations']}")
+        assert info["status_name"] == "VKMG_OK"
+        assert abs(info["iterations"] - d["iterations"]) <= 1
+        m = d["iterations"]
+        x = torch.zeros_like(b)
+        info_m = s.fgmres_solve(b, x, rtol=0.0, max_iters=m)
+        assert info_m["iterations"] == m
+        assert abs(info_m["true_rel_res"] - d["true_rel_res"]) <= 1e-3 * d["true_rel_res"]
+        xn = fem.normalise_pressure(N, host(x))
+        worst = _per_field(xn[dofs], np.array(d["solution"]), dofs, gs, d["solution_field_max"])
+        note(f"[C5 golden] after {m} steps: per-field max error {['%.2e' % e for e in worst]}")
+        assert max(worst) <= 1e-10, worst
 
 
 def test_c5_gradients_match_central_differences_at_256():

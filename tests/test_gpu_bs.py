@@ -155,3 +155,48 @@ def test_bs_fp32_multigrid_fgmres_reaches_fp64_tolerance():
     assert info["status_name"] == "VKMG_OK"
     assert np.linalg.norm(b - A @ host(x)) <= 1.01e-8 * np.linalg.norm(b - A @ xl)
     s.close()
+
+
+def test_bs_benchmark_solve_matches_oracle_golden():
+    """The benchmark's Braess-Sarazin solve at 1024 x 1024, 8 levels (GRF
+    force seed 5, x0 = 0, t = 1, omega_BS = 1, two Jacobi sweeps of weight 1,
+    FGMRES(30) to 1e-8) against the oracle's (tests/golden/bs_oracle_1024.json,
+    written by tests/golden/make_bs_oracle.py): iteration count within one;
+    after exactly the oracle's count the solution within 1e-10 of each
+    field's maximum at the sampled DoFs and the true relative residual equal
+    to the oracle's to 1e-3 relative."""
+    import json
+    import os
+
+    from stokes_inputs import gaussian_random_field, grid_sizes
+    N, levels = 1024, 8
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bs_oracle_1024.json")
+    with open(path) as fh:
+        d = json.load(fh)
+    assert d["N"] == N and d["levels"] == levels and d["bs"] == PARAMS[0]
+    note(f"[BS golden] N={N} levels={levels}")
+    gs = grid_sizes(N)
+    dofs = np.array(d["dofs"])
+    field = np.searchsorted([gs.off_uy, gs.off_p], dofs, side="right")
+    s = _solver(N, levels, PARAMS[0])
+    b = s.assemble_rhs(dev(gaussian_random_field(N, 5, length=0.1).ravel()))
+    x = torch.zeros_like(b)
+    info = s.fgmres_solve(b, x, rtol=1e-8, restart=30, max_iters=200)
+    note(f"[BS golden] GPU {info['iterations']} iterations, oracle {d['iterations']}")
+    assert info["status_name"] == "VKMG_OK"
+    assert abs(info["iterations"] - d["iterations"]) <= 1
+    m = d["iterations"]
+    x = torch.zeros_like(b)
+    info_m = s.fgmres_solve(b, x, rtol=0.0, restart=30, max_iters=m)
+    assert info_m["iterations"] == m
+    assert abs(info_m["true_rel_res"] - d["true_rel_res"]) <= 1e-3 * d["true_rel_res"]
+    xn = fem.normalise_pressure(N, host(x))
+    want = np.array(d["solution"])
+    worst = []
+    for f in range(3):
+        sel = field == f
+        assert sel.sum() > 1000
+        worst.append(float(np.abs(xn[dofs][sel] - want[sel]).max() / d["solution_field_max"][f]))
+    note(f"[BS golden] after {m} steps: per-field max error {['%.2e' % e for e in worst]}")
+    assert max(worst) <= 1e-10, worst
+    s.close()

@@ -316,3 +316,36 @@ def test_fullsize_fgmres_matches_oracle_golden(golden_dir):
     dofs = np.array(d["dofs"])
     _per_field_sampled(xn[dofs], np.array(d["solution"]), dofs, d["solution_field_max"], 1e-10,
                        f"FGMRES solution after {k} steps vs oracle")
+
+
+def test_fullsize_fp32_multigrid_fgmres_matches_oracle_golden(golden_dir):
+    """The benchmark's solve with the V-cycle in FP32 (FGMRES, the Arnoldi
+    process and the coarse solve in FP64) against the oracle's FP64 solve
+    (tests/golden/make_c3_oracle.py): iteration count within one of the
+    oracle's at rtol 1e-8; after exactly the oracle's count the true relative
+    residual at the tolerance (3.6e-9 against the oracle's 2.9e-9) and the
+    solution within 1e-8 of each field's maximum at the sampled DoFs.  The
+    FP32 cycle perturbs each preconditioned direction by ~1e-7 relative, so
+    the two solves follow different Krylov paths (FGMRES, being flexible,
+    still converges at the FP64 rate); their iterates agree to the level of
+    their distance from the exact solution, set by the tolerance, not to
+    rounding (measured: velocity 1.5e-11, pressure 4.4e-9 of its maximum)."""
+    d = _golden(golden_dir)
+    s = solver(precision="fp32")
+    g = grid_sizes(N_FULL)
+    f = gaussian_random_field(N_FULL, 5, length=0.1)
+    b = s.assemble_rhs(dev(f.ravel()))
+    x = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info = s.fgmres_solve(b, x, rtol=1e-8, restart=30, max_iters=500)
+    note(f"fp32-MG fgmres N={N_FULL}: {info}; oracle (FP64) {d['iterations']} iterations")
+    assert info["status_name"] == "VKMG_OK"
+    assert abs(info["iterations"] - d["iterations"]) <= 1
+    k = d["iterations"]
+    x = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info_k = s.fgmres_solve(b, x, rtol=0.0, restart=30, max_iters=k)
+    assert info_k["iterations"] == k
+    assert info_k["true_rel_res"] <= 1e-8, info_k
+    xn = fem.normalise_pressure(N_FULL, host(x))
+    dofs = np.array(d["dofs"])
+    _per_field_sampled(xn[dofs], np.array(d["solution"]), dofs, d["solution_field_max"], 1e-8,
+                       f"FP32-MG FGMRES solution after {k} steps vs oracle (FP64)")

@@ -272,32 +272,36 @@ def _per_field_sampled(got, want, dofs, field_max, tol, what):
     assert max(worst) <= tol, (what, worst)
 
 
-def test_fullsize_vcycle_matches_oracle_golden(golden_dir):
+@pytest.mark.parametrize("apply", ["vector", "matrix"])
+def test_fullsize_vcycle_matches_oracle_golden(golden_dir, apply):
     """One FP64 V(2,2) cycle at 1024 x 1024 (the launch configuration of the
     benchmark: parked tile kernel on the two finest levels, separate
-    prolongation above 256 x 256) against the oracle's cycle written by
-    tests/golden/make_c3_oracle.py, at ~5600 sampled DoFs: 1e-11 per field
-    (u_x, u_y, p each against its whole-field maximum)."""
+    prolongation above 256 x 256; or the interior apply on the matrix cores)
+    against the oracle's cycle written by tests/golden/make_c3_oracle.py, at
+    ~5600 sampled DoFs: 1e-11 per field (u_x, u_y, p each against its
+    whole-field maximum)."""
     d = _golden(golden_dir)
-    s = solver()
+    s = solver(apply=apply)
     g = grid_sizes(N_FULL)
     r = uniform_vector(g.n, d["vcycle_input"]["seed"])
     r[velocity_dirichlet_mask(N_FULL)] = 0.0
     z = host(s.vcycle(dev(r)))
     dofs = np.array(d["dofs"])
     _per_field_sampled(z[dofs], np.array(d["vcycle"]), dofs, d["vcycle_field_max"], 1e-11,
-                       "V-cycle vs oracle")
+                       f"V-cycle ({apply} apply) vs oracle")
 
 
-def test_fullsize_fgmres_matches_oracle_golden(golden_dir):
+@pytest.mark.parametrize("apply", ["vector", "matrix"])
+def test_fullsize_fgmres_matches_oracle_golden(golden_dir, apply):
     """The benchmark's solve (GRF force seed 5, x0 = 0, FGMRES(30), rtol
-    1e-8) against the oracle's (tests/golden/make_c3_oracle.py): iteration
-    count within one of the oracle's; after exactly the oracle's count
-    (rtol 0 and that cap) the solution, pressure reduced to zero
-    mass-weighted mean, within 1e-10 per field at the sampled DoFs, and the
-    true relative residual equal to the oracle's to 1e-3 relative."""
+    1e-8; interior apply on the vector ALUs or the matrix cores) against the
+    oracle's (tests/golden/make_c3_oracle.py): iteration count within one of
+    the oracle's; after exactly the oracle's count (rtol 0 and that cap) the
+    solution, pressure reduced to zero mass-weighted mean, within 1e-10 per
+    field at the sampled DoFs, and the true relative residual equal to the
+    oracle's to 1e-3 relative."""
     d = _golden(golden_dir)
-    s = solver()
+    s = solver(apply=apply)
     g = grid_sizes(N_FULL)
     f = gaussian_random_field(N_FULL, 5, length=0.1)
     b = s.assemble_rhs(dev(f.ravel()))
@@ -315,7 +319,7 @@ def test_fullsize_fgmres_matches_oracle_golden(golden_dir):
     xn = fem.normalise_pressure(N_FULL, host(x))
     dofs = np.array(d["dofs"])
     _per_field_sampled(xn[dofs], np.array(d["solution"]), dofs, d["solution_field_max"], 1e-10,
-                       f"FGMRES solution after {k} steps vs oracle")
+                       f"FGMRES ({apply} apply) solution after {k} steps vs oracle")
 
 
 def test_fullsize_fp32_multigrid_fgmres_matches_oracle_golden(golden_dir):

@@ -5,6 +5,10 @@ lifting): FGMRES(30) iteration count within one of the oracle's at rtol
 1e-8, and after exactly the oracle's count the solution (pressure reduced
 to zero mass-weighted mean) within 1e-10 per field, in FP64 multigrid; the
 FP32-multigrid solve reaches the FP64 tolerance within one iteration of it.
+The benchmark's standalone finest-level sweeps at this size (the update
+given a seeded uniform[-1, 1] residual, and residual + update given x and
+b) against the oracle's one-DoF-at-a-time sweep at sampled DoFs (corners,
+edges, tile seams, random), 1e-12 of each field's maximum.
 
 C4 (512 x 512, 7 levels, 32 right-hand sides: Gaussian random forces seeds
 1000 + k under the watertight lid): one batched solve against 32 single
@@ -37,10 +41,10 @@ residual of about 1.5e-11, so 1e-12 is out of reach).
 import numpy as np
 import pytest
 
-from oracle import fem, fgmres, multigrid
-from stokes_inputs import (gaussian_random_field, grid_sizes, lid_boundary_values,
-                           log_viscosity_field, manufactured_boundary_values,
-                           manufactured_nodal_force)
+from oracle import fem, fgmres, multigrid, vanka
+from stokes_inputs import (dirichlet_consistent_pair, gaussian_random_field, grid_sizes,
+                           lid_boundary_values, log_viscosity_field, manufactured_boundary_values,
+                           manufactured_nodal_force, uniform_vector, velocity_dirichlet_mask)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -103,6 +107,60 @@ def test_c2_manufactured_solve_matches_oracle():
                 note(f"[C2] solution after {k} steps vs oracle: {err:.2e} (worst field)")
                 assert err <= 1e-10
 
+
+
+def _c2_sample_dofs(N, seed, n_random=400):
+    """Corners, edges, one and two elements in, the seams of 14- and
+    16-element tiles, and random DoFs, in all three fields."""
+    g = grid_sizes(N)
+    s2, s1 = g.q2_side, g.q1_side
+    near = sorted({0, 1, 2, 3, 4, 5} | {s2 - 1 - k for k in range(6)}
+                  | {2 * 14 - 1, 2 * 14, 2 * 14 + 1, 2 * 16, 2 * 16 + 1, s2 // 2})
+    near1 = sorted({0, 1, 2, 3, s1 - 4, s1 - 3, s1 - 2, s1 - 1, 13, 14, 15, 16, 17, s1 // 2})
+    dofs = []
+    for i, qi in enumerate(near):
+        qj = near[(3 * i + 1) % len(near)]
+        dofs += [g.off_ux + qj * s2 + qi, g.off_uy + qi * s2 + qj]
+    for k, I in enumerate(near1):
+        dofs.append(g.off_p + near1[(5 * k + 2) % len(near1)] * s1 + I)
+    rng = np.random.default_rng(seed)
+    dofs += list(rng.choice(g.n, n_random, replace=False))
+    return np.array(sorted(set(int(d) for d in dofs)))
+
+
+def _fieldwise_close(N, got, want, dofs, tol, what):
+    g = grid_sizes(N)
+    field = np.searchsorted([g.off_uy, g.off_p], dofs, side="right")
+    worst = []
+    for f in range(3):
+        sel = field == f
+        assert sel.sum() > 5, (what, f)
+        worst.append(float(np.abs(got[sel] - want[sel]).max() / max(np.abs(want[sel]).max(), 1e-300)))
+    note(f"{what}: per-field max error {['%.2e' % e for e in worst]} at {len(dofs)} sampled DoFs")
+    assert max(worst) <= tol, (what, worst)
+
+
+def test_c2_standalone_sweeps_match_oracle():
+    N, levels = 256, 6
+    top = levels - 1
+    g = grid_sizes(N)
+    dofs = _c2_sample_dofs(N, 21)
+    note(f"[C2 sweeps] N={N} levels={levels}: {len(dofs)} sampled DoFs")
+    rin = uniform_vector(g.n, 2)
+    rin[velocity_dirichlet_mask(N)] = 0.0
+    xin, bin_ = dirichlet_consistent_pair(N, 3, 4)
+    with vk.VkmgSolver(N, levels) as s:
+        x = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+        s.vanka_update(top, x, dev(rin))
+        got = host(x)[dofs]
+        # x = 0: the sweep's residual is the given vector itself
+        want = vanka.sampled_sweep_update(N, np.zeros(g.n), rin, dofs)
+        _fieldwise_close(N, got, want, dofs, 1e-12, "[C2] update given r")
+        x = dev(xin.copy())
+        s.vanka_sweep(top, x, dev(bin_))
+        got = host(x)[dofs] - xin[dofs]
+        want = vanka.sampled_sweep_update(N, xin, bin_, dofs)
+        _fieldwise_close(N, got, want, dofs, 1e-12, "[C2] residual + update given x, b")
 
 def test_c4_batched_32_equals_single_solves():
     N, levels, B = 512, 7, 32

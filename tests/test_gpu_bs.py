@@ -157,14 +157,19 @@ def test_bs_fp32_multigrid_fgmres_reaches_fp64_tolerance():
     s.close()
 
 
-def test_bs_benchmark_solve_matches_oracle_golden():
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bs_benchmark_solve_matches_oracle_golden(precision):
     """The benchmark's Braess-Sarazin solve at 1024 x 1024, 8 levels (GRF
     force seed 5, x0 = 0, t = 1, omega_BS = 1, two Jacobi sweeps of weight 1,
     FGMRES(30) to 1e-8) against the oracle's (tests/golden/bs_oracle_1024.json,
     written by tests/golden/make_bs_oracle.py): iteration count within one;
-    after exactly the oracle's count the solution within 1e-10 of each
-    field's maximum at the sampled DoFs and the true relative residual equal
-    to the oracle's to 1e-3 relative."""
+    after exactly the oracle's count, with the V-cycle in FP64 the solution
+    within 1e-10 of each field's maximum at the sampled DoFs and the true
+    relative residual equal to the oracle's to 1e-3 relative; with the
+    V-cycle in FP32 (FGMRES in FP64) the true relative residual at the
+    tolerance and the solution within 1e-8 per field (the FP32 cycle changes
+    the Krylov path, so the solves agree to their distance from the exact
+    solution, not to rounding)."""
     import json
     import os
 
@@ -174,11 +179,11 @@ def test_bs_benchmark_solve_matches_oracle_golden():
     with open(path) as fh:
         d = json.load(fh)
     assert d["N"] == N and d["levels"] == levels and d["bs"] == PARAMS[0]
-    note(f"[BS golden] N={N} levels={levels}")
+    note(f"[BS golden] N={N} levels={levels} {precision}")
     gs = grid_sizes(N)
     dofs = np.array(d["dofs"])
     field = np.searchsorted([gs.off_uy, gs.off_p], dofs, side="right")
-    s = _solver(N, levels, PARAMS[0])
+    s = _solver(N, levels, PARAMS[0], precision=precision)
     b = s.assemble_rhs(dev(gaussian_random_field(N, 5, length=0.1).ravel()))
     x = torch.zeros_like(b)
     info = s.fgmres_solve(b, x, rtol=1e-8, restart=30, max_iters=200)
@@ -189,7 +194,10 @@ def test_bs_benchmark_solve_matches_oracle_golden():
     x = torch.zeros_like(b)
     info_m = s.fgmres_solve(b, x, rtol=0.0, restart=30, max_iters=m)
     assert info_m["iterations"] == m
-    assert abs(info_m["true_rel_res"] - d["true_rel_res"]) <= 1e-3 * d["true_rel_res"]
+    if precision == "fp64":
+        assert abs(info_m["true_rel_res"] - d["true_rel_res"]) <= 1e-3 * d["true_rel_res"]
+    else:
+        assert info_m["true_rel_res"] <= 1e-8, info_m
     xn = fem.normalise_pressure(N, host(x))
     want = np.array(d["solution"])
     worst = []
@@ -197,6 +205,7 @@ def test_bs_benchmark_solve_matches_oracle_golden():
         sel = field == f
         assert sel.sum() > 1000
         worst.append(float(np.abs(xn[dofs][sel] - want[sel]).max() / d["solution_field_max"][f]))
-    note(f"[BS golden] after {m} steps: per-field max error {['%.2e' % e for e in worst]}")
-    assert max(worst) <= 1e-10, worst
+    note(f"[BS golden] after {m} steps ({precision} V-cycle): per-field max error "
+         f"{['%.2e' % e for e in worst]}, true rel res {info_m['true_rel_res']:.2e}")
+    assert max(worst) <= (1e-10 if precision == "fp64" else 1e-8), worst
     s.close()

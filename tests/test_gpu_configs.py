@@ -301,7 +301,11 @@ def _per_field(got, want, dofs, gs, field_max):
     return worst
 
 
-def test_c5_forward_solve_matches_oracle_golden():
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c5_forward_solve_matches_oracle_golden(precision):
+    """With the V-cycle in FP32 (FGMRES in FP64) the bounds after the
+    oracle's count are those of the FP32-multigrid solves: true residual at
+    the tolerance, solution within 1e-8 per field."""
     import json
     import os
     N, levels = 256, 6
@@ -309,11 +313,11 @@ def test_c5_forward_solve_matches_oracle_golden():
     with open(path) as fh:
         d = json.load(fh)
     assert d["N"] == N and d["levels"] == levels
-    note(f"[C5 golden] N={N} levels={levels} per-element viscosity")
+    note(f"[C5 golden] N={N} levels={levels} per-element viscosity, {precision} V-cycle")
     nu = np.exp(log_viscosity_field(N, 7))
     gs = grid_sizes(N)
     dofs = np.array(d["dofs"])
-    with vk.VkmgSolver(N, levels, nu_elem=nu) as s:
+    with vk.VkmgSolver(N, levels, nu_elem=nu, precision=precision) as s:
         b = s.assemble_rhs(dev(gaussian_random_field(N, 5).ravel()))
         x = torch.zeros_like(b)
         info = s.fgmres_solve(b, x, rtol=1e-8)
@@ -324,11 +328,15 @@ def test_c5_forward_solve_matches_oracle_golden():
         x = torch.zeros_like(b)
         info_m = s.fgmres_solve(b, x, rtol=0.0, max_iters=m)
         assert info_m["iterations"] == m
-        assert abs(info_m["true_rel_res"] - d["true_rel_res"]) <= 1e-3 * d["true_rel_res"]
+        if precision == "fp64":
+            assert abs(info_m["true_rel_res"] - d["true_rel_res"]) <= 1e-3 * d["true_rel_res"]
+        else:
+            assert info_m["true_rel_res"] <= 1e-8, info_m
         xn = fem.normalise_pressure(N, host(x))
         worst = _per_field(xn[dofs], np.array(d["solution"]), dofs, gs, d["solution_field_max"])
-        note(f"[C5 golden] after {m} steps: per-field max error {['%.2e' % e for e in worst]}")
-        assert max(worst) <= 1e-10, worst
+        note(f"[C5 golden] after {m} steps: per-field max error {['%.2e' % e for e in worst]}, "
+             f"true rel res {info_m['true_rel_res']:.2e}")
+        assert max(worst) <= (1e-10 if precision == "fp64" else 1e-8), worst
 
 
 def test_c5_gradients_match_central_differences_at_256():

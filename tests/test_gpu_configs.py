@@ -38,7 +38,11 @@ the autograd gradients with respect to the log-viscosity and the force
 against central differences of the GPU solve on 20 seeded directions
 (seed 8), 1e-6 relative (solves at rtol 1e-10: with this viscosity field
 the adjoint system's FP64 rounding floor at 256 x 256 is a relative
-residual of about 1.5e-11, so 1e-12 is out of reach).
+residual of about 1.5e-11, so 1e-12 is out of reach); and the same
+gradients against the oracle's adjoint gradients
+(tests/golden/c5_gradient_oracle_256.json, written by
+tests/golden/make_c5_gradient_oracle.py): loss to 1e-8 relative, each
+gradient within 1e-6 of its largest magnitude at sampled entries.
 """
 
 import numpy as np
@@ -386,3 +390,46 @@ def test_c5_gradients_match_central_differences_at_256():
         worst_t = max(worst_t, abs(fdiff - an) / abs(an))
         assert abs(fdiff - an) <= 1e-6 * abs(an), ("log-viscosity", i, fdiff, an)
     note(f"[C5] worst relative FD mismatch: force {worst_f:.2e}, log-viscosity {worst_t:.2e}")
+
+
+def test_c5_gradients_match_oracle_golden():
+    """The autograd gradients at 256 x 256 (the C5 workload and loss of the
+    central-difference test above) against the oracle's adjoint gradients
+    (tests/golden/c5_gradient_oracle_256.json, written by
+    tests/golden/make_c5_gradient_oracle.py from the oracle's forward and
+    adjoint multigrid-FGMRES solves to rtol 1e-10): the loss to 1e-8
+    relative, and each gradient at its sampled entries (nodes and elements on
+    and next to the boundary, on tile seams and at random) within 1e-6 of its
+    largest magnitude."""
+    import json
+    import os
+    N, levels = 256, 6
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "c5_gradient_oracle_256.json")
+    with open(path) as fh:
+        d = json.load(fh)
+    assert d["N"] == N and d["levels"] == levels
+    note(f"[C5 gradient golden] N={N} levels={levels}")
+    theta = log_viscosity_field(N, 7)
+    nu = np.exp(theta)
+    f = gaussian_random_field(N, 5, length=0.1).ravel()
+    n = grid_sizes(N).n
+    xt = np.zeros(n)
+    xt[:2 * (2 * N + 1) ** 2] = 0.01 * gaussian_random_field(N, 6, length=0.1).ravel()
+    with vk.VkmgSolver(N, levels, nu_elem=nu) as s:
+        fd = dev(f).requires_grad_(True)
+        nud = dev(nu).requires_grad_(True)
+        x = stokes_solve(fd, s, nu=nud, rtol=1e-10)
+        loss = 0.5 * torch.sum((x - dev(xt)) ** 2)
+        loss.backward()
+        g_f, g_nu = host(fd.grad), host(nud.grad)
+    lv = float(loss.detach())
+    e_loss = abs(lv - d["loss"]) / abs(d["loss"])
+    fi, ei = np.array(d["force_entries"]), np.array(d["elements"])
+    e_f = float(np.abs(g_f[fi] - np.array(d["force_gradient"])).max() / d["force_gradient_max"])
+    e_nu = float(np.abs(g_nu[ei] - np.array(d["viscosity_gradient"])).max()
+                 / d["viscosity_gradient_max"])
+    note(f"[C5 gradient golden] loss {lv:.6e} vs {d['loss']:.6e} ({e_loss:.1e}); force gradient "
+         f"{e_f:.2e} at {len(fi)} entries, viscosity gradient {e_nu:.2e} at {len(ei)} elements")
+    assert e_loss <= 1e-8
+    assert e_f <= 1e-6 and e_nu <= 1e-6, (e_f, e_nu)

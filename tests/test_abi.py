@@ -31,6 +31,21 @@ def test_library_exports_every_declared_symbol():
     assert sorted(decl) == sorted(vk.EXPORTED)
 
 
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built HIP library nothing falls back to another path:
+    loading it, and constructing a solver, raise."""
+    from paper_2401_06277_amd import _vkmg
+
+    real_exists = os.path.exists
+    monkeypatch.setattr(_vkmg, "_lib", None)
+    monkeypatch.setattr(os.path, "exists",
+                        lambda p: False if str(p).endswith("libvkmg.so") else real_exists(p))
+    with pytest.raises(RuntimeError, match="not built"):
+        _vkmg.load_library()
+    with pytest.raises(RuntimeError, match="not built"):
+        vk.VkmgSolver(16, 3)
+
 def test_default_options_and_status_strings():
     lib = vk.load_library()
     o = lib.vkmg_default_options()

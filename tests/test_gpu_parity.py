@@ -276,6 +276,34 @@ def test_fgmres_iterations_and_solution(N, levels, name):
     assert rel2(xa, xo) <= 1e-10
 
 
+
+@pytest.mark.parametrize("N,levels", [(24, 3), (32, 4)])
+def test_fgmres_long_restart_matches_oracle(N, levels):
+    """The classical CGS2 path (restart lengths above 32, host rotations) at
+    equal iteration counts, on larger meshes than the test below: FGMRES(40)
+    against the oracle's FGMRES(40), iteration count within one at rtol 1e-10
+    and, after exactly the oracle's count, the solution within 1e-10."""
+    note(f"fgmres restart 40 N={N} levels={levels}")
+    s = solver(N, levels)
+    H = hierarchy(N, levels)
+    A, b, xl, _ = _manufactured_system(N, "trig")
+    ro = fgmres.fgmres(A, b, xl, H.vcycle, rtol=1e-10, restart=40, max_iters=500)
+    x = dev(xl)
+    info = s.fgmres_solve(dev(b), x, rtol=1e-10, restart=40, max_iters=500)
+    assert info["status_name"] == "VKMG_OK"
+    assert abs(info["iterations"] - ro.iterations) <= 1
+    assert info["true_rel_res"] <= 1e-10
+    k = ro.iterations
+    x = dev(xl)
+    info_k = s.fgmres_solve(dev(b), x, rtol=0.0, restart=40, max_iters=k)
+    assert info_k["iterations"] == k
+    ok = fgmres.fgmres(A, b, xl, H.vcycle, rtol=0.0, restart=40, fixed_iters=k)
+    xa = fem.normalise_pressure(N, host(x))
+    xo = fem.normalise_pressure(N, ok.x)
+    err = rel2(xa, xo)
+    note(f"  {k} iterations, solution difference {err:.2e}")
+    assert err <= 1e-10
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_fgmres_graph_replays_match_direct_launches(precision):
     """Each Arnoldi step replayed as a captured graph gives bitwise the same

@@ -2660,7 +2660,25 @@ int elementwise_blocks(int64_t n) {
 
 // ---------------------------------------------------------------------------
 // Launchers
+//
+// The build compiles this file twice, with VKMG_KERNEL_UNIT = 64 (the FP64
+// launchers and everything not tied to a precision; machine scheduling that
+// keeps memory clauses together, under which the residual kernel does not
+// spill) and with VKMG_KERNEL_UNIT = 32 (the FP32 launchers; the compiler's
+// default scheduling, faster for them).  Without the macro one unit holds
+// everything.
 // ---------------------------------------------------------------------------
+
+#if !defined(VKMG_KERNEL_UNIT) || VKMG_KERNEL_UNIT == 64
+#define VKMG_UNIT64 1
+#else
+#define VKMG_UNIT64 0
+#endif
+#if !defined(VKMG_KERNEL_UNIT) || VKMG_KERNEL_UNIT == 32
+#define VKMG_UNIT32 1
+#else
+#define VKMG_UNIT32 0
+#endif
 
 template <typename Tx, typename T>
 void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hipStream_t s,
@@ -2678,9 +2696,12 @@ void launch_residual(const Geom& g, const T* b, const Tx* x, T* r, int mode, hip
         residual_kernel<1, Tx, T><<<grid, RNT, 0, s>>>(g, b, x, r);
     }
 }
+#if VKMG_UNIT64
 template void launch_residual<double, double>(const Geom&, const double*, const double*, double*,
                                               int, hipStream_t, int, const double*);
+#endif
 
+#if VKMG_UNIT32
 void launch_apply_widen(const Geom& g, const float* x, double* y, double* x64, hipStream_t s,
                         const double* nue, int nb) {
     const int tiles = (g.N + 1 + RT - 1) / RT;
@@ -2692,6 +2713,7 @@ void launch_apply_widen(const Geom& g, const float* x, double* y, double* x64, h
         residual_kernel<1, float, double, false, false, true><<<grid, RNT, 0, s>>>(
             g, nullptr, x, y, nullptr, Geom{}, nullptr, x64);
 }
+#endif
 
 template <typename T>
 void launch_residual_prolong(const Geom& g, const Geom& gc, const T* b, const T* x, const T* ec,
@@ -2703,20 +2725,26 @@ void launch_residual_prolong(const Geom& g, const Geom& gc, const T* b, const T*
     else
         residual_kernel<0, T, T, false, true><<<grid, RNT, 0, s>>>(g, b, x, r, nullptr, gc, ec, x2);
 }
+#if VKMG_UNIT64
 template void launch_residual_prolong<double>(const Geom&, const Geom&, const double*,
                                               const double*, const double*, double*, double*,
                                               hipStream_t, int, const double*);
+#endif
+#if VKMG_UNIT32
 template void launch_residual_prolong<float>(const Geom&, const Geom&, const float*, const float*,
                                              const float*, float*, float*, hipStream_t, int,
                                              const float*);
 template void launch_residual<float, float>(const Geom&, const float*, const float*, float*, int,
                                             hipStream_t, int, const float*);
+#endif
 
+#if VKMG_UNIT64
 void launch_rhs(const Geom& g, const double* f, const double* gd, double* b, hipStream_t s,
                 int nb) {
     const dim3 grid((g.N + 1 + 15) / 16, (g.N + 1 + 15) / 16, nb);
     rhs_kernel<<<grid, 256, 0, s>>>(g, f, gd, b);
 }
+#endif
 
 template <typename T>
 void launch_bs_relax(const Geom& g, const T* r, const T* xin, T* xout, T* prhs, T* dp, T* vtmp,
@@ -2732,13 +2760,18 @@ void launch_bs_relax(const Geom& g, const T* r, const T* xin, T* xout, T* prhs, 
     }
     bs_grad_kernel<T, 1><<<grid, BNT, 0, s>>>(g, dp, r, xin, xout, T(omega / t), T(omega));
 }
+#if VKMG_UNIT64
 template void launch_bs_relax<double>(const Geom&, const double*, const double*, double*, double*,
                                       double*, double*, double, double, double, int, hipStream_t,
                                       int);
+#endif
+#if VKMG_UNIT32
 template void launch_bs_relax<float>(const Geom&, const float*, const float*, float*, float*,
                                      float*, float*, double, double, double, int, hipStream_t,
                                      int);
+#endif
 
+#if VKMG_UNIT64
 void launch_rhs_adjoint(const Geom& g, const double* lam, double* grad, hipStream_t s, int nb) {
     const dim3 grid((g.s2 + 63) / 64, nb, (g.s2 + 3) / 4);
     rhs_adjoint_kernel<<<grid, 256, 0, s>>>(g, lam, grad);
@@ -2757,6 +2790,7 @@ void launch_pressure_mean_zero(const Geom& g, double* x, double* part, double* s
     reduce_partials_kernel<<<dim3(1, nb), 256, 0, s>>>(part, kBlocks, sums, so);
     pressure_shift_kernel<<<dim3(kBlocks, nb), 256, 0, s>>>(g, x, sums, so);
 }
+#endif
 
 template <typename T>
 void launch_vanka_simple(const Geom& g, const T* r, const T* xin, T* xout, const T* tables,
@@ -2767,12 +2801,18 @@ void launch_vanka_simple(const Geom& g, const T* r, const T* xin, T* xout, const
     const dim3 grid(8 * ((ntile + 7) / 8), nb);
     vanka_sweep_kernel<T, true><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf, T(0), T(0));
 }
+#if VKMG_UNIT64
 template void launch_vanka_simple<double>(const Geom&, const double*, const double*, double*,
                                           const double*, double*, hipStream_t, int);
+#endif
+#if VKMG_UNIT32
 template void launch_vanka_simple<float>(const Geom&, const float*, const float*, float*,
                                          const float*, float*, hipStream_t, int);
+#endif
 
+#if VKMG_UNIT64
 int64_t vanka_boundary_scratch(int N) { return int64_t(n_boundary_patches(N)) * 64; }
+#endif
 
 template <typename T>
 void launch_vanka_boundary(const Geom& g, const T* r, const T* table, T* dbuf, hipStream_t s,
@@ -2789,10 +2829,14 @@ void launch_vanka_boundary(const Geom& g, const T* r, const T* table, T* dbuf, h
     else
         vanka_boundary_kernel<T, 1><<<bgrid, 256, 0, s>>>(g, r, table, dbuf);
 }
+#if VKMG_UNIT64
 template void launch_vanka_boundary<double>(const Geom&, const double*, const double*, double*,
                                             hipStream_t, int, int);
+#endif
+#if VKMG_UNIT32
 template void launch_vanka_boundary<float>(const Geom&, const float*, const float*, float*,
                                            hipStream_t, int, int);
+#endif
 
 template <typename T>
 void launch_vanka_tiles(const Geom& g, const T* r, const T* xin, T* xout, const T* mtab,
@@ -2810,12 +2854,16 @@ void launch_vanka_tiles(const Geom& g, const T* r, const T* xin, T* xout, const 
         vanka_sweep_kernel<T><<<grid, VNT, 0, s>>>(g, r, xin, xout, dbuf, T(omega / g.nu),
                                                    T(g.nu / g.h));
 }
+#if VKMG_UNIT64
 template void launch_vanka_tiles<double>(const Geom&, const double*, const double*, double*,
                                          const double*, const double*, double, bool, hipStream_t,
                                          int, bool);
+#endif
+#if VKMG_UNIT32
 template void launch_vanka_tiles<float>(const Geom&, const float*, const float*, float*,
                                         const float*, const float*, double, bool, hipStream_t,
                                         int, bool);
+#endif
 
 template <typename T>
 void launch_vanka_fused(const Geom& g, const T* b, const T* xin, T* xout, const T* table,
@@ -2829,11 +2877,17 @@ void launch_vanka_fused(const Geom& g, const T* b, const T* xin, T* xout, const 
         vanka_fused_kernel<T, false><<<grid, FNT, 0, s>>>(g, b, xin, xout, table,
                                                           T(omega / g.nu), T(g.nu / g.h));
 }
+#if VKMG_UNIT64
 template void launch_vanka_fused<double>(const Geom&, const double*, const double*, double*,
                                          const double*, double, hipStream_t, int);
+#endif
+#if VKMG_UNIT32
 template void launch_vanka_fused<float>(const Geom&, const float*, const float*, float*,
                                         const float*, double, hipStream_t, int);
+#endif
+#if VKMG_UNIT64
 int vanka_fused_min_n() { return kFusedMinN; }
+#endif
 
 template <typename T>
 void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const T* table,
@@ -2842,57 +2896,80 @@ void launch_vanka_update(const Geom& g, const T* r, const T* xin, T* xout, const
     launch_vanka_boundary<T>(g, r, table, dbuf, s, nrhs, per_wave);
     launch_vanka_tiles<T>(g, r, xin, xout, mtab, dbuf, omega, mfma, s, nrhs, park);
 }
+#if VKMG_UNIT64
 template void launch_vanka_update<double>(const Geom&, const double*, const double*, double*,
                                           const double*, const double*, double*, double, bool,
                                           hipStream_t, int, bool, int);
+#endif
+#if VKMG_UNIT32
 template void launch_vanka_update<float>(const Geom&, const float*, const float*, float*,
                                          const float*, const float*, float*, double, bool,
                                          hipStream_t, int, bool, int);
+#endif
 
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, hipStream_t s, int nb) {
     const dim3 grid((gc.s2 + 63) / 64, (gc.N + 3) / 4, nb);
     restrict_kernel<T><<<grid, 256, 0, s>>>(gf, gc, rf, bc);
 }
+#if VKMG_UNIT64
 template void launch_restrict<double>(const Geom&, const Geom&, const double*, double*, hipStream_t,
                                       int);
+#endif
+#if VKMG_UNIT32
 template void launch_restrict<float>(const Geom&, const Geom&, const float*, float*, hipStream_t,
                                      int);
+#endif
 
 template <typename T>
 void launch_prolong_add(const Geom& gf, const Geom& gc, const T* ec, T* xf, hipStream_t s, int nb) {
     const dim3 grid((gf.s2 + 63) / 64, (gc.N + 3) / 4, nb);
     prolong_kernel<T><<<grid, 256, 0, s>>>(gf, gc, ec, xf);
 }
+#if VKMG_UNIT64
 template void launch_prolong_add<double>(const Geom&, const Geom&, const double*, double*,
                                          hipStream_t, int);
+#endif
+#if VKMG_UNIT32
 template void launch_prolong_add<float>(const Geom&, const Geom&, const float*, float*,
                                         hipStream_t, int);
+#endif
 
 template <typename T>
 void launch_coarse_gemv(int64_t n, const double* C, const T* r, T* e, hipStream_t s, int nb) {
     const dim3 grid(int((n + 3) / 4), nb);
     coarse_gemv_kernel<T><<<grid, 256, 0, s>>>(n, C, r, e);
 }
+#if VKMG_UNIT64
 template void launch_coarse_gemv<double>(int64_t, const double*, const double*, double*,
                                          hipStream_t, int);
+#endif
+#if VKMG_UNIT32
 template void launch_coarse_gemv<float>(int64_t, const double*, const float*, float*, hipStream_t,
                                         int);
+#endif
 
 template <typename T>
 void launch_fill_zero(T* x, int64_t n, hipStream_t s) {
     fill_zero_kernel<T><<<elementwise_blocks(n), 256, 0, s>>>(x, n);
 }
+#if VKMG_UNIT64
 template void launch_fill_zero<double>(double*, int64_t, hipStream_t);
+#endif
+#if VKMG_UNIT32
 template void launch_fill_zero<float>(float*, int64_t, hipStream_t);
+#endif
 
 template <typename Ti, typename To>
 void launch_cast(const Ti* in, To* out, int64_t n, hipStream_t s) {
     cast_kernel<Ti, To><<<elementwise_blocks(n), 256, 0, s>>>(in, out, n);
 }
+#if VKMG_UNIT32
 template void launch_cast<double, float>(const double*, float*, int64_t, hipStream_t);
 template void launch_cast<float, double>(const float*, double*, int64_t, hipStream_t);
+#endif
 
+#if VKMG_UNIT64
 void launch_lift(const Geom& g, const double* b, double* x, hipStream_t s, int nb) {
     const int64_t total = g.n * nb;
     lift_kernel<<<elementwise_blocks(total), 256, 0, s>>>(g, b, x, total);
@@ -2901,6 +2978,7 @@ void launch_lift(const Geom& g, const double* b, double* x, hipStream_t s, int n
 void launch_scale(const double* in, double alpha, double* out, int64_t n, hipStream_t s) {
     scale_kernel<<<elementwise_blocks(n), 256, 0, s>>>(in, alpha, out, n);
 }
+#endif
 
 #define VKMG_KDISPATCH(k, KERNEL, ...)                                     \
     do {                                                                   \
@@ -2914,6 +2992,7 @@ void launch_scale(const double* in, double alpha, double* out, int64_t n, hipStr
 // bases are processed in chunks of 32 vectors (single right-hand side).
 constexpr int kChunk = 32;
 
+#if VKMG_UNIT64
 void launch_givens_init(double* area, int64_t stride, const double* init, double* stat, int nsys,
                         hipStream_t s) {
     givens_init_kernel<<<(nsys + 63) / 64, 64, 0, s>>>(area, stride, init, stat, nsys);
@@ -2922,10 +3001,12 @@ void launch_givens_init(double* area, int64_t stride, const double* init, double
 void launch_givens_solve(double* area, int64_t stride, int kmax, int nsys, hipStream_t s) {
     givens_solve_kernel<<<nsys, 64, 0, s>>>(area, stride, kmax);
 }
+#endif
 
 // Every batch entry is reduced over the same kDotBlocks partial sums as a
 // single right-hand side, so batched dot products (and with them the whole
 // batched solve) are bitwise those of single solves.
+#if VKMG_UNIT64
 int dot_blocks(int) { return kDotBlocks; }
 
 void launch_scale_batched(const double* in, int64_t sin, const double* alpha, int64_t sa,
@@ -2994,5 +3075,6 @@ void launch_axpy_multi(const double* Z, int64_t ldz, int k, const double* y, dou
         VKMG_KDISPATCH(kc, axpy_multi_kernel, Z + c0 * ldz, ldz, kc, y + c0, x, n, sb, sy);
     }
 }
+#endif
 
 }  // namespace vkmg
